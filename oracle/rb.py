@@ -1,0 +1,245 @@
+"""Reduced-basis iteration (RBI) and RB-preconditioned CG (RBCG), oracle side.
+
+TEST INFRASTRUCTURE ONLY.  Follows the paper step by step, in float64:
+
+  * reduced operators A_{N,q} = W^T A_q W, f_{N,r} = W^T f_r          (eq. 12c)
+  * online assembly A_N(mu) = sum_q Theta_q A_{N,q}, f_N likewise      (eq. 12b)
+  * A_N(mu) is SPD and is inverted through its Cholesky factor          (Sec. 2.1)
+  * RBI(A, b, W, m): residual, projection W^T r, reduced solve, update
+    x += W e, post-smoothing, repeated m times (Alg. 2; eqs. 5-8)
+  * RBCG(A, b, W): CG preconditioned by one RBI step from x = 0 (Alg. 3)
+  * MGS(W, x): modified Gram-Schmidt of a snapshot against W (Sec. 2.2)
+
+Readings where the paper is silent (each also listed in the design notes):
+  - stopping test is relative, ||r|| <= rtol ||b|| (eq. relerr of Sec. 5.1); when the
+    recursive CG residual passes, the true residual b - A x is recomputed and must
+    pass too, else r is replaced by it and CG restarts with p = y
+  - the RBI preconditioner skips its own exit test (the outer test just failed)
+  - the reduced matrix is factored once per mu; each application is two triangular
+    solves (same result as re-inverting each iteration)
+  - beta is the ratio of step 10 of Alg. 3; "flexible" uses y_{k+1}^T (r_{k+1} - r_k)
+  - iteration count = number of products A p
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from .smoother import Smoother, RBGS, NONE
+
+
+# --- offline / online reduced operators (eqs. 12b, 12c) ------------------------
+def reduced_operators(A_q, f_r, W):
+    """A_{N,q} = W^T A_q W (Q x n x n) and f_{N,r} = W^T f_r (R x n)."""
+    AN = np.stack([W.T @ (Aq @ W) for Aq in A_q])
+    fN = np.stack([W.T @ f for f in f_r])
+    return AN, fN
+
+
+def assemble_reduced(AN_q, theta, fN_r=None, phi=None):
+    AN = np.tensordot(np.asarray(theta, dtype=np.float64), AN_q, axes=1)
+    if fN_r is None:
+        return AN
+    phi = np.ones(fN_r.shape[0]) if phi is None else np.asarray(phi, dtype=np.float64)
+    return AN, phi @ fN_r
+
+
+class NotSPD(Exception):
+    pass
+
+
+def cholesky(AN):
+    """Lower-triangular L with L L^T = A_N (Sec. 2.1)."""
+    try:
+        return np.linalg.cholesky(AN)
+    except np.linalg.LinAlgError as exc:
+        raise NotSPD(str(exc)) from exc
+
+
+def chol_solve(L, t):
+    """e = A_N^{-1} t = L^-T L^-1 t."""
+    u = sla.solve_triangular(L, t, lower=True)
+    return sla.solve_triangular(L.T, u, lower=False)
+
+
+# --- RBI (Alg. 2) -------------------------------------------------------------
+class RBPreconditioner:
+    """One RBI iteration from x = 0 applied to a right-hand side r (Alg. 3, steps 2/9).
+
+    With x = 0 the residual of step 2 of Alg. 2 is r itself (no product with A).
+    W may have zero columns (W_0 = empty): then the coarse correction is 0 and only
+    the smoother acts, as in the first snapshot solve of the adaptive greedy.
+    """
+
+    def __init__(self, A, W, L, smoother: Smoother):
+        self.A, self.W, self.L, self.S = A, W, L, smoother
+
+    def coarse(self, r):
+        """x = W e with A_N e = W^T r (Alg. 2 steps 4-6)."""
+        if self.W.shape[1] == 0:
+            return np.zeros_like(r)
+        t = self.W.T @ r
+        e = chol_solve(self.L, t)
+        return self.W @ e
+
+    def __call__(self, r):
+        return self.S(r, self.coarse(r))
+
+
+def rbi(A, b, W, L, smoother: Smoother, m, rtol=0.0):
+    """y = RBI(A, b, W, m) (Alg. 2).  Returns (x, iterations run, residual history)."""
+    x = np.zeros_like(b)
+    nb = np.linalg.norm(b)
+    hist = []
+    k = 0
+    for k in range(1, m + 1):
+        r = b - A @ x                              # step 2
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= rtol:                       # step 3 (relative reading)
+            k -= 1
+            break
+        if W.shape[1] > 0:
+            t = W.T @ r                            # step 4
+            e = chol_solve(L, t)                   # step 5
+            x = x + W @ e                          # step 6
+        x = smoother(b, x)                         # step 7
+    return x, k, hist
+
+
+# --- RBCG (Alg. 3) ------------------------------------------------------------
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    rel_res_true: float
+    rel_res_recursive: float
+    status: str = "ok"
+    history: list = field(default_factory=list)
+    iterates: list = field(default_factory=list)
+
+
+def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None,
+         keep_iterates=False, keep_vectors=False):
+    """x = RBCG(A, b, W) (Alg. 3) with the stopping rule described in the module doc.
+
+    precond: callable r -> y (one RBI step, or identity for plain CG).
+    fixed_iters: run exactly this many products A p (no stopping test) for iterate parity.
+    keep_vectors: record every r_k and p_k (for orthogonality checks).
+    """
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)                    # step 0
+    r = b.copy()                            # step 1 (x0 = 0, no product needed)
+    y = precond(r)                          # step 2
+    p = y.copy()                            # step 3
+    rho = r @ y
+    it = 0
+    hist = [1.0]
+    iterates = []
+    status = "ok"
+    rel_rec = 1.0
+    vecs = {"r": [r.copy()], "p": [p.copy()]} if keep_vectors else None
+    while True:                             # step 4
+        if fixed_iters is not None and it >= fixed_iters:
+            break
+        if it >= maxit:
+            status = "noconv"
+            break
+        q = A @ p
+        pq = p @ q
+        if not pq > 0.0 or not rho > 0.0:
+            status = "breakdown"
+            break
+        alpha = rho / pq                    # step 5
+        x = x + alpha * p                   # step 6
+        r_old = r
+        r = r - alpha * q                   # step 7
+        it += 1
+        rel_rec = np.linalg.norm(r) / nb
+        hist.append(rel_rec)
+        if keep_iterates:
+            iterates.append(x.copy())
+        if fixed_iters is None and rel_rec <= rtol:   # step 8
+            rt = b - A @ x
+            if np.linalg.norm(rt) / nb <= rtol:
+                break
+            r = rt                          # residual replacement and restart
+            y = precond(r)
+            p = y.copy()
+            rho = r @ y
+            continue
+        y = precond(r)                      # step 9
+        rho_new = y @ r
+        if flexible:
+            beta = (y @ (r - r_old)) / rho
+        else:
+            beta = rho_new / rho            # step 10
+        p = y + beta * p                    # step 11
+        rho = rho_new
+        if keep_vectors:
+            vecs["r"].append(r.copy())
+            vecs["p"].append(p.copy())
+    rel_true = np.linalg.norm(b - A @ x) / nb
+    converged = status == "ok" and rel_true <= rtol
+    out = SolveResult(x, it, converged, rel_true, rel_rec, status, hist, iterates)
+    out.vectors = vecs
+    return out
+
+
+# --- modified Gram-Schmidt (Sec. 2.2, step 4 of Alg. 1 / Alg. 4) ---------------
+class Degenerate(Exception):
+    pass
+
+
+def mgs(W, x, reorth_ratio=0.5, degenerate_tol=1e-12):
+    """Orthonormalise x against the orthonormal columns of W.
+
+    One modified Gram-Schmidt pass; a second pass if the norm dropped below
+    reorth_ratio of its value before the pass; Degenerate if the remainder is below
+    degenerate_tol * ||x||.  Returns the new unit column.
+    """
+    w = np.array(x, dtype=np.float64, copy=True)
+    nx = np.linalg.norm(w)
+    if nx == 0.0:
+        raise Degenerate("zero snapshot")
+    for _ in range(2):
+        before = np.linalg.norm(w)
+        for j in range(W.shape[1]):
+            w = w - (W[:, j] @ w) * W[:, j]
+        after = np.linalg.norm(w)
+        if after >= reorth_ratio * before:
+            break
+    if after < degenerate_tol * nx:
+        raise Degenerate("snapshot lies in span(W)")
+    return w / after
+
+
+def make_preconditioner(op, theta, W, AN_q=None, smoother_kind=RBGS):
+    """Build (A(theta), RBI preconditioner) for one parameter vector."""
+    A = op.assemble(theta)
+    S = Smoother(A, op.colors(), smoother_kind)
+    if W.shape[1] == 0:
+        return A, RBPreconditioner(A, W, None, S)
+    if AN_q is None:
+        AN_q, _ = reduced_operators(op.A_q, [op.rhs()], W)
+    L = cholesky(assemble_reduced(AN_q, theta))
+    return A, RBPreconditioner(A, W, L, S)
+
+
+def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, **kw):
+    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
+    return rbcg(A, op.rhs(), M, **kw)
+
+
+def solve_cg(op, theta, **kw):
+    """Plain CG (Hestenes-Stiefel): the identity preconditioner."""
+    A = op.assemble(theta)
+    return rbcg(A, op.rhs(), lambda r: r.copy(), **kw)
+
+
+def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS):
+    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
+    x, k, hist = rbi(A, op.rhs(), W, M.L, M.S, m, rtol)
+    return x, k, hist

@@ -1,0 +1,123 @@
+"""Pins of the oracle's greedy (Alg. 1 / Alg. 4) and MLP surrogate."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import greedy, mlp
+from oracle.operator import BlockDiffusion
+
+
+def _brute_force_picks(op, thetas, n_max, kind):
+    """Alg. 1 with exact dense snapshot solves, a QR basis and dense reduced solves."""
+    f = op.rhs()
+    dense = [op.assemble(t).toarray() for t in thetas]
+    sols = [np.linalg.solve(A, f) for A in dense]
+    picks = [0]
+    while True:
+        Wq, _ = np.linalg.qr(np.column_stack([sols[i] for i in picks]))
+        vals = []
+        for A in dense:
+            a = np.linalg.solve(Wq.T @ A @ Wq, Wq.T @ f)
+            if kind == "l1":
+                vals.append(np.abs(a).sum())
+            else:
+                vals.append(np.linalg.norm(f - A @ (Wq @ a)) / np.linalg.norm(f))
+        if len(picks) == n_max:
+            return picks, vals
+        v = np.array(vals)
+        v[picks] = -np.inf
+        picks.append(int(np.argmax(v)))
+
+
+@pytest.mark.parametrize("kind", ["residual", "l1"])
+def test_greedy_picks_match_brute_force(kind):
+    op = BlockDiffusion((7, 7), (2, 2))
+    rng = np.random.default_rng(12)
+    thetas = 10 ** rng.uniform(-1, 1, (24, op.Q))
+    g = greedy.adaptive_greedy(op, thetas, 5, indicator=kind, snapshot_rtol=1e-12)
+    bf, vals = _brute_force_picks(op, thetas, 5, kind)
+    assert g.picks == bf
+    assert np.abs(g.W.T @ g.W - np.eye(5)).max() <= 1e-13
+
+
+def test_residual_indicator_vanishes_on_samples():
+    op = BlockDiffusion((7, 7), (2, 2))
+    rng = np.random.default_rng(13)
+    thetas = 10 ** rng.uniform(-1, 1, (16, op.Q))
+    g = greedy.adaptive_greedy(op, thetas, 4, keep_indicators=True, snapshot_rtol=1e-12)
+    last = g.indicators[-1]
+    for p in g.picks:
+        assert last[p] <= 1e-9
+
+
+def test_masked_argmax_ties_and_exclusion():
+    assert greedy.masked_argmax([1.0, 3.0, 3.0, 2.0], {0}) == 1
+    assert greedy.masked_argmax([1.0, 3.0, 3.0, 2.0], {1}) == 2
+    with pytest.raises(FloatingPointError):
+        greedy.masked_argmax([1.0, float("nan")], set())
+
+
+# --- MLP ----------------------------------------------------------------------
+def test_splitmix64_published_values():
+    # SplitMix64 with state 0: the first outputs of the reference generator
+    # (state += golden gamma; mix) are 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4.
+    assert mlp.splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    assert mlp.splitmix64(0, 1) == 0x6E789E6AA1B965F4
+
+
+def test_gelu_reference_values():
+    # GELU(x) = x * Phi(x): Phi(1) = 0.8413447460685429, Phi(-1) = 0.15865525393145707
+    g = mlp.gelu(np.array([1.0, -1.0, 0.0]))
+    assert g[0] == pytest.approx(0.8413447460685429, rel=1e-15)
+    assert g[1] == pytest.approx(-0.15865525393145707, rel=1e-14)
+    assert g[2] == 0.0
+
+
+def test_mlp_gradients_finite_differences():
+    rng = np.random.default_rng(20)
+    P, H = 8, 16
+    params = mlp.init_params(P, H, seed=7)
+    for k in ("b1", "b2", "b3"):
+        params[k] = rng.standard_normal(params[k].shape) * 0.1
+    X = rng.uniform(-1, 1, (12, P))
+    y = rng.standard_normal(12)
+    loss, g = mlp.loss_and_grads(params, X, y)
+    h = 1e-6
+    for name in mlp.PARAM_NAMES:
+        flat = params[name].ravel()
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.loss_and_grads(params, X, y)
+            flat[idx] = old - h
+            lm, _ = mlp.loss_and_grads(params, X, y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert g[name].ravel()[idx] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_glorot_range_and_adam_reduces_loss():
+    P, H = 8, 32
+    params = mlp.init_params(P, H, seed=3)
+    a1 = math.sqrt(6.0 / (P + H))
+    assert np.abs(params["W1"]).max() <= a1 and np.abs(params["W1"]).max() > 0.8 * a1
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (64, P))
+    y = np.sin(X[:, 0]) + X[:, 1] ** 2
+    opt = mlp.Adam(params, lr=1e-2)
+    l0, _ = mlp.loss_and_grads(params, X, y)
+    for _ in range(200):
+        _, g = mlp.loss_and_grads(params, X, y)
+        opt.step(params, g)
+    l1, _ = mlp.loss_and_grads(params, X, y)
+    assert l1 < 0.05 * l0
+
+
+def test_adam_first_step_is_signed_lr():
+    """With bias correction the first Adam step moves each weight by lr * sign(g)."""
+    params = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    opt = mlp.Adam(params, lr=0.1, eps=0.0)
+    opt.step(params, g)
+    assert np.allclose(params["w"], [0.9, -1.9, 2.9], rtol=0, atol=1e-15)

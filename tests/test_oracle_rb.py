@@ -1,0 +1,233 @@
+"""Pins of the oracle's smoother, RBI, RBCG, Cholesky and MGS against facts fixed by the
+paper (Lemmas 1-3 of Sec. 3.2, Galerkin projection eq. 2b) and by linear algebra."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import rb
+from oracle.operator import BlockDiffusion
+from oracle.smoother import Smoother, RBGS, RBGS_SYM, JACOBI, NONE
+from workloads import random_orthonormal
+
+
+def _problem(dims=(7, 7), blocks=(2, 2), seed=3):
+    op = BlockDiffusion(dims, blocks)
+    rng = np.random.default_rng(seed)
+    theta = 10 ** rng.uniform(-1, 1, op.Q)
+    return op, theta, op.assemble(theta)
+
+
+def _snapshot_basis(op, n, seed=5):
+    """Orthonormal basis of exact solutions at n random parameters (dense solves + QR)."""
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([np.linalg.solve(op.assemble(10 ** rng.uniform(-1, 1, op.Q)).toarray(),
+                                         op.rhs()) for _ in range(n)])
+    q, _ = np.linalg.qr(X)
+    return q
+
+
+# --- smoother -----------------------------------------------------------------
+@pytest.mark.parametrize("dims,blocks", [((7, 7), (2, 2)), ((7, 5, 3), (2, 3, 2))])
+def test_rbgs_is_forward_substitution_in_red_first_order(dims, blocks):
+    op, theta, A = _problem(dims, blocks)
+    rng = np.random.default_rng(0)
+    b, y0 = rng.standard_normal(op.N), rng.standard_normal(op.N)
+    col = op.colors()
+    perm = np.concatenate([np.flatnonzero(col == 0), np.flatnonzero(col == 1)])
+    Ad = A.toarray()[np.ix_(perm, perm)]
+    # forward: y = y0 + (D + L)^-1 (b - A y0) in the permuted order
+    upd = sla.solve_triangular(np.tril(Ad), (b - A @ y0)[perm], lower=True)
+    expect = y0.copy()
+    expect[perm] += upd
+    got = Smoother(A, col, RBGS)(b, y0)
+    assert np.abs(got - expect).max() <= 1e-13 * np.abs(expect).max()
+    # symmetric: forward then backward substitution
+    y1 = expect
+    upd2 = sla.solve_triangular(np.triu(Ad), (b - A @ y1)[perm], lower=False)
+    expect2 = y1.copy()
+    expect2[perm] += upd2
+    got2 = Smoother(A, col, RBGS_SYM)(b, y0)
+    assert np.abs(got2 - expect2).max() <= 1e-13 * np.abs(expect2).max()
+
+
+def test_rbgs_ignores_red_part_of_start():
+    op, theta, A = _problem()
+    rng = np.random.default_rng(1)
+    b, y0 = rng.standard_normal(op.N), rng.standard_normal(op.N)
+    col = op.colors()
+    y1 = y0.copy()
+    y1[col == 0] = rng.standard_normal((col == 0).sum())
+    S = Smoother(A, col, RBGS)
+    assert np.array_equal(S(b, y0), S(b, y1))
+
+
+@pytest.mark.parametrize("kind", [RBGS, RBGS_SYM, JACOBI, NONE])
+def test_smoothers_fix_the_solution(kind):
+    op, theta, A = _problem()
+    b = op.rhs()
+    xs = np.linalg.solve(A.toarray(), b)
+    y = Smoother(A, op.colors(), kind)(b, xs)
+    assert np.linalg.norm(y - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_gs_sweeps_converge_to_solution():
+    op, theta, A = _problem()
+    b = op.rhs()
+    xs = np.linalg.solve(A.toarray(), b)
+    S = Smoother(A, op.colors(), RBGS)
+    y = np.zeros(op.N)
+    for _ in range(400):
+        y = S(b, y)
+    assert np.linalg.norm(y - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+# --- reduced operators / Cholesky ---------------------------------------------
+def test_affine_reduced_assembly_equals_projection():
+    op, theta, A = _problem((7, 5, 3), (2, 3, 2))
+    W = random_orthonormal(7, op.N, 6)
+    AN_q, fN = rb.reduced_operators(op.A_q, [op.rhs()], W)
+    AN, f = rb.assemble_reduced(AN_q, theta, fN)
+    assert np.abs(AN - W.T @ (A @ W)).max() <= 1e-12 * np.abs(AN).max()
+    assert np.abs(f - W.T @ op.rhs()).max() <= 1e-12 * np.abs(f).max()
+
+
+def test_cholesky_and_solve():
+    rng = np.random.default_rng(2)
+    M = rng.standard_normal((12, 12))
+    S = M @ M.T + 12 * np.eye(12)
+    L = rb.cholesky(S)
+    assert np.allclose(np.triu(L, 1), 0)
+    assert np.abs(L @ L.T - S).max() <= 1e-13 * np.abs(S).max()
+    assert np.abs(L - sla.cholesky(S, lower=True)).max() <= 1e-13 * np.abs(L).max()
+    t = rng.standard_normal(12)
+    assert np.linalg.norm(S @ rb.chol_solve(L, t) - t) <= 1e-12 * np.linalg.norm(t)
+    with pytest.raises(rb.NotSPD):
+        rb.cholesky(-S)
+
+
+# --- RBI: Galerkin step and Lemmas 1-3 (Sec. 3.2) ------------------------------
+def test_first_coarse_correction_is_galerkin():
+    """After step 6 of the first RBI iteration, W^T (f - A x_hat) = 0 (eq. 2b)."""
+    op, theta, A = _problem()
+    W = _snapshot_basis(op, 4)
+    A_, M = rb.make_preconditioner(op, theta, W)
+    f = op.rhs()
+    xhat = M.coarse(f)
+    assert np.linalg.norm(W.T @ (f - A @ xhat)) <= 1e-12 * np.linalg.norm(W.T @ f)
+
+
+def test_lemma1_complete_basis_one_step():
+    op, theta, A = _problem()
+    W = random_orthonormal(11, op.N, op.N)
+    x, k, hist = rb.solve_rbi(op, theta, W, m=5, rtol=1e-12)
+    assert k == 1
+    res = rb.solve_rbcg(op, theta, W, rtol=1e-12)
+    assert res.iters == 1 and res.rel_res_true <= 1e-12
+
+
+def test_lemma1_snapshot_parameter():
+    """For mu in S_N the first RB iterate x_hat equals the snapshot x(mu)."""
+    op = BlockDiffusion((7, 7), (2, 2))
+    rng = np.random.default_rng(4)
+    thetas = 10 ** rng.uniform(-1, 1, (3, op.Q))
+    X = np.column_stack([np.linalg.solve(op.assemble(t).toarray(), op.rhs()) for t in thetas])
+    W, _ = np.linalg.qr(X)
+    for j, t in enumerate(thetas):
+        A, M = rb.make_preconditioner(op, t, W)
+        assert np.linalg.norm(M.coarse(op.rhs()) - X[:, j]) <= 1e-11 * np.linalg.norm(X[:, j])
+
+
+def test_lemma2_stagnation_without_smoother():
+    op, theta, A = _problem()
+    W = _snapshot_basis(op, 3)
+    A_, M = rb.make_preconditioner(op, theta, W, smoother_kind=NONE)
+    f = op.rhs()
+    x1, _, _ = rb.rbi(A, f, W, M.L, M.S, 1)
+    x2, _, _ = rb.rbi(A, f, W, M.L, M.S, 2)
+    xhat = M.coarse(f)
+    assert np.linalg.norm(x1 - xhat) <= 1e-13 * np.linalg.norm(xhat)
+    assert np.linalg.norm(x2 - x1) <= 1e-12 * np.linalg.norm(x1)
+
+
+def test_lemma3_error_approximation():
+    """W e_N of step 5 is the Galerkin approximation of the error A^-1 r."""
+    op, theta, A = _problem()
+    W = _snapshot_basis(op, 4)
+    Ad = A.toarray()
+    xs = np.linalg.solve(Ad, op.rhs())
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(op.N)
+    r = op.rhs() - A @ x
+    A_, M = rb.make_preconditioner(op, theta, W)
+    We = M.coarse(r)
+    expect = W @ np.linalg.solve(W.T @ Ad @ W, W.T @ Ad @ (xs - x))
+    assert np.linalg.norm(We - expect) <= 1e-11 * np.linalg.norm(expect)
+
+
+def test_rbi_converges_to_dense_solution():
+    op, theta, A = _problem()
+    W = _snapshot_basis(op, 3)
+    x, k, hist = rb.solve_rbi(op, theta, W, m=500, rtol=1e-12)
+    xs = np.linalg.solve(A.toarray(), op.rhs())
+    assert hist[-1] <= 1e-12 or np.linalg.norm(op.rhs() - A @ x) <= 1e-12 * np.linalg.norm(op.rhs())
+    assert np.linalg.norm(x - xs) <= np.linalg.cond(A.toarray()) * 1e-12 * np.linalg.norm(xs)
+
+
+# --- CG mechanics -------------------------------------------------------------
+def test_plain_cg_orthogonality_and_finite_termination():
+    op, theta, A = _problem()
+    res = rb.solve_cg(op, theta, fixed_iters=10, keep_vectors=True)
+    R = np.column_stack(res.vectors["r"][:10])
+    P = np.column_stack(res.vectors["p"][:10])
+    G = R.T @ R
+    off = G - np.diag(np.diag(G))
+    assert np.abs(off).max() <= 1e-10 * np.sqrt(np.outer(np.diag(G), np.diag(G))).max()
+    H = P.T @ (A @ P)
+    offh = H - np.diag(np.diag(H))
+    assert np.abs(offh).max() <= 1e-10 * np.abs(np.diag(H)).max()
+    # finite termination: with kappa uniform on a 7x7 grid and f = 1 only the modes with
+    # odd wave numbers (1,3,5,7 per axis) are excited, so A restricted to the Krylov space
+    # has at most 10 distinct eigenvalues (lambda_j + lambda_k, j <= k): CG ends in <= 10 steps
+    full = rb.solve_cg(op, np.full(op.Q, 1.7), rtol=1e-10)
+    assert full.converged and full.iters <= 10
+
+
+def test_rbcg_residual_orthogonal_to_last_direction():
+    """For the non-symmetric RB preconditioner only r_{k+1}^T p_k = 0 holds."""
+    op, theta, A = _problem()
+    W = _snapshot_basis(op, 2)
+    A_, M = rb.make_preconditioner(op, theta, W)
+    res = rb.rbcg(A, op.rhs(), M, fixed_iters=8, keep_vectors=True)
+    r, p = res.vectors["r"], res.vectors["p"]
+    for k in range(len(p) - 1):
+        assert abs(r[k + 1] @ p[k]) <= 1e-10 * np.linalg.norm(r[k + 1]) * np.linalg.norm(p[k])
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 7, 7), (2, 2, 2))])
+def test_rbcg_converged_solution_matches_dense(dims, blocks, flexible):
+    op, theta, A = _problem(dims, blocks)
+    W = _snapshot_basis(op, 5)
+    res = rb.solve_rbcg(op, theta, W, rtol=1e-10, flexible=flexible)
+    assert res.converged and res.rel_res_true <= 1e-10
+    Ad = A.toarray()
+    xs = np.linalg.solve(Ad, op.rhs())
+    bound = np.linalg.cond(Ad) * 1e-10
+    assert np.linalg.norm(res.x - xs) <= bound * np.linalg.norm(xs)
+
+
+# --- MGS ----------------------------------------------------------------------
+def test_mgs_orthonormal_and_span():
+    op = BlockDiffusion((7, 7), (2, 2))
+    rng = np.random.default_rng(9)
+    X = np.column_stack([np.linalg.solve(op.assemble(10 ** rng.uniform(-1, 1, op.Q)).toarray(),
+                                         op.rhs()) for _ in range(8)])
+    W = np.zeros((op.N, 0))
+    for j in range(X.shape[1]):
+        W = np.column_stack([W, rb.mgs(W, X[:, j])])
+    assert np.abs(W.T @ W - np.eye(W.shape[1])).max() <= 1e-13
+    # every snapshot lies in span(W)
+    for j in range(X.shape[1]):
+        assert np.linalg.norm(X[:, j] - W @ (W.T @ X[:, j])) <= 1e-12 * np.linalg.norm(X[:, j])
+    with pytest.raises(rb.Degenerate):
+        rb.mgs(W, X[:, 3])
