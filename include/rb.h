@@ -1,0 +1,238 @@
+/*
+ * rb.h -- C ABI of the MI355X (gfx950) reduced-basis solver library (librb.so).
+ *
+ * Method: Nguyen & Chen, "Reduced-basis method for the iterative solution of
+ * parametrized symmetric positive-definite linear systems".  The library solves
+ * many instances of the parametrized SPD system A(mu) x(mu) = f(mu) (eq. 1) whose
+ * operator and right-hand side are affine in the parameters (eq. 12, Sec. 2.3):
+ *
+ *     A(mu) = sum_{q<Q} Theta_q(mu) A_q,      f(mu) = sum_{r<R} Phi_r(mu) f_r.
+ *
+ * The caller evaluates Theta_q(mu) and Phi_r(mu) on the host and passes them per
+ * query.  Solvers: RB-preconditioned CG (Alg. 3, Sec. 4.1), the stand-alone RB
+ * iteration (Alg. 2, Sec. 3.1) and plain CG.  The reduced basis W comes from the
+ * adaptive greedy (Alg. 4, Sec. 4.2) or from the caller.
+ *
+ * Conventions
+ *  - Every function returns rb_status.  No C++ exception crosses this ABI.
+ *  - On a non-OK return nothing has been written to caller outputs, and
+ *    rb_last_error() returns a message (thread-local, valid until the next call on
+ *    the same thread).
+ *  - Per-query failures (not SPD, no convergence, breakdown) are reported in
+ *    rb_query_stats.status; the call still returns RB_OK and other queries are
+ *    unaffected.
+ *  - Handles are owned by the library and freed with their *_destroy call.
+ *  - Host arrays passed in are borrowed for the duration of the call (copied).
+ *  - Vectors exchanged with the caller use the natural lexicographic ordering of
+ *    the grid (x fastest).  "DEVICE" pointers are HIP device memory owned by the
+ *    caller (e.g. a torch tensor's data_ptr()); all others are host memory.
+ *  - All work is ordered on the context's HIP stream.  Calls that return host
+ *    results (stats, reports) synchronise that stream before returning.
+ *  - One rb_ctx per host thread.  Calls that overlap on one context race.
+ */
+#ifndef RB_H_
+#define RB_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RB_OK = 0,
+  RB_EINVAL = 1,       /* bad argument (null pointer, size, NaN parameter, ...) */
+  RB_ENOMEM = 2,       /* device allocation failed; nothing left allocated */
+  RB_EDEVICE = 3,      /* HIP runtime error */
+  RB_ENOTSPD = 4,      /* reduced matrix A_N(mu) not SPD (Cholesky breakdown) */
+  RB_ENOCONV = 5,      /* maxit reached before the tolerance */
+  RB_EBREAKDOWN = 6,   /* p^T A p <= 0 or y^T r <= 0 in CG */
+  RB_EDEGENERATE = 7,  /* snapshot already in span(W) (Gram-Schmidt) */
+  RB_EUNSUPPORTED = 8, /* valid request this build does not handle */
+  RB_EIO = 9           /* file read/write failure */
+} rb_status;
+
+typedef enum { RB_PREC_FP64 = 0, RB_PREC_FP32 = 1, RB_PREC_BF16 = 2 } rb_prec;
+typedef enum { RB_SOLVER_RBCG = 0, RB_SOLVER_RBI = 1, RB_SOLVER_CG = 2 } rb_solver;
+typedef enum { RB_IND_RESIDUAL = 0, RB_IND_L1 = 1 } rb_indicator;
+typedef enum {
+  RB_SMOOTH_RBGS = 0,     /* one forward red-black Gauss-Seidel sweep, red first */
+  RB_SMOOTH_RBGS_SYM = 1, /* forward then backward red-black sweep */
+  RB_SMOOTH_JACOBI = 2,   /* one damped Jacobi step, omega = 2/3 */
+  RB_SMOOTH_NONE = 3      /* no smoothing (Lemma 2 of Sec. 3.2: RBI stagnates) */
+} rb_smoother;
+
+typedef struct rb_ctx rb_ctx;
+typedef struct rb_problem rb_problem;
+typedef struct rb_basis rb_basis;
+
+/* Context: a device and a HIP stream (NULL = the null stream).  The stream must
+ * outlive the context. */
+rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx** out);
+rb_status rb_ctx_destroy(rb_ctx* ctx);
+const char* rb_last_error(void);
+/* Library version string, e.g. "rb 0.1 gfx950". */
+const char* rb_version(void);
+
+/* ---- Problems: the affine operator of eq. (12) ------------------------------
+ * Matrix-free block diffusion: -div(kappa grad u) = f on the unit square/cube,
+ * u = 0 on the boundary, finite differences with n[a] interior nodes per axis
+ * (h_a = 1/(n[a]+1)), kappa constant on blocks[0] x blocks[1] x blocks[2]
+ * rectangular blocks.  Face coefficients are the mean of kappa over the face's dual
+ * cell, so A_q is the operator with kappa = indicator of block q (block number
+ * q = bx + blocks[0]*(by + blocks[1]*bz)) and Q = prod(blocks).
+ * Requirements: dim in 1..3; (n[a]+1) % blocks[a] == 0; n[0] odd if dim >= 2 and
+ * n[1] odd if dim == 3 (red-black colouring by index parity); Q <= 64.
+ * Default right-hand side: R = 1, f_1 = 1. */
+typedef struct {
+  int dim;
+  int n[3];
+  int blocks[3];
+} rb_stencil_desc;
+rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* desc, rb_problem** out);
+/* Replace the right-hand-side terms f_r: f is [R][N] host, natural ordering. */
+rb_status rb_problem_set_rhs(rb_problem* prob, int R, const double* f);
+/* Query sizes: any output pointer may be NULL. */
+rb_status rb_problem_info(const rb_problem* prob, int64_t* N, int* Q, int* R);
+rb_status rb_problem_destroy(rb_problem* prob);
+
+/* ---- Reduced bases -----------------------------------------------------------
+ * W: [n][N] host, column j = basis vector w_j (natural ordering), assumed
+ * orthonormal.  The library precomputes A_{N,q} = W^T A_q W and f_{N,r} = W^T f_r
+ * (eq. 12c) on the device. */
+rb_status rb_basis_from_host(rb_ctx* ctx, const rb_problem* prob, int n, const double* W,
+                             rb_basis** out);
+/* n, and optional copies: W [n][N] natural ordering, AN [Q][n][n], fN [R][n]. */
+rb_status rb_basis_info(const rb_basis* basis, int* n, double* W, double* AN, double* fN);
+/* Binary file: header, W (FP64), sample indices, A_{N,q}, f_{N,r}. */
+rb_status rb_basis_save(const rb_basis* basis, const char* path);
+rb_status rb_basis_load(rb_ctx* ctx, const rb_problem* prob, const char* path, rb_basis** out);
+rb_status rb_basis_destroy(rb_basis* basis);
+
+/* ---- Online solves (Alg. 3 RBCG, Alg. 2 RBI, plain CG) -----------------------
+ * Stopping rule: ||r_k|| <= rtol ||f|| on the recursive residual, confirmed on the
+ * true residual f - A x in FP64 (eq. relerr of Sec. 5.1); if the true residual
+ * fails, r is replaced by it and CG restarts from p = y.  iters = number of A p
+ * products (RBCG/CG) or of RB iterations (RBI).
+ * precond_prec: FP64 = everything in FP64; FP32 / BF16 = the preconditioner's
+ * contractions W^T r and W e in FP32 / BF16 with FP32 accumulation and the
+ * smoother and y in FP32, while x, r, p, every CG dot product, alpha, beta, the
+ * true residual and the reduced Cholesky stay FP64.
+ * beta_flexible: 0 = the ratio of step 10 of Alg. 3; 1 = y_{k+1}^T (r_{k+1}-r_k) /
+ * y_k^T r_k.  use_graph: replay captured HIP graphs of the iteration.
+ * fixed_iters > 0: run exactly that many iterations, no stopping test (testing). */
+typedef struct {
+  size_t struct_size; /* sizeof(rb_solve_opts) */
+  rb_solver solver;
+  rb_prec precond_prec;
+  rb_smoother smoother;
+  double rtol;     /* default 1e-10 */
+  int maxit;       /* default 2000 */
+  int beta_flexible;
+  int use_graph;
+  int fixed_iters;
+  int check_every; /* iterations between host checks of the active count; 0 = auto */
+} rb_solve_opts;
+void rb_solve_opts_default(rb_solve_opts* opts);
+
+typedef struct {
+  int iters;
+  double rel_res_true;
+  double rel_res_recursive;
+  rb_status status;
+} rb_query_stats;
+
+/* B queries on one problem and basis.  theta [B][Q] host; phi [B][R] host or NULL
+ * (all ones); n_use [B] host or NULL (= basis size): query b uses the leading
+ * n_use[b] basis vectors; basis may be NULL for RB_SOLVER_CG.
+ * x: [B][N] DEVICE doubles, natural ordering, written with the solutions.
+ * stats: [B] host, written. */
+rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
+                         const rb_solve_opts* opts, int B, const double* theta,
+                         const double* phi, const int* n_use, double* x,
+                         rb_query_stats* stats);
+
+/* Queries on several problems/bases in one call (uneven batches). */
+typedef struct {
+  int problem;          /* index into probs/bases */
+  int n_use;            /* <= 0: the whole basis */
+  const double* theta;  /* [Q] host */
+  const double* phi;    /* [R] host or NULL */
+  double* x;            /* [N] DEVICE */
+} rb_query;
+rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
+                         const rb_basis* const* bases, const rb_solve_opts* opts, int B,
+                         const rb_query* queries, rb_query_stats* stats);
+
+/* ---- Single steps of the hot path (diagnostics and parity tests) ------------
+ * y_b = A(theta_b) u_b.  u, y: [B][N] DEVICE, natural ordering. */
+rb_status rb_apply_batch(rb_ctx* ctx, const rb_problem* prob, int B, const double* theta,
+                         const double* u, double* y);
+/* y_b = RBI(A(theta_b), r_b, W_{n_use[b]}, 1): one RB iteration from x = 0 (projection
+ * W^T r, reduced Cholesky solve, prolongation, one smoother application) as used by
+ * RBCG (Alg. 3 steps 2 and 9).  r, y: [B][N] DEVICE FP64, natural ordering. */
+rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
+                           const rb_solve_opts* opts, int B, const double* theta,
+                           const int* n_use, const double* r, double* y);
+/* t_b = W^T r_b (eq. 5) with the given precision.  r: [B][N] DEVICE natural
+ * ordering; t: [B][n] host. */
+rb_status rb_project_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
+                           rb_prec prec, int B, const double* r, double* t);
+/* L_b = chol(sum_q theta_bq A_{N,q}) (lower, row-major [B][n][n] host, upper part
+ * zero), status[b] = RB_OK or RB_ENOTSPD. */
+rb_status rb_reduced_factor_batch(rb_ctx* ctx, const rb_basis* basis, int B,
+                                  const double* theta, double* L, rb_status* status);
+
+/* ---- Offline: adaptive greedy (Alg. 4) --------------------------------------
+ * Training set Xi_train of M parameters: theta [M][Q] host (and phi [M][R] or
+ * NULL).  mu [M][P] host or NULL is used only for the surrogate's features.
+ * Snapshot solves x(mu_N) = RBCG(A(mu_N), f, W_{N-1}) (W_0 empty: smoother-only
+ * PCG), modified Gram-Schmidt, growth of A_{N,q} and f_{N,r}, and a sweep of the
+ * indicator over Xi_train with argmax over the unpicked candidates (lowest index
+ * wins ties).  Indicators: RB_IND_L1 = sum_n |a_n(mu)| (Alg. 1/4 step 6);
+ * RB_IND_RESIDUAL = ||f - A(mu) W a(mu)|| / ||f||.
+ * use_surrogate: rank candidates by an MLP (P -> 128 -> 128 -> 1, GELU) trained
+ * on the GPU on the indicators already computed; the true indicator is evaluated
+ * on the top `topk` plus `explore` random candidates and decides the pick; full
+ * sweeps every `full_sweep_every` steps, for the first `warmup_full_sweeps` steps,
+ * and whenever the ranking check fails. */
+typedef struct {
+  size_t struct_size; /* sizeof(rb_greedy_opts) */
+  int n_max;
+  int64_t seed_index;
+  rb_indicator indicator;
+  double snapshot_rtol;  /* default 1e-10 */
+  int snapshot_maxit;    /* default 5000 */
+  int snapshot_flexible; /* default 1 */
+  int use_surrogate;
+  int topk;              /* default 256 */
+  int explore;           /* default 64 */
+  int full_sweep_every;  /* default 10 */
+  int warmup_full_sweeps;/* default 4 */
+  int train_steps;       /* Adam steps per greedy step, default 50 */
+  double lr;             /* default 1e-3 */
+  double mu_lo, mu_hi;   /* log range of mu for the features */
+  uint64_t seed;
+} rb_greedy_opts;
+void rb_greedy_opts_default(rb_greedy_opts* opts);
+
+typedef struct {
+  int n_built;
+  int64_t* picks;          /* caller-allocated [n_max] or NULL */
+  double* max_indicator;   /* [n_max] or NULL: max indicator after step N */
+  int* snapshot_iters;     /* [n_max] or NULL */
+  int64_t true_evals;      /* candidates whose true indicator was computed */
+  int full_sweeps;
+  double seconds;
+  double mlp_loss;         /* last training loss (surrogate) */
+} rb_greedy_report;
+
+rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob, const rb_greedy_opts* opts,
+                           int64_t M, int P, const double* mu, const double* theta,
+                           const double* phi, rb_basis** out, rb_greedy_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RB_H_ */

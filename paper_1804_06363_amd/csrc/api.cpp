@@ -1,0 +1,627 @@
+// C ABI of librb (include/rb.h): contexts, problems, bases, online solves and the
+// single-step diagnostics.  Every entry point catches all C++ exceptions and turns
+// them into an rb_status plus a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+#include "solver.h"
+
+namespace rb {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+void DevBuf::alloc(size_t n) {
+  release();
+  if (n == 0) n = 64;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    throw Error{RB_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+  }
+  bytes = n;
+  if (hipMemset(p, 0, n) != hipSuccess) {
+    (void)hipFree(p);
+    p = nullptr;
+    throw Error{RB_EDEVICE, "hipMemset failed"};
+  }
+}
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+template <typename F>
+static rb_status guarded(F&& f) {
+  try {
+    f();
+    return RB_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return RB_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RB_EINVAL;
+  } catch (...) {
+    set_error("unknown error");
+    return RB_EINVAL;
+  }
+}
+
+struct DeviceGuard {
+  int old = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&old);
+    if (old != dev) RB_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(old); }
+};
+
+static void check_finite(const double* v, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    RB_REQUIRE(std::isfinite(v[i]), RB_EINVAL, std::string(what) + " contains NaN or Inf");
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+static int64_t align_ld(int64_t N) { return (N + 63) / 64 * 64; }
+
+// Red-black storage position -> lexicographic index.
+static inline int lex_of(const StencilGeom& g, int pos) {
+  return pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
+}
+
+const void* rb_basis::shadow(rb_prec prec) {
+  if (prec == RB_PREC_FP64) return W64.p;
+  DevBuf& dst = prec == RB_PREC_FP32 ? W32 : W16;
+  if (!dst.p) {
+    const size_t es = prec == RB_PREC_FP32 ? sizeof(float) : sizeof(uint16_t);
+    dst.alloc(es * (size_t)std::max(n, 1) * ld);
+    if (n > 0) launch_cast(W64.as<double>(), dst.p, (int64_t)n * ld, prec, ctx->stream);
+  }
+  return dst.p;
+}
+
+extern "C" {
+
+const char* rb_last_error(void) { return g_err.c_str(); }
+const char* rb_version(void) { return "rb 0.1 gfx950"; }
+
+void rb_solve_opts_default(rb_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(rb_solve_opts);
+  o->solver = RB_SOLVER_RBCG;
+  o->precond_prec = RB_PREC_FP64;
+  o->smoother = RB_SMOOTH_RBGS;
+  o->rtol = 1e-10;
+  o->maxit = 2000;
+}
+
+rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx** out) {
+  return guarded([&] {
+    RB_REQUIRE(out, RB_EINVAL, "out is NULL");
+    int count = 0;
+    RB_HIP(hipGetDeviceCount(&count));
+    RB_REQUIRE(device >= 0 && device < count, RB_EINVAL, "no such device");
+    auto c = std::make_unique<rb_ctx>();
+    c->device = device;
+    DeviceGuard dg(device);
+    RB_HIP(hipGetDeviceProperties(&c->prop, device));
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      RB_HIP(hipStreamCreate(&c->stream));  // blocking stream, default priority
+      c->own_stream = true;
+    }
+    *out = c.release();
+  });
+}
+
+rb_status rb_ctx_destroy(rb_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    if (ctx->own_stream && ctx->stream) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+  });
+}
+
+rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* d, rb_problem** out) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && d && out, RB_EINVAL, "null argument");
+    RB_REQUIRE(d->dim >= 1 && d->dim <= 3, RB_EINVAL, "dim must be 1..3");
+    int n[3] = {1, 1, 1}, b[3] = {1, 1, 1};
+    int64_t N = 1;
+    int Q = 1;
+    for (int a = 0; a < d->dim; ++a) {
+      n[a] = d->n[a];
+      b[a] = d->blocks[a];
+      RB_REQUIRE(n[a] >= 1 && b[a] >= 1, RB_EINVAL, "sizes must be positive");
+      RB_REQUIRE((n[a] + 1) % b[a] == 0, RB_EINVAL, "(n+1) must be divisible by blocks");
+      RB_REQUIRE(b[a] <= 64, RB_EUNSUPPORTED, "at most 64 blocks per axis");
+      N *= n[a];
+      Q *= b[a];
+    }
+    RB_REQUIRE(N < (1ll << 30), RB_EUNSUPPORTED, "grid too large (N >= 2^30)");
+    RB_REQUIRE(Q <= 64, RB_EUNSUPPORTED, "at most 64 affine terms");
+    if (d->dim >= 2) RB_REQUIRE(n[0] % 2 == 1, RB_EUNSUPPORTED, "n[0] must be odd");
+    if (d->dim == 3) RB_REQUIRE(n[1] % 2 == 1, RB_EUNSUPPORTED, "n[1] must be odd");
+    DeviceGuard dg(ctx->device);
+    auto p = std::make_unique<rb_problem>();
+    p->ctx = ctx;
+    p->desc = *d;
+    p->N = N;
+    p->ld = align_ld(N);
+    StencilGeom& g = p->g;
+    g.dim = d->dim;
+    g.nx = n[0]; g.ny = n[1]; g.nz = n[2];
+    g.bx = b[0]; g.by = b[1]; g.bz = b[2];
+    g.Q = Q;
+    g.N = (int)N;
+    g.NR = (int)((N + 1) / 2);
+    g.nxy = n[0] * n[1];
+    g.div_nx = rbk::make_fastdiv((uint32_t)n[0]);
+    g.div_nxy = rbk::make_fastdiv((uint32_t)(n[0] * n[1]));
+    // per-axis node tables: state | lo-face block << 8 | hi-face block << 16
+    std::vector<uint32_t> tab;
+    size_t offs[3];
+    for (int a = 0; a < 3; ++a) {
+      offs[a] = tab.size();
+      const int m = (n[a] + 1) / b[a];
+      for (int i = 0; i < n[a]; ++i) {
+        const int I = i + 1;
+        const int state = (I % m == 0) ? 2 * (I / m) - 1 : 2 * (I / m);
+        const int lo = i / m, hi = (i + 1) / m;
+        tab.push_back((uint32_t)state | ((uint32_t)lo << 8) | ((uint32_t)hi << 16));
+      }
+    }
+    p->tabs.alloc(sizeof(uint32_t) * tab.size());
+    RB_HIP(hipMemcpy(p->tabs.p, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice));
+    for (int a = 0; a < 3; ++a) g.tab[a] = p->tabs.as<uint32_t>() + offs[a];
+    // coefficient tables: axis a -> [normal block][state t1][state t2]
+    int off = 0;
+    const int S[3] = {2 * b[0] - 1, 2 * b[1] - 1, 2 * b[2] - 1};
+    for (int a = 0; a < 3; ++a) {
+      const int t1 = a == 0 ? 1 : 0;
+      const int t2 = a == 2 ? 1 : 2;
+      g.ct_off[a] = off;
+      g.ct_s1[a] = S[t1];
+      g.ct_s2[a] = S[t2];
+      if (a < d->dim) off += b[a] * S[t1] * S[t2];
+    }
+    g.ct_size = (off + 7) / 8 * 8;
+    RB_REQUIRE(g.ct_size <= 1024, RB_EUNSUPPORTED, "too many kappa blocks for the stencil tables");
+    // default right-hand side f = 1
+    p->R = 1;
+    p->f_host.assign((size_t)N, 1.0);
+    p->f.alloc(sizeof(double) * p->ld);
+    launch_fill<double>(p->f.as<double>(), 0, N, 1, 1.0, ctx->stream);
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    *out = p.release();
+  });
+}
+
+rb_status rb_problem_set_rhs(rb_problem* p, int R, const double* f) {
+  return guarded([&] {
+    RB_REQUIRE(p && f && R >= 1 && R <= 64, RB_EINVAL, "bad rhs arguments");
+    check_finite(f, (size_t)R * p->N, "f");
+    DeviceGuard dg(p->ctx->device);
+    DevBuf nat(sizeof(double) * (size_t)R * p->N);
+    RB_HIP(hipMemcpy(nat.p, f, sizeof(double) * (size_t)R * p->N, hipMemcpyHostToDevice));
+    DevBuf sto(sizeof(double) * (size_t)R * p->ld);
+    launch_to_storage(*p, R, nat.as<double>(), p->N, sto.as<double>(), p->ld, p->ctx->stream);
+    RB_HIP(hipStreamSynchronize(p->ctx->stream));
+    p->f = std::move(sto);
+    p->f_host.assign(f, f + (size_t)R * p->N);
+    p->R = R;
+  });
+}
+
+rb_status rb_problem_info(const rb_problem* p, int64_t* N, int* Q, int* R) {
+  return guarded([&] {
+    RB_REQUIRE(p, RB_EINVAL, "null problem");
+    if (N) *N = p->N;
+    if (Q) *Q = p->g.Q;
+    if (R) *R = p->R;
+  });
+}
+
+rb_status rb_problem_destroy(rb_problem* p) {
+  return guarded([&] { delete p; });
+}
+
+}  // extern "C"
+
+namespace rb {
+
+// A_{N,q} = W^T A_q W and f_{N,r} = W^T f_r (eq. 12c) for the columns [j0, n) of the
+// basis (rows/columns < j0 are kept), computed with the stencil and projection kernels.
+void compute_reduced(rb_basis* bs, int j0) {
+  const rb_problem* p = bs->prob;
+  const StencilGeom& g = p->g;
+  hipStream_t st = bs->ctx->stream;
+  const int n = bs->n, Q = g.Q, R = p->R;
+  const int nn = n - j0;
+  std::vector<double> AN((size_t)Q * n * n, 0.0), fN((size_t)R * n, 0.0);
+  for (int q = 0; q < Q; ++q)
+    for (int i = 0; i < j0; ++i)
+      for (int j = 0; j < j0; ++j)
+        AN[((size_t)q * n + i) * n + j] = bs->AN_host[((size_t)q * j0 + i) * j0 + j];
+  for (int r = 0; r < R; ++r)
+    for (int j = 0; j < j0; ++j) fN[(size_t)r * n + j] = bs->fN_host[(size_t)r * j0 + j];
+  if (nn > 0) {
+    const int64_t ld = p->ld;
+    DevBuf V(sizeof(double) * (size_t)nn * ld);
+    DevBuf th(sizeof(double) * (size_t)nn * Q);
+    DevBuf coef(sizeof(double) * (size_t)nn * g.ct_size);
+    DevBuf t(sizeof(double) * (size_t)nn * n);
+    const ProjPlan pl = plan_projection(g.N, nn, n, 2048);
+    DevBuf part(sizeof(double) * (size_t)pl.chunks * nn * pl.nj);
+    DevBuf ones(sizeof(int) * nn);
+    launch_fill<int>(ones.as<int>(), 0, nn, 1, 1, st);
+    std::vector<double> unit((size_t)nn * Q);
+    for (int q = 0; q < Q; ++q) {
+      std::fill(unit.begin(), unit.end(), 0.0);
+      for (int j = 0; j < nn; ++j) unit[(size_t)j * Q + q] = 1.0;
+      RB_HIP(hipMemcpyAsync(th.p, unit.data(), sizeof(double) * unit.size(), hipMemcpyHostToDevice,
+                            st));
+      launch_coef_tables(g, nn, th.as<double>(), nullptr, coef.as<double>(), st);
+      // V_j = A_q w_{j0+j}
+      launch_apply(g, ld, nn, coef.as<double>(), bs->W64.as<double>() + (size_t)j0 * ld,
+                   V.as<double>(), 0, nullptr, 0, nullptr, nullptr, nullptr, 4, st);
+      // t[j][i] = w_i^T V_j for i < n
+      launch_projection(pl, RB_PREC_FP64, V.as<double>(), ld, bs->W64.p, ld, n, nn, ones.as<int>(),
+                        part.p, st);
+      launch_reduce_solve(true, part.p, pl.chunks, nn, pl.nj, n, nullptr, nullptr, nullptr,
+                          t.as<double>(), nullptr, nullptr, 16, false, st);
+      std::vector<double> th_((size_t)nn * n);
+      RB_HIP(hipMemcpyAsync(th_.data(), t.p, sizeof(double) * th_.size(), hipMemcpyDeviceToHost,
+                            st));
+      RB_HIP(hipStreamSynchronize(st));
+      for (int j = 0; j < nn; ++j)
+        for (int i = 0; i < n; ++i) {
+          const double v = th_[(size_t)j * n + i];
+          AN[((size_t)q * n + i) * n + (j0 + j)] = v;
+          AN[((size_t)q * n + (j0 + j)) * n + i] = v;
+        }
+    }
+    // f_{N,r}: project the right-hand-side terms
+    const ProjPlan pf = plan_projection(g.N, R, n, 2048);
+    DevBuf partf(sizeof(double) * (size_t)pf.chunks * R * pf.nj);
+    DevBuf tf(sizeof(double) * (size_t)R * n);
+    DevBuf onesR(sizeof(int) * R);
+    launch_fill<int>(onesR.as<int>(), 0, R, 1, 1, st);
+    launch_projection(pf, RB_PREC_FP64, p->f.as<double>(), ld, bs->W64.p, ld, n, R,
+                      onesR.as<int>(), partf.p, st);
+    launch_reduce_solve(true, partf.p, pf.chunks, R, pf.nj, n, nullptr, nullptr, nullptr,
+                        tf.as<double>(), nullptr, nullptr, 16, false, st);
+    std::vector<double> fh((size_t)R * n);
+    RB_HIP(hipMemcpyAsync(fh.data(), tf.p, sizeof(double) * fh.size(), hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < R; ++r)
+      for (int j = j0; j < n; ++j) fN[(size_t)r * n + j] = fh[(size_t)r * n + j];
+  }
+  bs->AN_host = std::move(AN);
+  bs->fN_host = std::move(fN);
+  bs->AN.alloc(sizeof(double) * std::max<size_t>(1, bs->AN_host.size()));
+  bs->fN.alloc(sizeof(double) * std::max<size_t>(1, bs->fN_host.size()));
+  if (!bs->AN_host.empty())
+    RB_HIP(hipMemcpyAsync(bs->AN.p, bs->AN_host.data(), sizeof(double) * bs->AN_host.size(),
+                          hipMemcpyHostToDevice, st));
+  if (!bs->fN_host.empty())
+    RB_HIP(hipMemcpyAsync(bs->fN.p, bs->fN_host.data(), sizeof(double) * bs->fN_host.size(),
+                          hipMemcpyHostToDevice, st));
+  RB_HIP(hipStreamSynchronize(st));
+}
+
+static rb_basis* basis_upload(rb_ctx* ctx, const rb_problem* p, int n, const double* W) {
+  auto bs = std::make_unique<rb_basis>();
+  bs->ctx = ctx;
+  bs->prob = p;
+  bs->n = n;
+  bs->ld = p->ld;
+  bs->W64.alloc(sizeof(double) * (size_t)std::max(n, 1) * p->ld);
+  if (n > 0) {
+    DevBuf nat(sizeof(double) * (size_t)n * p->N);
+    RB_HIP(hipMemcpy(nat.p, W, sizeof(double) * (size_t)n * p->N, hipMemcpyHostToDevice));
+    launch_to_storage(*p, n, nat.as<double>(), p->N, bs->W64.as<double>(), p->ld, ctx->stream);
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  compute_reduced(bs.get(), 0);
+  return bs.release();
+}
+
+}  // namespace rb
+
+extern "C" {
+
+rb_status rb_basis_from_host(rb_ctx* ctx, const rb_problem* p, int n, const double* W,
+                             rb_basis** out) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && out && n >= 0 && (n == 0 || W), RB_EINVAL, "bad basis arguments");
+    RB_REQUIRE(n <= 80, RB_EUNSUPPORTED, "basis size above 80");
+    check_finite(W, (size_t)n * p->N, "W");
+    DeviceGuard dg(ctx->device);
+    *out = basis_upload(ctx, p, n, W);
+  });
+}
+
+rb_status rb_basis_info(const rb_basis* bs, int* n, double* W, double* AN, double* fN) {
+  return guarded([&] {
+    RB_REQUIRE(bs, RB_EINVAL, "null basis");
+    const rb_problem* p = bs->prob;
+    if (n) *n = bs->n;
+    if (W && bs->n > 0) {
+      DeviceGuard dg(bs->ctx->device);
+      DevBuf nat(sizeof(double) * (size_t)bs->n * p->N);
+      launch_from_storage(*p, bs->n, bs->W64.as<double>(), p->ld, nat.as<double>(), p->N,
+                          bs->ctx->stream);
+      RB_HIP(hipStreamSynchronize(bs->ctx->stream));
+      RB_HIP(hipMemcpy(W, nat.p, sizeof(double) * (size_t)bs->n * p->N, hipMemcpyDeviceToHost));
+    }
+    if (AN) std::copy(bs->AN_host.begin(), bs->AN_host.end(), AN);
+    if (fN) std::copy(bs->fN_host.begin(), bs->fN_host.end(), fN);
+  });
+}
+
+static const uint64_t kMagic = 0x3142425242524231ull;  // "1BRBRBB1"
+
+rb_status rb_basis_save(const rb_basis* bs, const char* path) {
+  return guarded([&] {
+    RB_REQUIRE(bs && path, RB_EINVAL, "null argument");
+    const rb_problem* p = bs->prob;
+    std::vector<double> W((size_t)bs->n * p->N);
+    rb_status s = rb_basis_info(bs, nullptr, W.data(), nullptr, nullptr);
+    RB_REQUIRE(s == RB_OK, s, rb_last_error());
+    FILE* f = std::fopen(path, "wb");
+    RB_REQUIRE(f, RB_EIO, std::string("cannot open ") + path);
+    const int64_t hdr[6] = {(int64_t)kMagic, p->N, bs->n, p->g.Q, p->R, (int64_t)bs->picks.size()};
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+    ok = ok && std::fwrite(W.data(), sizeof(double), W.size(), f) == W.size();
+    ok = ok && std::fwrite(bs->picks.data(), sizeof(int64_t), bs->picks.size(), f) ==
+                   bs->picks.size();
+    ok = ok && std::fwrite(bs->AN_host.data(), sizeof(double), bs->AN_host.size(), f) ==
+                   bs->AN_host.size();
+    ok = ok && std::fwrite(bs->fN_host.data(), sizeof(double), bs->fN_host.size(), f) ==
+                   bs->fN_host.size();
+    ok = (std::fclose(f) == 0) && ok;
+    RB_REQUIRE(ok, RB_EIO, std::string("write failed: ") + path);
+  });
+}
+
+rb_status rb_basis_load(rb_ctx* ctx, const rb_problem* p, const char* path, rb_basis** out) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && path && out, RB_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    RB_REQUIRE(f, RB_EIO, std::string("cannot open ") + path);
+    int64_t hdr[6];
+    bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1;
+    if (!ok || (uint64_t)hdr[0] != kMagic) {
+      std::fclose(f);
+      throw Error{RB_EIO, "not a basis file"};
+    }
+    if (hdr[1] != p->N || hdr[3] != p->g.Q || hdr[4] != p->R || hdr[2] < 0 || hdr[2] > 80 ||
+        hdr[5] < 0 || hdr[5] > hdr[2]) {
+      std::fclose(f);
+      throw Error{RB_EINVAL, "basis file does not match the problem"};
+    }
+    const int n = (int)hdr[2];
+    std::vector<double> W((size_t)n * p->N);
+    std::vector<int64_t> picks((size_t)hdr[5]);
+    ok = std::fread(W.data(), sizeof(double), W.size(), f) == W.size();
+    ok = ok && std::fread(picks.data(), sizeof(int64_t), picks.size(), f) == picks.size();
+    std::fclose(f);
+    RB_REQUIRE(ok, RB_EIO, "truncated basis file");
+    DeviceGuard dg(ctx->device);
+    rb_basis* bs = basis_upload(ctx, p, n, W.data());
+    bs->picks = picks;
+    *out = bs;
+  });
+}
+
+rb_status rb_basis_destroy(rb_basis* bs) {
+  return guarded([&] { delete bs; });
+}
+
+static void check_opts(const rb_solve_opts* o) {
+  RB_REQUIRE(o && o->struct_size == sizeof(rb_solve_opts), RB_EINVAL,
+             "rb_solve_opts.struct_size mismatch");
+  RB_REQUIRE(o->rtol >= 0.0 && o->maxit >= 1 && o->fixed_iters >= 0, RB_EINVAL, "bad options");
+  RB_REQUIRE(o->solver >= RB_SOLVER_RBCG && o->solver <= RB_SOLVER_CG, RB_EINVAL, "bad solver");
+  RB_REQUIRE(o->precond_prec >= RB_PREC_FP64 && o->precond_prec <= RB_PREC_BF16, RB_EINVAL,
+             "bad precision");
+  RB_REQUIRE(o->smoother >= RB_SMOOTH_RBGS && o->smoother <= RB_SMOOTH_NONE, RB_EINVAL,
+             "bad smoother");
+}
+
+rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
+                         const rb_solve_opts* o, int B, const double* theta, const double* phi,
+                         const int* n_use, double* x, rb_query_stats* stats) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && theta && x && stats && B >= 1 && B <= 65535, RB_EINVAL,
+               "bad solve arguments");
+    check_opts(o);
+    RB_REQUIRE(bs || o->solver == RB_SOLVER_CG, RB_EINVAL, "basis required");
+    RB_REQUIRE(!bs || bs->prob == p, RB_EINVAL, "basis belongs to another problem");
+    check_finite(theta, (size_t)B * p->g.Q, "theta");
+    if (phi) check_finite(phi, (size_t)B * p->R, "phi");
+    DeviceGuard dg(ctx->device);
+    BatchSolver s(ctx, p, bs, *o, B, theta, phi, n_use);
+    s.run();
+    std::vector<rb_query_stats> st;
+    s.gather(x, p->N, st);
+    std::copy(st.begin(), st.end(), stats);
+  });
+}
+
+rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
+                         const rb_basis* const* bases, const rb_solve_opts* o, int B,
+                         const rb_query* qs, rb_query_stats* stats) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && probs && qs && stats && nprob >= 1 && B >= 0, RB_EINVAL,
+               "bad multi-solve arguments");
+    check_opts(o);
+    // group the queries by problem; each group is one batched solve
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < B; ++i) {
+      RB_REQUIRE(qs[i].problem >= 0 && qs[i].problem < nprob && qs[i].theta && qs[i].x,
+                 RB_EINVAL, "bad query");
+      groups[qs[i].problem].push_back(i);
+    }
+    DeviceGuard dg(ctx->device);
+    for (auto& kv : groups) {
+      const rb_problem* p = probs[kv.first];
+      const rb_basis* bs = bases ? bases[kv.first] : nullptr;
+      RB_REQUIRE(p, RB_EINVAL, "null problem");
+      const std::vector<int>& idx = kv.second;
+      const int Bg = (int)idx.size();
+      const int Q = p->g.Q, R = p->R;
+      std::vector<double> th((size_t)Bg * Q), ph((size_t)Bg * R, 1.0);
+      std::vector<int> nu(Bg);
+      bool any_phi = false;
+      for (int k = 0; k < Bg; ++k) {
+        const rb_query& q = qs[idx[k]];
+        std::copy(q.theta, q.theta + Q, th.begin() + (size_t)k * Q);
+        if (q.phi) {
+          any_phi = true;
+          std::copy(q.phi, q.phi + R, ph.begin() + (size_t)k * R);
+        }
+        nu[k] = (q.n_use <= 0 && bs) ? bs->n : q.n_use;
+      }
+      check_finite(th.data(), th.size(), "theta");
+      BatchSolver s(ctx, p, bs, *o, Bg, th.data(), any_phi ? ph.data() : nullptr, nu.data());
+      s.run();
+      std::vector<rb_query_stats> st;
+      DevBuf xs(sizeof(double) * (size_t)Bg * p->N);
+      s.gather(xs.as<double>(), p->N, st);
+      for (int k = 0; k < Bg; ++k) {
+        RB_HIP(hipMemcpyAsync(qs[idx[k]].x, xs.as<double>() + (size_t)k * p->N,
+                              sizeof(double) * p->N, hipMemcpyDeviceToDevice, ctx->stream));
+        stats[idx[k]] = st[k];
+      }
+      RB_HIP(hipStreamSynchronize(ctx->stream));
+    }
+  });
+}
+
+rb_status rb_apply_batch(rb_ctx* ctx, const rb_problem* p, int B, const double* theta,
+                         const double* u, double* y) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && theta && u && y && B >= 1 && B <= 65535, RB_EINVAL, "bad arguments");
+    check_finite(theta, (size_t)B * p->g.Q, "theta");
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = ctx->stream;
+    DevBuf th(sizeof(double) * (size_t)B * p->g.Q);
+    RB_HIP(hipMemcpyAsync(th.p, theta, th.bytes, hipMemcpyHostToDevice, st));
+    DevBuf coef(sizeof(double) * (size_t)B * p->g.ct_size);
+    launch_coef_tables(p->g, B, th.as<double>(), nullptr, coef.as<double>(), st);
+    DevBuf us(sizeof(double) * (size_t)B * p->ld), ys(sizeof(double) * (size_t)B * p->ld);
+    launch_to_storage(*p, B, u, p->N, us.as<double>(), p->ld, st);
+    launch_apply(p->g, p->ld, B, coef.as<double>(), us.as<double>(), ys.as<double>(), 0, nullptr,
+                 0, nullptr, nullptr, nullptr, 4, st);
+    launch_from_storage(*p, B, ys.as<double>(), p->ld, y, p->N, st);
+    RB_HIP(hipStreamSynchronize(st));
+  });
+}
+
+rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
+                           const rb_solve_opts* o, int B, const double* theta, const int* n_use,
+                           const double* r, double* y) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && theta && r && y && B >= 1 && B <= 65535, RB_EINVAL, "bad arguments");
+    check_opts(o);
+    RB_REQUIRE(!bs || bs->prob == p, RB_EINVAL, "basis belongs to another problem");
+    check_finite(theta, (size_t)B * p->g.Q, "theta");
+    DeviceGuard dg(ctx->device);
+    rb_solve_opts oo = *o;
+    oo.solver = RB_SOLVER_RBCG;
+    oo.beta_flexible = 0;
+    BatchSolver s(ctx, p, bs, oo, B, theta, nullptr, n_use);
+    hipStream_t st = ctx->stream;
+    launch_to_storage(*p, B, r, p->N, s.r0.as<double>(), p->ld, st);
+    s.factor();
+    s.precondition(s.r0.as<double>(), nullptr);
+    // y (FP64 or FP32) -> natural-order FP64
+    DevBuf y64;
+    const double* ysrc = s.y.as<double>();
+    if (s.y32) {
+      y64.alloc(sizeof(double) * (size_t)B * p->ld);
+      launch_widen(s.y.as<float>(), y64.as<double>(), (int64_t)B * p->ld, st);
+      ysrc = y64.as<double>();
+    }
+    launch_from_storage(*p, B, ysrc, p->ld, y, p->N, st);
+    RB_HIP(hipStreamSynchronize(st));
+  });
+}
+
+rb_status rb_project_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs, rb_prec prec,
+                           int B, const double* r, double* t) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && p && bs && r && t && B >= 1 && B <= 65535, RB_EINVAL, "bad arguments");
+    RB_REQUIRE(bs->prob == p, RB_EINVAL, "basis belongs to another problem");
+    RB_REQUIRE(prec >= RB_PREC_FP64 && prec <= RB_PREC_BF16, RB_EINVAL, "bad precision");
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = ctx->stream;
+    const int n = bs->n;
+    if (n == 0) return;
+    DevBuf rs(sizeof(double) * (size_t)B * p->ld);
+    launch_to_storage(*p, B, r, p->N, rs.as<double>(), p->ld, st);
+    const ProjPlan pl = plan_projection(p->g.N, B, n, 2048);
+    const size_t acc = prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
+    DevBuf part(acc * (size_t)pl.chunks * B * pl.nj);
+    DevBuf ones(sizeof(int) * B);
+    launch_fill<int>(ones.as<int>(), 0, B, 1, 1, st);
+    const void* W = const_cast<rb_basis*>(bs)->shadow(prec);
+    launch_projection(pl, prec, rs.as<double>(), p->ld, W, p->ld, n, B, ones.as<int>(), part.p, st);
+    DevBuf td(sizeof(double) * (size_t)B * n);
+    launch_reduce_solve(prec == RB_PREC_FP64, part.p, pl.chunks, B, pl.nj, n, nullptr, nullptr,
+                        nullptr, td.as<double>(), nullptr, nullptr, 16, false, st);
+    RB_HIP(hipMemcpyAsync(t, td.p, sizeof(double) * (size_t)B * n, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+  });
+}
+
+rb_status rb_reduced_factor_batch(rb_ctx* ctx, const rb_basis* bs, int B, const double* theta,
+                                  double* L, rb_status* status) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && bs && theta && L && status && B >= 1 && B <= 65535, RB_EINVAL,
+               "bad arguments");
+    const int n = bs->n, Q = bs->prob->g.Q;
+    RB_REQUIRE(n >= 1, RB_EINVAL, "empty basis");
+    check_finite(theta, (size_t)B * Q, "theta");
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = ctx->stream;
+    DevBuf th(sizeof(double) * (size_t)B * Q), Ld(sizeof(double) * (size_t)B * n * n),
+        sd(sizeof(int) * B);
+    RB_HIP(hipMemcpyAsync(th.p, theta, th.bytes, hipMemcpyHostToDevice, st));
+    launch_cholesky(bs->AN.as<double>(), n, Q, B, th.as<double>(), nullptr, Ld.as<double>(),
+                    sd.as<int>(), st);
+    std::vector<int> sh(B);
+    RB_HIP(hipMemcpyAsync(L, Ld.p, Ld.bytes, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipMemcpyAsync(sh.data(), sd.p, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < B; ++i) status[i] = (rb_status)sh[i];
+  });
+}
+
+}  // extern "C"

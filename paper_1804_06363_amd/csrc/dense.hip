@@ -1,0 +1,906 @@
+// Reduced-basis contractions and reduced solves.
+//
+//  * projection   t_b = W^T r_b            (eq. 5; Alg. 2 step 4)   MFMA, split-K partials
+//  * prolongation z_b = W e_b              (eq. 7; Alg. 2 step 6)   one node per thread
+//  * reduced assembly + Cholesky  A_N(mu) = sum_q Theta_q A_{N,q} = L L^T  (eq. 12b, Sec. 2.1)
+//  * reduced solve  e_b = L^-T L^-1 t_b    (eq. 6; Alg. 2 step 5)
+//  * deterministic finalisation of per-block partial sums and the CG scalars of Alg. 3
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace rb {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// ---- MFMA projection ---------------------------------------------------------------
+// part[chunk][b][j] = sum_{k in chunk} W[j][k] r_b[k] for j < 16*JT.
+// One wave owns a 16*QT (queries) x 16*JT (basis) tile of the product R W^T and walks
+// its DOF range in steps of 16 with 16x16 MFMA tiles (queries = MFMA rows, basis
+// vectors = MFMA columns).  Within a 16-DOF step lane l (row l%16, group g = l/16)
+// supplies the four consecutive DOFs k0+4g..k0+4g+3, so each lane issues contiguous
+// vector loads; for the K=4 instructions (FP32/FP64) sub-step s uses DOF k0+4g+s of
+// both operands, for the K=16 BF16 instruction group g holds k0+4g..+3.  The
+// summation order is fixed by the tiling, so results are deterministic.
+// Vectors must be zero beyond N up to their stride (the library keeps them so).
+template <typename TW>
+struct ProjTraits;
+template <>
+struct ProjTraits<double> {
+  using Acc = double;
+  using Vec = doublex4;
+};
+template <>
+struct ProjTraits<float> {
+  using Acc = float;
+  using Vec = floatx4;
+};
+template <>
+struct ProjTraits<uint16_t> {
+  using Acc = float;
+  using Vec = floatx4;
+};
+
+// Row (within a 16-row tile) of accumulator register i held by lane group g: the FP32 /
+// BF16 16x16 instructions give row 4g + i, the FP64 16x16x4 instruction row g + 4i.
+template <typename TW>
+__device__ __forceinline__ int acc_row(int g, int i) {
+  return sizeof(TW) == 8 ? g + 4 * i : 4 * g + i;
+}
+
+template <typename TW, int QT, int JT>
+__device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t r_ld,
+                                          const TW* __restrict__ W, int64_t w_ld, int n,
+                                          int q_base, int B, const int* __restrict__ active,
+                                          int k0, typename ProjTraits<TW>::Vec (&acc)[QT][JT]) {
+  const int lane = threadIdx.x & 63;
+  const int qi = lane & 15, kg = lane >> 4;
+  const int kk = k0 + 4 * kg;
+  double a[QT][4];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    const int q = q_base + 16 * t + qi;
+    if (q < B && active[q]) {
+      const double2* src = reinterpret_cast<const double2*>(R + (size_t)q * r_ld + kk);
+      const double2 v0 = src[0], v1 = src[1];
+      a[t][0] = v0.x; a[t][1] = v0.y; a[t][2] = v1.x; a[t][3] = v1.y;
+    } else {
+      a[t][0] = a[t][1] = a[t][2] = a[t][3] = 0.0;
+    }
+  }
+  if constexpr (sizeof(TW) == 8) {  // FP64
+    double w[JT][4];
+#pragma unroll
+    for (int u = 0; u < JT; ++u) {
+      const int j = 16 * u + qi;
+      if (j < n) {
+        const double2* src = reinterpret_cast<const double2*>(W + (size_t)j * w_ld + kk);
+        const double2 v0 = src[0], v1 = src[1];
+        w[u][0] = v0.x; w[u][1] = v0.y; w[u][2] = v1.x; w[u][3] = v1.y;
+      } else {
+        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < QT; ++t)
+#pragma unroll
+        for (int u = 0; u < JT; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], w[u][s], acc[t][u], 0, 0, 0);
+  } else if constexpr (sizeof(TW) == 4) {  // FP32 operands, FP32 accumulation
+    float w[JT][4];
+#pragma unroll
+    for (int u = 0; u < JT; ++u) {
+      const int j = 16 * u + qi;
+      if (j < n) {
+        const float4 v = *reinterpret_cast<const float4*>(W + (size_t)j * w_ld + kk);
+        w[u][0] = v.x; w[u][1] = v.y; w[u][2] = v.z; w[u][3] = v.w;
+      } else {
+        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < QT; ++t)
+#pragma unroll
+        for (int u = 0; u < JT; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[t][s], w[u][s], acc[t][u],
+                                                           0, 0, 0);
+  } else {  // BF16 operands, FP32 accumulation
+    shortx4 w[JT];
+#pragma unroll
+    for (int u = 0; u < JT; ++u) {
+      const int j = 16 * u + qi;
+      if (j < n) {
+        const uint2 v = *reinterpret_cast<const uint2*>(W + (size_t)j * w_ld + kk);
+        w[u][0] = (short)(v.x & 0xffff); w[u][1] = (short)(v.x >> 16);
+        w[u][2] = (short)(v.y & 0xffff); w[u][3] = (short)(v.y >> 16);
+      } else {
+        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      shortx4 av;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) av[s] = (short)rbk::f32_to_bf16_rne((float)a[t][s]);
+#pragma unroll
+      for (int u = 0; u < JT; ++u)
+        acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, w[u], acc[t][u], 0, 0, 0);
+    }
+  }
+}
+
+// WSPLIT = true: the block's 4 waves split the DOF range of one query tile and are
+// reduced through LDS (small batches).  WSPLIT = false: the 4 waves own 4 query tiles
+// over the same DOF range (large batches).
+template <typename TW, int QT, int JT, bool WSPLIT>
+__global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, int64_t r_ld,
+                                                 const TW* __restrict__ W, int64_t w_ld, int n,
+                                                 int B, int kend, int steps,
+                                                 const int* __restrict__ active,
+                                                 typename ProjTraits<TW>::Acc* __restrict__ part) {
+  using Acc = typename ProjTraits<TW>::Acc;
+  using Vec = typename ProjTraits<TW>::Vec;
+  constexpr int NJ = 16 * JT;
+  constexpr int QW = 16 * QT;  // queries per wave tile
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int chunk = blockIdx.x;
+  int q_base, k_begin, k_stop;
+  if (WSPLIT) {
+    q_base = blockIdx.y * QW;
+    k_begin = (chunk * 4 + wave) * steps * 16;
+  } else {
+    q_base = (blockIdx.y * 4 + wave) * QW;
+    k_begin = chunk * steps * 16;
+  }
+  k_stop = k_begin + steps * 16;
+  if (k_stop > kend) k_stop = kend;
+  Vec acc[QT][JT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t)
+#pragma unroll
+    for (int u = 0; u < JT; ++u) acc[t][u] = Vec{0, 0, 0, 0};
+  for (int k0 = k_begin; k0 < k_stop; k0 += 16)
+    proj_step<TW, QT, JT>(R, r_ld, W, w_ld, n, q_base, B, active, k0, acc);
+
+  const int qi = lane & 15, kg = lane >> 4;
+  if (!WSPLIT) {
+#pragma unroll
+    for (int t = 0; t < QT; ++t)
+#pragma unroll
+      for (int u = 0; u < JT; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = q_base + 16 * t + acc_row<TW>(kg, i);
+          const int j = 16 * u + qi;
+          if (q < B) part[((size_t)chunk * B + q) * NJ + j] = acc[t][u][i];
+        }
+  } else {
+    __shared__ Acc sh[4][QW][NJ];
+#pragma unroll
+    for (int t = 0; t < QT; ++t)
+#pragma unroll
+      for (int u = 0; u < JT; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          sh[wave][16 * t + acc_row<TW>(kg, i)][16 * u + qi] = acc[t][u][i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < QW * NJ; e += 256) {
+      const int ql = e / NJ, j = e % NJ;
+      const int q = q_base + ql;
+      const Acc s = (sh[0][ql][j] + sh[1][ql][j]) + (sh[2][ql][j] + sh[3][ql][j]);
+      if (q < B) part[((size_t)chunk * B + q) * NJ + j] = s;
+    }
+  }
+}
+
+ProjPlan plan_projection(int N, int B, int n, int target_blocks) {
+  ProjPlan p;
+  p.jt = (n + 15) / 16;
+  if (p.jt < 1) p.jt = 1;
+  p.kend = ((N + 15) / 16) * 16;
+  const int nsteps = p.kend / 16;
+  if (B <= 16) {
+    p.wsplit = true;
+    p.qt = 1;
+    p.qgroups = (B + 15) / 16;
+    // steps per wave so that chunks*qgroups ~ target
+    int chunks_wanted = target_blocks / p.qgroups;
+    if (chunks_wanted < 1) chunks_wanted = 1;
+    p.steps = (nsteps + 4 * chunks_wanted - 1) / (4 * chunks_wanted);
+    if (p.steps < 1) p.steps = 1;
+    p.chunks = (nsteps + 4 * p.steps - 1) / (4 * p.steps);
+  } else {
+    p.wsplit = false;
+    p.qt = B <= 64 ? 1 : (B <= 128 ? 2 : 4);
+    if (p.jt > 3 && p.qt > 2) p.qt = 2;  // register budget
+    p.qgroups = (B + 64 * p.qt - 1) / (64 * p.qt);
+    int chunks_wanted = target_blocks / p.qgroups;
+    if (chunks_wanted < 1) chunks_wanted = 1;
+    p.steps = (nsteps + chunks_wanted - 1) / chunks_wanted;
+    if (p.steps < 1) p.steps = 1;
+    p.chunks = (nsteps + p.steps - 1) / p.steps;
+  }
+  p.nj = 16 * p.jt;
+  return p;
+}
+
+template <typename TW, int QT, int JT>
+static void launch_proj_t(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
+                          int64_t w_ld, int n, int B, const int* active, void* part,
+                          hipStream_t s) {
+  using Acc = typename ProjTraits<TW>::Acc;
+  const dim3 grid(pl.chunks, pl.qgroups);
+  if (pl.wsplit)
+    hipLaunchKernelGGL((k_project<TW, QT, JT, true>), grid, dim3(256), 0, s, R, r_ld, W, w_ld, n,
+                       B, pl.kend, pl.steps, active, (Acc*)part);
+  else
+    hipLaunchKernelGGL((k_project<TW, QT, JT, false>), grid, dim3(256), 0, s, R, r_ld, W, w_ld, n,
+                       B, pl.kend, pl.steps, active, (Acc*)part);
+}
+
+template <typename TW, int QT>
+static void launch_proj_q(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
+                          int64_t w_ld, int n, int B, const int* active, void* part,
+                          hipStream_t s) {
+  switch (pl.jt) {
+    case 1: launch_proj_t<TW, QT, 1>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+    case 2: launch_proj_t<TW, QT, 2>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+    case 3: launch_proj_t<TW, QT, 3>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+    case 4: launch_proj_t<TW, QT, 4>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+    default: launch_proj_t<TW, QT, 5>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+  }
+}
+
+void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
+                       const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
+                       hipStream_t s) {
+  if (prec == RB_PREC_FP64) {
+    const double* w = (const double*)W;
+    switch (pl.qt) {
+      case 1: launch_proj_q<double, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 2: launch_proj_q<double, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      default: launch_proj_q<double, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+    }
+  } else if (prec == RB_PREC_FP32) {
+    const float* w = (const float*)W;
+    switch (pl.qt) {
+      case 1: launch_proj_q<float, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 2: launch_proj_q<float, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      default: launch_proj_q<float, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+    }
+  } else {
+    const uint16_t* w = (const uint16_t*)W;
+    switch (pl.qt) {
+      case 1: launch_proj_q<uint16_t, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 2: launch_proj_q<uint16_t, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      default: launch_proj_q<uint16_t, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+    }
+  }
+}
+
+// ---- prolongation -----------------------------------------------------------------
+// out_b[pos] (=|+=) sum_{j<n} W[j][pos] e_b[j] for pos in [lo, hi); QG queries per
+// block (blockIdx.x = query group, blockIdx.y = node chunk).  e rows are zero beyond a
+// query's own basis size.
+template <typename TW, typename TA, typename TO, int QG, bool ADD>
+__global__ __launch_bounds__(256) void k_prolong(const TW* __restrict__ W, int64_t w_ld, int n,
+                                                 const TA* __restrict__ e, int e_ld, int B,
+                                                 const int* __restrict__ active,
+                                                 TO* __restrict__ out, int64_t o_ld, int lo,
+                                                 int hi) {
+  const int q0 = blockIdx.x * QG;
+  const int pos = lo + blockIdx.y * 256 + threadIdx.x;
+  if (pos >= hi) return;
+  TA acc[QG];
+#pragma unroll
+  for (int q = 0; q < QG; ++q) acc[q] = TA(0);
+  for (int j = 0; j < n; ++j) {
+    TA w;
+    if constexpr (sizeof(TW) == 2)
+      w = (TA)rbk::bf16_to_f32(W[(size_t)j * w_ld + pos]);
+    else
+      w = (TA)W[(size_t)j * w_ld + pos];
+#pragma unroll
+    for (int q = 0; q < QG; ++q) acc[q] += w * e[(size_t)(q0 + q) * e_ld + j];
+  }
+#pragma unroll
+  for (int q = 0; q < QG; ++q) {
+    const int b = q0 + q;
+    if (b < B && active[b]) {
+      TO* o = out + (size_t)b * o_ld + pos;
+      if (ADD)
+        *o += (TO)acc[q];
+      else
+        *o = (TO)acc[q];
+    }
+  }
+}
+
+template <typename TW, typename TA, typename TO, bool ADD>
+static void launch_prolong_t(const TW* W, int64_t w_ld, int n, const TA* e, int e_ld, int B,
+                             const int* active, TO* out, int64_t o_ld, int lo, int hi,
+                             hipStream_t s) {
+  constexpr int QG = 8;
+  const dim3 grid((B + QG - 1) / QG, (hi - lo + 255) / 256);
+  hipLaunchKernelGGL((k_prolong<TW, TA, TO, QG, ADD>), grid, dim3(256), 0, s, W, w_ld, n, e, e_ld,
+                     B, active, out, o_ld, lo, hi);
+}
+
+void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const double* e64,
+                    const float* e32, int e_ld, int B, const int* active, void* out,
+                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s) {
+  if (hi <= lo || n == 0) return;
+  if (prec == RB_PREC_FP64) {
+    RB_REQUIRE(out_is_double, RB_EINVAL, "FP64 prolongation needs a double output");
+    if (add)
+      launch_prolong_t<double, double, double, true>((const double*)W, w_ld, n, e64, e_ld, B,
+                                                     active, (double*)out, o_ld, lo, hi, s);
+    else
+      launch_prolong_t<double, double, double, false>((const double*)W, w_ld, n, e64, e_ld, B,
+                                                      active, (double*)out, o_ld, lo, hi, s);
+    return;
+  }
+#define PR(TW)                                                                                   \
+  if (out_is_double) {                                                                           \
+    if (add)                                                                                     \
+      launch_prolong_t<TW, float, double, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,     \
+                                                (double*)out, o_ld, lo, hi, s);                  \
+    else                                                                                         \
+      launch_prolong_t<TW, float, double, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,    \
+                                                 (double*)out, o_ld, lo, hi, s);                 \
+  } else {                                                                                       \
+    if (add)                                                                                     \
+      launch_prolong_t<TW, float, float, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,      \
+                                               (float*)out, o_ld, lo, hi, s);                    \
+    else                                                                                         \
+      launch_prolong_t<TW, float, float, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,     \
+                                                (float*)out, o_ld, lo, hi, s);                   \
+  }
+  if (prec == RB_PREC_FP32) {
+    PR(float)
+  } else {
+    PR(uint16_t)
+  }
+#undef PR
+}
+
+// ---- reduced assembly + Cholesky (one wavefront per query) --------------------------
+// Right-looking unpivoted Cholesky of the leading nb x nb block of A (LDS, lower part
+// overwritten by L) by one wavefront.  Returns true on a non-positive (or NaN) pivot.
+template <int NMAX>
+__device__ bool chol_lds(double (*A)[NMAX + 1], int nb, int lane, int* bad) {
+  if (lane == 0) *bad = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = A[j][j];
+    if (!(d > 0.0)) {
+      if (lane == 0) *bad = 1;
+      break;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    if (lane == 0) A[j][j] = ljj;
+    for (int i = j + 1 + lane; i < nb; i += 64) A[i][j] /= ljj;
+    __syncthreads();
+    // trailing update of the lower triangle: A[i][k] -= L[i][j] L[k][j], j < k <= i
+    const int m = nb - j - 1;
+    for (int e = lane; e < m * m; e += 64) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) A[i][k] -= A[i][j] * A[k][j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return *bad != 0;
+}
+
+// A = sum_q theta_bq A_{N,q} restricted to the leading n_b x n_b block.  L is written
+// row-major [b][n][n] with zeros above the diagonal and outside n_b.  status[b] =
+// RB_ENOTSPD on a non-positive (or NaN) pivot.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_cholesky(const double* __restrict__ AN, int n, int Q,
+                                                 const double* __restrict__ theta,
+                                                 const int* __restrict__ n_use,
+                                                 double* __restrict__ L, int* __restrict__ status) {
+  __shared__ double A[NMAX][NMAX + 1];
+  __shared__ int bad;
+  const int b = blockIdx.x;
+  const int nb = n_use ? n_use[b] : n;
+  const double* th = theta + (size_t)b * Q;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < nb * nb; e += 64) {
+    const int i = e / nb, j = e % nb;
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q) s += th[q] * AN[((size_t)q * n + i) * n + j];
+    A[i][j] = s;
+  }
+  __syncthreads();
+  const bool fail = chol_lds<NMAX>(A, nb, lane, &bad);
+  double* Lb = L + (size_t)b * n * n;
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    Lb[e] = (i < nb && j <= i && !fail) ? A[i][j] : 0.0;
+  }
+  if (lane == 0) status[b] = fail ? (int)RB_ENOTSPD : (int)RB_OK;
+}
+
+// Greedy sweep, steps 5-6 of Alg. 1/4: for candidate m, a(mu_m) = A_N(mu_m)^-1 f_N(mu_m)
+// (assembly by eq. 12b, Cholesky, two triangular solves) and the L1 indicator
+// sum_n |a_n|.  a rows have stride a_ld; status[m] = RB_ENOTSPD on failure (l1 = NaN).
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_sweep_coeffs(const double* __restrict__ AN,
+                                                     const double* __restrict__ fN, int n, int Q,
+                                                     int R, const double* __restrict__ theta,
+                                                     const double* __restrict__ phi,
+                                                     double* __restrict__ a, int a_ld,
+                                                     double* __restrict__ l1,
+                                                     int* __restrict__ status) {
+  __shared__ double A[NMAX][NMAX + 1];
+  __shared__ double u[NMAX];
+  __shared__ int bad;
+  const int m = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* th = theta + (size_t)m * Q;
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q) s += th[q] * AN[((size_t)q * n + i) * n + j];
+    A[i][j] = s;
+  }
+  for (int j = lane; j < n; j += 64) {
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) s += (phi ? phi[(size_t)m * R + r] : 1.0) * fN[(size_t)r * n + j];
+    u[j] = s;
+  }
+  __syncthreads();
+  const bool fail = chol_lds<NMAX>(A, n, lane, &bad);
+  if (!fail) {
+    for (int j = 0; j < n; ++j) {  // L v = f_N
+      const double vj = u[j] / A[j][j];
+      __syncthreads();
+      if (lane == 0) u[j] = vj;
+      for (int i = j + 1 + lane; i < n; i += 64) u[i] -= A[i][j] * vj;
+      __syncthreads();
+    }
+    for (int j = n - 1; j >= 0; --j) {  // L^T a = v
+      const double aj = u[j] / A[j][j];
+      __syncthreads();
+      if (lane == 0) u[j] = aj;
+      for (int i = lane; i < j; i += 64) u[i] -= A[j][i] * aj;
+      __syncthreads();
+    }
+  }
+  double s1 = 0.0;
+  for (int j = lane; j < a_ld; j += 64) {
+    const double v = (j < n && !fail) ? u[j] : 0.0;
+    a[(size_t)m * a_ld + j] = v;
+    s1 += fabs(v);
+  }
+  s1 = rbk::wave_sum(s1);
+  if (lane == 0) {
+    l1[m] = fail ? __builtin_nan("") : s1;
+    status[m] = fail ? (int)RB_ENOTSPD : (int)RB_OK;
+  }
+}
+
+void launch_sweep_coeffs(const double* AN, const double* fN, int n, int Q, int R, int M,
+                         const double* theta, const double* phi, double* a, int a_ld, double* l1,
+                         int* status, hipStream_t s) {
+  RB_REQUIRE(n >= 1 && n <= 80, RB_EUNSUPPORTED, "reduced basis size must be 1..80");
+  if (n <= 32)
+    hipLaunchKernelGGL(k_sweep_coeffs<32>, dim3(M), dim3(64), 0, s, AN, fN, n, Q, R, theta, phi, a,
+                       a_ld, l1, status);
+  else
+    hipLaunchKernelGGL(k_sweep_coeffs<80>, dim3(M), dim3(64), 0, s, AN, fN, n, Q, R, theta, phi, a,
+                       a_ld, l1, status);
+}
+
+// Masked argmax over M values (Alg. 1/4 step 6): largest value among the entries with
+// excluded[m] == 0; ties go to the lowest index.  out_val/out_idx; out_idx = -1 if every
+// entry is excluded; nan_flag = 1 if a non-excluded entry is NaN.
+__global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ v,
+                                                const int* __restrict__ excluded, int M,
+                                                double* __restrict__ out_val,
+                                                int* __restrict__ out_idx,
+                                                int* __restrict__ nan_flag) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  __shared__ int snan;
+  if (threadIdx.x == 0) snan = 0;
+  __syncthreads();
+  double best = -__builtin_inf();
+  int bi = -1;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    if (excluded[m]) continue;
+    const double x = v[m];
+    if (!(x == x)) {
+      snan = 1;
+      continue;
+    }
+    if (bi < 0 || x > best) {  // strictly greater keeps the lowest index of a tie
+      best = x;
+      bi = m;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double ov = sv[threadIdx.x + off];
+      const int oi = si[threadIdx.x + off];
+      const int ci = si[threadIdx.x];
+      if (oi >= 0 && (ci < 0 || ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < ci))) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out_val = sv[0];
+    *out_idx = si[0];
+    *nan_flag = snan;
+  }
+}
+void launch_argmax(const double* v, const int* excluded, int M, double* out_val, int* out_idx,
+                   int* nan_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, s, v, excluded, M, out_val, out_idx,
+                     nan_flag);
+}
+
+// partial sums of a_b . c_b over chunks of 256*per_thread entries: part[b][chunk]
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
+                                             const double* __restrict__ c, int64_t ld, int N,
+                                             double* __restrict__ part, int per_thread) {
+  __shared__ double sh[4];
+  const int b = blockIdx.y;
+  double acc = 0.0;
+  const int base = blockIdx.x * 256 * per_thread;
+  for (int t = 0; t < per_thread; ++t) {
+    const int i = base + t * 256 + threadIdx.x;
+    if (i >= N) break;
+    acc += a[(size_t)b * ld + i] * c[(size_t)b * ld + i];
+  }
+  const double s = rbk::block_sum_256(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+int launch_dot(const double* a, const double* c, int64_t ld, int N, int B, double* part,
+               int per_thread, hipStream_t s) {
+  const int chunks = (N + 256 * per_thread - 1) / (256 * per_thread);
+  hipLaunchKernelGGL(k_dot, dim3(chunks, B), dim3(256), 0, s, a, c, ld, N, part, per_thread);
+  return chunks;
+}
+
+// dst[i] = alpha * src[i]
+__global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, int64_t n,
+                        double alpha) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = alpha * src[i];
+}
+void launch_scale(double* dst, const double* src, int64_t n, double alpha, hipStream_t s) {
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_scale, dim3(bx), dim3(256), 0, s, dst, src, n, alpha);
+}
+
+void launch_cholesky(const double* AN, int n, int Q, int B, const double* theta, const int* n_use,
+                     double* L, int* status, hipStream_t s) {
+  RB_REQUIRE(n <= 80, RB_EUNSUPPORTED, "reduced basis larger than 80");
+  if (n <= 32)
+    hipLaunchKernelGGL(k_cholesky<32>, dim3(B), dim3(64), 0, s, AN, n, Q, theta, n_use, L, status);
+  else
+    hipLaunchKernelGGL(k_cholesky<80>, dim3(B), dim3(64), 0, s, AN, n, Q, theta, n_use, L, status);
+}
+
+// ---- finalise projection partials + reduced solve --------------------------------------
+// t_b[j] = sum over chunks (fixed order, FP64), then e_b = L_b^-T L_b^-1 t_b.
+// One block of 256 threads per query: the 4 waves sum interleaved chunks, then wave 0
+// solves.  e64 / e32 rows have stride e_ld and are zero for j >= n_b.
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_reduce_solve(const Acc* __restrict__ part, int chunks,
+                                                      int B, int nj, int n,
+                                                      const int* __restrict__ n_use,
+                                                      const double* __restrict__ L,
+                                                      const int* __restrict__ active,
+                                                      double* __restrict__ t_out,
+                                                      double* __restrict__ e64,
+                                                      float* __restrict__ e32, int e_ld,
+                                                      int solve) {
+  __shared__ double sh[4][128];
+  __shared__ double u[128];
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int nb = n_use ? n_use[b] : n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = lane; j < nj; j += 64) {
+    double s = 0.0;
+    for (int c = wave; c < chunks; c += 4) s += (double)part[((size_t)c * B + b) * nj + j];
+    sh[wave][j] = s;
+  }
+  __syncthreads();
+  // wave 0 does the solve; the other waves only take part in the barriers
+  const bool w0 = wave == 0;
+  if (w0)
+    for (int j = lane; j < nj; j += 64) {
+      const double t = (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
+      u[j] = j < nb ? t : 0.0;
+      if (t_out && j < n) t_out[(size_t)b * n + j] = t;
+    }
+  __syncthreads();
+  if (solve) {
+    const double* Lb = L + (size_t)b * n * n;
+    // forward: L v = t (column oriented)
+    for (int j = 0; j < nb; ++j) {
+      const double vj = u[j] / Lb[(size_t)j * n + j];
+      __syncthreads();
+      if (w0) {
+        if (lane == 0) u[j] = vj;
+        for (int i = j + 1 + lane; i < nb; i += 64) u[i] -= Lb[(size_t)i * n + j] * vj;
+      }
+      __syncthreads();
+    }
+    // backward: L^T e = v
+    for (int j = nb - 1; j >= 0; --j) {
+      const double ej = u[j] / Lb[(size_t)j * n + j];
+      __syncthreads();
+      if (w0) {
+        if (lane == 0) u[j] = ej;
+        for (int i = lane; i < j; i += 64) u[i] -= Lb[(size_t)j * n + i] * ej;
+      }
+      __syncthreads();
+    }
+  }
+  if (w0)
+    for (int j = lane; j < e_ld; j += 64) {
+      const double v = (j < nb) ? u[j] : 0.0;
+      if (e64) e64[(size_t)b * e_ld + j] = v;
+      if (e32) e32[(size_t)b * e_ld + j] = (float)v;
+    }
+}
+
+void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, int nj, int n,
+                         const int* n_use, const double* L, const int* active, double* t_out,
+                         double* e64, float* e32, int e_ld, bool solve, hipStream_t s) {
+  RB_REQUIRE(nj <= 128 && e_ld <= 128, RB_EUNSUPPORTED, "basis too large for reduce_solve");
+  if (fp64_part)
+    hipLaunchKernelGGL(k_reduce_solve<double>, dim3(B), dim3(256), 0, s, (const double*)part,
+                       chunks, B, nj, n, n_use, L, active, t_out, e64, e32, e_ld, solve ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_reduce_solve<float>, dim3(B), dim3(256), 0, s, (const float*)part,
+                       chunks, B, nj, n, n_use, L, active, t_out, e64, e32, e_ld, solve ? 1 : 0);
+}
+
+// ---- CG scalars (Alg. 3) ----------------------------------------------------------------
+__device__ __forceinline__ double sum_parts(const double* p, int cnt, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += 256) s += p[i];
+  return rbk::block_sum_256(s, sh);
+}
+
+// step 5: alpha = rho / p^T A p (breakdown if either is not positive)
+__global__ __launch_bounds__(256) void k_fin_alpha(const double* __restrict__ part, int stride,
+                                                   int cnt, QState q) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (!q.active[b]) return;
+  const double pAp = sum_parts(part + (size_t)b * stride, cnt, sh);
+  if (threadIdx.x == 0) {
+    const double rho = q.rho[b];
+    if (!(pAp > 0.0) || !(rho > 0.0)) {
+      q.status[b] = RB_EBREAKDOWN;
+      q.active[b] = 0;
+      q.alpha[b] = 0.0;
+    } else {
+      q.alpha[b] = rho / pAp;
+    }
+  }
+}
+
+// step 8: recursive residual test; flags the query for the true-residual check
+__global__ __launch_bounds__(256) void k_fin_rr(const double* __restrict__ part, int stride,
+                                                int cnt, QState q, double rtol, int maxit,
+                                                int fixed) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (!q.active[b]) return;
+  const double rr = sum_parts(part + (size_t)b * stride, cnt, sh);
+  if (threadIdx.x == 0) {
+    const int it = q.iters[b] + 1;
+    q.iters[b] = it;
+    const double rel = sqrt(rr / q.fnorm2[b]);
+    q.rel_rec[b] = rel;
+    if (fixed) return;
+    if (rel <= rtol) {
+      q.flag[b] = 1;
+    } else if (!(rel == rel)) {
+      q.status[b] = RB_EBREAKDOWN;
+      q.active[b] = 0;
+    } else if (it >= maxit) {
+      q.status[b] = RB_ENOCONV;
+      q.active[b] = 0;
+    }
+  }
+}
+
+// true residual (eq. relerr): retire on success, else restart with the replaced residual
+__global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ part, int stride,
+                                                  int cnt, QState q, double rtol, int maxit) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (!q.active[b] || !q.flag[b]) return;
+  const double rr = sum_parts(part + (size_t)b * stride, cnt, sh);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(rr / q.fnorm2[b]);
+    q.rel_true[b] = rel;
+    q.flag[b] = 0;
+    if (rel <= rtol) {
+      q.active[b] = 0;
+      q.status[b] = RB_OK;
+    } else if (q.iters[b] >= maxit) {
+      q.active[b] = 0;
+      q.status[b] = RB_ENOCONV;
+    } else {
+      q.restart[b] = 1;
+    }
+  }
+}
+
+// steps 9-10: rho_new = y^T r (red + black partials); beta (literal or flexible)
+__global__ __launch_bounds__(256) void k_fin_beta(const double* __restrict__ pr, int cr,
+                                                  const double* __restrict__ pb, int cb,
+                                                  const double* __restrict__ fr,
+                                                  const double* __restrict__ fb, QState q,
+                                                  int flexible) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (!q.active[b]) return;
+  const double s0 = sum_parts(pr + (size_t)b * cr, cr, sh);
+  const double s1 = pb ? sum_parts(pb + (size_t)b * cb, cb, sh) : 0.0;
+  double x0 = 0.0, x1 = 0.0;
+  if (flexible && fr) {
+    x0 = sum_parts(fr + (size_t)b * cr, cr, sh);
+    x1 = fb ? sum_parts(fb + (size_t)b * cb, cb, sh) : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    const double rho_new = s0 + s1;
+    const double rho_old = q.rho[b];
+    double beta;
+    if (q.restart[b]) {
+      beta = 0.0;
+      q.restart[b] = 0;
+    } else if (flexible) {
+      beta = (rho_new - (x0 + x1)) / rho_old;
+    } else {
+      beta = rho_new / rho_old;
+    }
+    q.beta[b] = beta;
+    q.rho[b] = rho_new;
+  }
+}
+
+// ||f||^2 per query (RBCG init) or ||r||^2 (RBI loop) from partials
+__global__ __launch_bounds__(256) void k_fin_sum(const double* __restrict__ part, int stride,
+                                                 int cnt, double* __restrict__ out,
+                                                 const int* __restrict__ active) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const double s = sum_parts(part + (size_t)b * stride, cnt, sh);
+  if (threadIdx.x == 0) out[b] = s;
+}
+
+void launch_fin_alpha(const double* part, int stride, int cnt, const QState& q, int B,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(B), dim3(256), 0, s, part, stride, cnt, q);
+}
+void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
+                   int maxit, bool fixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_rr, dim3(B), dim3(256), 0, s, part, stride, cnt, q, rtol, maxit,
+                     fixed ? 1 : 0);
+}
+void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
+                     int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_true, dim3(B), dim3(256), 0, s, part, stride, cnt, q, rtol, maxit);
+}
+void launch_fin_beta(const double* pr, int cr, const double* pb, int cb, const double* fr,
+                     const double* fb, const QState& q, int B, bool flexible, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(B), dim3(256), 0, s, pr, cr, pb, cb, fr, fb, q,
+                     flexible ? 1 : 0);
+}
+void launch_fin_sum(const double* part, int stride, int cnt, double* out, const int* active,
+                    int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_sum, dim3(B), dim3(256), 0, s, part, stride, cnt, out, active);
+}
+
+// ---- small helpers ---------------------------------------------------------------------
+// dst[b][pos] = value for pos < n (fill kernel; graph-safe replacement for memset)
+template <typename T>
+__global__ void k_fill(T* __restrict__ dst, int64_t ld, int64_t n, T value) {
+  const int b = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[(size_t)b * ld + i] = value;
+}
+template <typename T>
+void launch_fill(T* dst, int64_t ld, int64_t n, int B, T value, hipStream_t s) {
+  int bx = (int)((n + 255) / 256);
+  if (bx > 2048) bx = 2048;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_fill<T>, dim3(bx, B), dim3(256), 0, s, dst, ld, n, value);
+}
+template void launch_fill<double>(double*, int64_t, int64_t, int, double, hipStream_t);
+template void launch_fill<float>(float*, int64_t, int64_t, int, float, hipStream_t);
+template void launch_fill<int>(int*, int64_t, int64_t, int, int, hipStream_t);
+
+// r_b = phi_b * f[pos] (shared term) and partial ||r_b||^2
+__global__ __launch_bounds__(256) void k_init_rhs(const double* __restrict__ f, int64_t f_ld,
+                                                  const double* __restrict__ scale, int N,
+                                                  double* __restrict__ r, int64_t ld,
+                                                  double* __restrict__ part, int per_thread) {
+  __shared__ double sh[4];
+  const int b = blockIdx.y;
+  const double sc = scale[b];
+  const double* fb = f + (size_t)b * f_ld;
+  double acc = 0.0;
+  const int base = blockIdx.x * 256 * per_thread;
+  for (int t = 0; t < per_thread; ++t) {
+    const int pos = base + t * 256 + threadIdx.x;
+    if (pos >= N) break;
+    const double v = sc * fb[pos];
+    r[(size_t)b * ld + pos] = v;
+    acc += v * v;
+  }
+  const double s = rbk::block_sum_256(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+void launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
+                     int64_t ld, int B, double* part, int per_thread, hipStream_t s) {
+  const int chunks = (N + 256 * per_thread - 1) / (256 * per_thread);
+  hipLaunchKernelGGL(k_init_rhs, dim3(chunks, B), dim3(256), 0, s, f, f_ld, scale, N, r, ld, part,
+                     per_thread);
+}
+
+// precision shadows of the basis (round to nearest even)
+__global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void k_cast_bf16(const double* __restrict__ src, uint16_t* __restrict__ dst,
+                            int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = rbk::f32_to_bf16_rne((float)src[i]);
+}
+__global__ void k_widen(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+void launch_widen(const float* src, double* dst, int64_t n, hipStream_t s) {
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_widen, dim3(bx), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_cast(const double* src, void* dst, int64_t n, rb_prec prec, hipStream_t s) {
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  if (prec == RB_PREC_FP32)
+    hipLaunchKernelGGL(k_cast_f32, dim3(bx), dim3(256), 0, s, src, (float*)dst, n);
+  else
+    hipLaunchKernelGGL(k_cast_bf16, dim3(bx), dim3(256), 0, s, src, (uint16_t*)dst, n);
+}
+
+}  // namespace rb

@@ -1,0 +1,122 @@
+// Internal types of librb: context, problem, basis, launch declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rb.h"
+#include "common.h"
+
+namespace rb {
+
+// ---- error handling --------------------------------------------------------
+void set_error(const std::string& msg);
+struct Error {
+  rb_status code;
+  std::string msg;
+};
+#define RB_HIP(call)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::rb::Error{RB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define RB_REQUIRE(cond, code, msg)                      \
+  do {                                                   \
+    if (!(cond)) throw ::rb::Error{(code), (msg)};       \
+  } while (0)
+
+// Device allocation owned by a C++ object; throws RB_ENOMEM on failure.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n);
+  void release();
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace rb
+
+// ---- stencil geometry (device-side view) --------------------------------------
+// Vectors of a stencil problem are stored in red-black order: position g < NR holds
+// the red node with lexicographic index L = 2g, position g >= NR the black node
+// L = 2(g - NR) + 1.  With n_x (and n_y in 3D) odd, the parity of L equals the
+// colour (i + j + k) mod 2.
+struct StencilGeom {
+  int dim;
+  int nx, ny, nz;
+  int bx, by, bz;
+  int Q;
+  int N;      // nodes
+  int NR;     // red nodes = (N + 1) / 2
+  int nxy;    // nx * ny
+  rbk::FastDiv div_nx, div_nxy;
+  // per-axis node tables (device): packed state | lo-face block << 8 | hi-face block << 16
+  const uint32_t* tab[3];
+  // coefficient-table layout per query (doubles)
+  int ct_off[3];  // offset of the table of axis a
+  int ct_s1[3];   // size of the first tangential state dimension (or 1)
+  int ct_s2[3];   // size of the second tangential state dimension (or 1)
+  int ct_size;    // doubles per query (padded)
+};
+
+struct rb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipDeviceProp_t prop{};
+};
+
+struct rb_problem {
+  rb_ctx* ctx = nullptr;
+  rb_stencil_desc desc{};
+  StencilGeom g{};
+  int64_t N = 0;
+  int64_t ld = 0;  // padded per-vector stride (elements)
+  int R = 1;
+  rb::DevBuf tabs;       // per-axis node tables
+  rb::DevBuf perm;       // int32 [N]: storage position -> lexicographic index
+  rb::DevBuf f;          // double [R][ld], storage (red-black) order
+  std::vector<double> f_host;  // [R][N] natural order
+};
+
+struct rb_basis {
+  rb_ctx* ctx = nullptr;
+  const rb_problem* prob = nullptr;
+  int n = 0;
+  int64_t ld = 0;
+  rb::DevBuf W64;   // double [n][ld] storage order
+  rb::DevBuf W32;   // float  [n][ld] shadow (lazily)
+  rb::DevBuf W16;   // bf16   [n][ld] shadow (lazily)
+  rb::DevBuf AN;    // double [Q][n][n]
+  rb::DevBuf fN;    // double [R][n]
+  std::vector<double> AN_host, fN_host;
+  std::vector<int64_t> picks;
+  const void* shadow(rb_prec prec);
+};
+
+namespace rb {
+
+// ---- launchers (kernels in *.hip) ---------------------------------------------
+// problem setup
+void launch_coef_tables(const StencilGeom& g, int B, const double* theta, const int* qidx,
+                        double* coef, hipStream_t s);
+void launch_to_storage(const rb_problem& p, int B, const double* nat, int64_t nat_ld,
+                       double* sto, int64_t sto_ld, hipStream_t s);
+void launch_from_storage(const rb_problem& p, int B, const double* sto, int64_t sto_ld,
+                         double* nat, int64_t nat_ld, hipStream_t s);
+
+}  // namespace rb

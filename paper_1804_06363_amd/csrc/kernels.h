@@ -1,0 +1,99 @@
+// Launch declarations of the HIP kernels (stencil.hip, dense.hip, mlp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace rb {
+
+// Per-query CG state on the device (each array has B entries).
+struct QState {
+  double* fnorm2;    // ||f_b||^2
+  double* rho;       // y_k^T r_k
+  double* alpha;
+  double* beta;
+  double* rel_rec;   // recursive relative residual
+  double* rel_true;  // true relative residual (last check)
+  double* scalar;    // scratch per query (e.g. ||r||^2 of RBI)
+  int* active;
+  int* status;
+  int* iters;
+  int* flag;     // true-residual check pending
+  int* restart;  // next beta = 0 (p = y)
+};
+
+struct ProjPlan {
+  bool wsplit = false;
+  int qt = 1, jt = 1, nj = 16;
+  int qgroups = 1, chunks = 1, steps = 1;
+  int kend = 0;
+};
+
+// stencil.hip
+int stencil_chunks(int count, int per_thread);
+void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
+                  double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                  const int* flag, double* part, int per_thread, hipStream_t s);
+template <typename TY>
+void launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
+                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
+                   const int* active, double* part, int per_thread, hipStream_t s);
+void launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
+                   double* x, const double* r_in, double* r_out, const double* alpha,
+                   const int* active, double* part, int per_thread, hipStream_t s);
+template <typename TY>
+void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
+                     int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                     double* part1, int per_thread, hipStream_t s);
+template <typename TY>
+void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
+                   int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
+                   const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                   double* part1, int per_thread, hipStream_t s);
+
+// dense.hip
+ProjPlan plan_projection(int N, int B, int n, int target_blocks);
+void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
+                       const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
+                       hipStream_t s);
+void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const double* e64,
+                    const float* e32, int e_ld, int B, const int* active, void* out,
+                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s);
+void launch_cholesky(const double* AN, int n, int Q, int B, const double* theta, const int* n_use,
+                     double* L, int* status, hipStream_t s);
+void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, int nj, int n,
+                         const int* n_use, const double* L, const int* active, double* t_out,
+                         double* e64, float* e32, int e_ld, bool solve, hipStream_t s);
+void launch_fin_alpha(const double* part, int stride, int cnt, const QState& q, int B,
+                      hipStream_t s);
+void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
+                   int maxit, bool fixed, hipStream_t s);
+void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
+                     int maxit, hipStream_t s);
+// Partial-sum arrays are [B][count] (the stride of each array equals its count).
+void launch_fin_beta(const double* pr, int cr, const double* pb, int cb, const double* fr,
+                     const double* fb, const QState& q, int B, bool flexible, hipStream_t s);
+void launch_fin_sum(const double* part, int stride, int cnt, double* out, const int* active,
+                    int B, hipStream_t s);
+template <typename T>
+void launch_fill(T* dst, int64_t ld, int64_t n, int B, T value, hipStream_t s);
+void launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
+                     int64_t ld, int B, double* part, int per_thread, hipStream_t s);
+void launch_cast(const double* src, void* dst, int64_t n, rb_prec prec, hipStream_t s);
+void launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
+void compute_reduced(rb_basis* bs, int j0);
+void launch_sweep_coeffs(const double* AN, const double* fN, int n, int Q, int R, int M,
+                         const double* theta, const double* phi, double* a, int a_ld, double* l1,
+                         int* status, hipStream_t s);
+void launch_argmax(const double* v, const int* excluded, int M, double* out_val, int* out_idx,
+                   int* nan_flag, hipStream_t s);
+// returns the number of chunks (partials per row)
+int launch_dot(const double* a, const double* c, int64_t ld, int N, int B, double* part,
+               int per_thread, hipStream_t s);
+void launch_scale(double* dst, const double* src, int64_t n, double alpha, hipStream_t s);
+
+}  // namespace rb

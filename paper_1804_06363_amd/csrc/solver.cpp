@@ -1,0 +1,466 @@
+// Batched online solver: drives the HIP kernels of one iteration of RBCG (Alg. 3),
+// RBI (Alg. 2) or plain CG for B queries, with device-side stopping tests and a host
+// check of the active queries every few iterations (optionally replaying a captured
+// HIP graph of two iterations).
+#include "solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace rb {
+
+static int64_t align64(int64_t v) { return (v + 63) / 64 * 64; }
+
+BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
+                         const rb_solve_opts& o, int B_, const double* theta, const double* phi,
+                         const int* n_use)
+    : ctx(c), prob(p), basis(b), opt(o), B(B_) {
+  const StencilGeom& g = prob->g;
+  const int Q = g.Q;
+  if (opt.solver == RB_SOLVER_CG) {
+    basis = nullptr;
+    opt.precond_prec = RB_PREC_FP64;
+  }
+  n = basis ? basis->n : 0;
+  std::vector<int> nu(B, n);
+  if (n_use && basis)
+    for (int i = 0; i < B; ++i) {
+      RB_REQUIRE(n_use[i] >= 0, RB_EINVAL, "n_use must be >= 0");
+      nu[i] = std::min(n_use[i], n);
+    }
+  e_ld = std::max(16, (n + 15) / 16 * 16);
+  y32 = opt.precond_prec != RB_PREC_FP64 && opt.solver != RB_SOLVER_RBI;
+  pt = g.N >= (1 << 20) ? 8 : 4;
+  cN = stencil_chunks(g.N, pt);
+  cR = stencil_chunks(g.NR, pt);
+  cB = stencil_chunks(g.N - g.NR, pt);
+  pstride = cN;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+
+  // per-query inputs
+  theta_d.alloc(sizeof(double) * B * Q);
+  RB_HIP(hipMemcpyAsync(theta_d.p, theta, sizeof(double) * B * Q, hipMemcpyHostToDevice, st));
+  const int R = prob->R;
+  std::vector<double> sc(B, 1.0);
+  if (R == 1 && phi)
+    for (int i = 0; i < B; ++i) sc[i] = phi[i];
+  scale_d.alloc(sizeof(double) * B);
+  RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+  nuse_d.alloc(sizeof(int) * B);
+  RB_HIP(hipMemcpyAsync(nuse_d.p, nu.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  if (R == 1) {
+    f_base = prob->f.as<double>();
+    f_ld = 0;
+  } else {
+    // f_b = sum_r phi_br f_r, formed on the host once (R small) and uploaded
+    fb.alloc(sizeof(double) * B * L_);
+    std::vector<double> tmp((size_t)B * L_, 0.0);
+    // storage order of f_r is kept on the device; build from the host copy
+    std::vector<double> sto((size_t)g.N);
+    for (int i = 0; i < B; ++i) {
+      for (int pos = 0; pos < g.N; ++pos) {
+        const int Lx = pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
+        double v = 0.0;
+        for (int r = 0; r < R; ++r)
+          v += (phi ? phi[(size_t)i * R + r] : 1.0) * prob->f_host[(size_t)r * g.N + Lx];
+        tmp[(size_t)i * L_ + pos] = v;
+      }
+    }
+    RB_HIP(hipMemcpyAsync(fb.p, tmp.data(), sizeof(double) * B * L_, hipMemcpyHostToDevice, st));
+    RB_HIP(hipStreamSynchronize(st));
+    f_base = fb.as<double>();
+    f_ld = L_;
+    std::fill(sc.begin(), sc.end(), 1.0);
+    RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+  }
+
+  coef.alloc(sizeof(double) * B * g.ct_size);
+  launch_coef_tables(g, B, theta_d.as<double>(), nullptr, coef.as<double>(), st);
+
+  // state vectors
+  const size_t vb = sizeof(double) * (size_t)B * L_;
+  x.alloc(vb);
+  r0.alloc(vb);
+  if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
+    r1.alloc(vb);
+  if (opt.solver != RB_SOLVER_RBI) {
+    p0.alloc(vb);
+    p1.alloc(vb);
+    y.alloc((y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+    if (opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
+      z.alloc((y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+  }
+  part_m.alloc(sizeof(double) * (size_t)B * pstride);
+  part_r0.alloc(sizeof(double) * (size_t)B * pstride);
+  part_r1.alloc(sizeof(double) * (size_t)B * pstride);
+  part_b0.alloc(sizeof(double) * (size_t)B * pstride);
+  part_b1.alloc(sizeof(double) * (size_t)B * pstride);
+
+  // reduced basis data
+  if (n > 0) {
+    Wsh = const_cast<rb_basis*>(basis)->shadow(opt.precond_prec);
+    plan = plan_projection(g.N, B, n, 2 * ctx->prop.multiProcessorCount * 4);
+    const size_t acc = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
+    projpart.alloc(acc * (size_t)plan.chunks * B * plan.nj);
+    L.alloc(sizeof(double) * (size_t)B * n * n);
+    // the prolongation reads e in groups of 8 queries: pad and zero the rows
+    const int Bp = (B + 7) / 8 * 8;
+    e64.alloc(sizeof(double) * (size_t)Bp * e_ld);
+    e32.alloc(sizeof(float) * (size_t)Bp * e_ld);
+    launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
+    launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
+  }
+
+  // per-query scalars
+  qbuf.alloc((sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
+  char* qb = qbuf.as<char>();
+  auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
+  auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
+  takeD(q.fnorm2); takeD(q.rho); takeD(q.alpha); takeD(q.beta); takeD(q.rel_rec);
+  takeD(q.rel_true); takeD(q.scalar);
+  takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
+  launch_fill<double>(q.fnorm2, 0, 7 * (int64_t)B, 1, 0.0, st);
+  launch_fill<int>(q.status, 0, (int64_t)B, 1, (int)RB_OK, st);
+  launch_fill<int>(q.active, 0, (int64_t)B, 1, 1, st);
+  launch_fill<int>(q.iters, 0, 3 * (int64_t)B, 1, 0, st);  // iters, flag, restart
+}
+
+BatchSolver::~BatchSolver() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+}
+
+// Reduced assembly + Cholesky of every query (eq. 12b, Sec. 2.1).  A query whose
+// reduced matrix is not SPD is retired with RB_ENOTSPD.
+void BatchSolver::factor() {
+  if (n == 0) return;
+  launch_cholesky(basis->AN.as<double>(), n, prob->g.Q, B, theta_d.as<double>(),
+                  nuse_d.as<int>(), L.as<double>(), q.status, s());
+  // status != OK -> inactive
+  std::vector<int> st(B);
+  RB_HIP(hipMemcpyAsync(st.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost, s()));
+  RB_HIP(hipStreamSynchronize(s()));
+  std::vector<int> act(B);
+  for (int i = 0; i < B; ++i) act[i] = st[i] == RB_OK ? 1 : 0;
+  RB_HIP(hipMemcpyAsync(q.active, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, s()));
+}
+
+// One application y = RBI(A, r, W, 1) from x = 0 (Alg. 3 steps 2/9, i.e. Alg. 2 steps 4-7
+// with the residual equal to r), plus the partial sums of y^T r (and y^T r_old).
+void BatchSolver::precondition(const double* r, const double* r_old) {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  const bool flex = opt.beta_flexible && r_old;
+  if (opt.solver == RB_SOLVER_CG) {  // identity: y = r
+    launch_jacobi<double>(g, B, coef.as<double>(), r, y.as<double>(), L_, 0.0, r, L_,
+                          flex ? r_old : nullptr, L_, q.active, part_r0.as<double>(),
+                          flex ? part_r1.as<double>() : nullptr, pt, st);
+    return;
+  }
+  const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
+  // coarse correction z = W A_N^-1 W^T r (black nodes only for Gauss-Seidel: the red
+  // sweep overwrites every red node and reads only black ones)
+  void* zdst = full ? z.p : y.p;
+  if (n > 0) {
+    launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st);
+    launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, plan.chunks, B, plan.nj, n,
+                        nuse_d.as<int>(), L.as<double>(), q.active, nullptr, e64.as<double>(),
+                        e32.as<float>(), e_ld, true, st);
+    launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
+                   q.active, zdst, !y32, L_, full ? 0 : g.NR, g.N, false, st);
+  } else {
+    if (y32)
+      launch_fill<float>((float*)zdst + (full ? 0 : g.NR), L_, full ? g.N : g.N - g.NR, B, 0.f, st);
+    else
+      launch_fill<double>((double*)zdst + (full ? 0 : g.NR), L_, full ? g.N : g.N - g.NR, B, 0.0,
+                          st);
+  }
+  double* pr0 = part_r0.as<double>();
+  double* pr1 = flex ? part_r1.as<double>() : nullptr;
+  double* pb0 = part_b0.as<double>();
+  double* pb1 = flex ? part_b1.as<double>() : nullptr;
+  auto sweep = [&](int color, bool dots) {
+    if (y32)
+      launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
+                             flex ? r_old : nullptr, L_, q.active, dots ? (color ? pb0 : pr0) : nullptr,
+                             dots ? (color ? pb1 : pr1) : nullptr, pt, st);
+    else
+      launch_gs_color<double>(g, color, B, coef.as<double>(), y.as<double>(), L_, r, L_, nullptr,
+                              flex ? r_old : nullptr, L_, q.active,
+                              dots ? (color ? pb0 : pr0) : nullptr,
+                              dots ? (color ? pb1 : pr1) : nullptr, pt, st);
+  };
+  switch (opt.smoother) {
+    case RB_SMOOTH_RBGS:
+      sweep(0, true);
+      sweep(1, true);
+      break;
+    case RB_SMOOTH_RBGS_SYM:  // forward (red, black) then backward (black, red); the
+      sweep(0, false);        // repeated black sweep changes nothing
+      sweep(1, true);
+      sweep(0, true);
+      break;
+    default: {  // Jacobi (omega 2/3) or none (omega 0): y = z + omega D^-1 (r - A z)
+      const double om = opt.smoother == RB_SMOOTH_JACOBI ? 2.0 / 3.0 : 0.0;
+      if (y32)
+        launch_jacobi<float>(g, B, coef.as<double>(), z.as<float>(), y.as<float>(), L_, om, r, L_,
+                             flex ? r_old : nullptr, L_, q.active, pr0, pr1, pt, st);
+      else
+        launch_jacobi<double>(g, B, coef.as<double>(), z.as<double>(), y.as<double>(), L_, om, r,
+                              L_, flex ? r_old : nullptr, L_, q.active, pr0, pr1, pt, st);
+    }
+  }
+}
+
+static bool dots_split(const rb_solve_opts& o) {
+  return o.solver != RB_SOLVER_CG &&
+         (o.smoother == RB_SMOOTH_RBGS || o.smoother == RB_SMOOTH_RBGS_SYM);
+}
+
+// RBCG steps 0-3 (Alg. 3): x = 0, r = f, y = RBI(A, r, W, 1), p = y (beta = 0).
+void BatchSolver::init_cg() {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  launch_fill<double>(x.as<double>(), L_, L_, B, 0.0, st);
+  launch_fill<double>(p0.as<double>(), L_, L_, B, 0.0, st);
+  launch_fill<double>(p1.as<double>(), L_, L_, B, 0.0, st);
+  launch_fill<double>(r0.as<double>(), L_, L_, B, 0.0, st);  // also zeroes the padding
+  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, B, 0.0, st);
+  launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_, B,
+                  part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), cN, cN, q.fnorm2, nullptr, B, st);
+  factor();
+  launch_fill<int>(q.restart, 0, B, 1, 1, st);
+  precondition(r0.as<double>(), nullptr);
+  const bool split = dots_split(opt);
+  launch_fin_beta(part_r0.as<double>(), split ? cR : cN, split ? part_b0.as<double>() : nullptr,
+                  cB, nullptr, nullptr, q, B, false, st);
+}
+
+// One RBCG iteration (Alg. 3 steps 5-11) for every active query.
+void BatchSolver::iterate_cg(int k) {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  double* pold = (k & 1) ? p1.as<double>() : p0.as<double>();
+  double* pnew = (k & 1) ? p0.as<double>() : p1.as<double>();
+  const bool flex = opt.beta_flexible != 0;
+  double* rin = (flex && (k & 1)) ? r1.as<double>() : r0.as<double>();
+  double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
+  // step 11 of the previous iteration fused with step 5's product: p = y + beta p; A p
+  if (y32)
+    launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
+                         q.beta, q.active, part_m.as<double>(), pt, st);
+  else
+    launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, pold, pnew,
+                          q.beta, q.active, part_m.as<double>(), pt, st);
+  launch_fin_alpha(part_m.as<double>(), cN, cN, q, B, st);
+  // steps 6-7: x += alpha p, r -= alpha A p
+  launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
+                part_m.as<double>(), pt, st);
+  // step 8
+  const bool fixed = opt.fixed_iters > 0;
+  launch_fin_rr(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, fixed, st);
+  if (!fixed) {
+    launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
+                 scale_d.as<double>(), q.flag, part_m.as<double>(), pt, st);
+    launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st);
+  }
+  // steps 9-10
+  precondition(rout, flex ? rin : nullptr);
+  const bool split = dots_split(opt);
+  launch_fin_beta(part_r0.as<double>(), split ? cR : cN, split ? part_b0.as<double>() : nullptr,
+                  cB, flex ? part_r1.as<double>() : nullptr,
+                  (flex && split) ? part_b1.as<double>() : nullptr, q, B, flex, st);
+}
+
+// ---- stand-alone RBI (Alg. 2) ----------------------------------------------------------
+__global__ void k_fin_rbi(QState q, double rtol, int maxit, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || !q.active[b]) return;
+  const double rel = sqrt(q.scalar[b] / q.fnorm2[b]);
+  q.rel_true[b] = rel;
+  q.rel_rec[b] = rel;
+  if (rel <= rtol) {
+    q.active[b] = 0;
+    q.status[b] = RB_OK;
+  } else if (!(rel == rel)) {
+    q.active[b] = 0;
+    q.status[b] = RB_EBREAKDOWN;
+  } else if (q.iters[b] >= maxit) {
+    q.active[b] = 0;
+    q.status[b] = RB_ENOCONV;
+  } else {
+    q.iters[b] += 1;
+  }
+}
+
+void BatchSolver::init_rbi() {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  launch_fill<double>(x.as<double>(), L_, L_, B, 0.0, st);
+  launch_fill<double>(r0.as<double>(), L_, L_, B, 0.0, st);
+  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, B, 0.0, st);
+  launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_, B,
+                  part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), cN, cN, q.fnorm2, nullptr, B, st);
+  factor();
+}
+
+// Alg. 2 steps 2-7 for every active query (x lives in x, r in r0).
+void BatchSolver::iterate_rbi(int k) {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  double* xc = x.as<double>();
+  // step 2: r = f - A x, ||r||^2  (the active flags select the queries)
+  launch_apply(g, L_, B, coef.as<double>(), xc, r0.as<double>(), 1, f_base, f_ld,
+               scale_d.as<double>(), q.active, part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, q.active, B, st);
+  // step 3
+  const bool fixed = opt.fixed_iters > 0;
+  hipLaunchKernelGGL(k_fin_rbi, dim3((B + 63) / 64), dim3(64), 0, st, q, fixed ? -1.0 : opt.rtol,
+                     fixed ? (1 << 30) : opt.maxit, B);
+  const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
+  // steps 4-6: x += W A_N^-1 W^T r (black nodes only before a Gauss-Seidel sweep)
+  if (n > 0) {
+    launch_projection(plan, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
+                      projpart.p, st);
+    launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, plan.chunks, B, plan.nj, n,
+                        nuse_d.as<int>(), L.as<double>(), q.active, nullptr, e64.as<double>(),
+                        e32.as<float>(), e_ld, true, st);
+    launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
+                   q.active, xc, true, L_, full ? 0 : g.NR, g.N, true, st);
+  }
+  // step 7: x = S(A, f, x)
+  auto sweep = [&](int color) {
+    launch_gs_color<double>(g, color, B, coef.as<double>(), xc, L_, f_base, f_ld,
+                            scale_d.as<double>(), nullptr, 0, q.active, nullptr, nullptr, pt, st);
+  };
+  switch (opt.smoother) {
+    case RB_SMOOTH_RBGS:
+      sweep(0);
+      sweep(1);
+      break;
+    case RB_SMOOTH_RBGS_SYM:
+      sweep(0);
+      sweep(1);
+      sweep(0);
+      break;
+    case RB_SMOOTH_JACOBI:
+      RB_REQUIRE(f_ld == L_ || prob->R == 1, RB_EUNSUPPORTED, "Jacobi RBI");
+      // x_new = x + omega D^-1 (f - A x) into r1, copied back into x
+      launch_jacobi<double>(g, B, coef.as<double>(), xc, r1.as<double>(), L_, 2.0 / 3.0, f_base,
+                            f_ld, nullptr, 0, q.active, nullptr, nullptr, pt, st);
+      RB_HIP(hipMemcpyAsync(xc, r1.p, sizeof(double) * (size_t)B * L_, hipMemcpyDeviceToDevice,
+                            st));
+      break;
+    default:
+      break;
+  }
+  (void)k;
+}
+
+// Final FP64 true residual of every query (reported in the stats).
+void BatchSolver::final_true_residual() {
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  DevBuf ones(sizeof(int) * B);
+  launch_fill<int>(ones.as<int>(), 0, B, 1, 1, st);
+  double* tmp = r0.as<double>();
+  launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), tmp, 1, f_base, f_ld,
+               scale_d.as<double>(), ones.as<int>(), part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, nullptr, B, st);
+  RB_HIP(hipStreamSynchronize(st));
+}
+
+void BatchSolver::run() {
+  hipStream_t st = s();
+  const bool rbi = opt.solver == RB_SOLVER_RBI;
+  if (rbi)
+    init_rbi();
+  else
+    init_cg();
+  const bool fixed = opt.fixed_iters > 0;
+  int k = 0;
+  int chunk = opt.check_every > 0 ? opt.check_every : (prob->g.N >= (1 << 18) ? 4 : 16);
+  if (opt.use_graph && chunk % 2) ++chunk;
+  std::vector<int> act(B);
+  // RBI: iteration k checks the residual of the k-th iterate first; maxit + 1 checks
+  const int limit = fixed ? opt.fixed_iters : (rbi ? opt.maxit + 1 : opt.maxit);
+  while (k < limit) {
+    int todo = std::min(chunk, limit - k);
+    if (opt.use_graph && !rbi && todo >= 2) {
+      if (!graph) {
+        hipGraph_t gr;
+        RB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        iterate_cg(0);
+        iterate_cg(1);
+        RB_HIP(hipStreamEndCapture(st, &gr));
+        RB_HIP(hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0));
+        RB_HIP(hipGraphDestroy(gr));
+      }
+      // the graph holds iterations (even, odd); k is even here
+      while (todo >= 2) {
+        RB_HIP(hipGraphLaunch(graph, st));
+        k += 2;
+        todo -= 2;
+      }
+    }
+    for (; todo > 0; --todo, ++k) {
+      if (rbi)
+        iterate_rbi(k);
+      else
+        iterate_cg(k);
+    }
+    if (fixed) continue;
+    RB_HIP(hipMemcpyAsync(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int i = 0; i < B; ++i) any |= act[i] != 0;
+    if (!any) break;
+  }
+  RB_HIP(hipStreamSynchronize(st));
+  // queries still active after maxit did not converge
+  if (!fixed) {
+    std::vector<int> stt(B);
+    RB_HIP(hipMemcpy(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost));
+    RB_HIP(hipMemcpy(stt.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost));
+    bool changed = false;
+    for (int i = 0; i < B; ++i)
+      if (act[i]) {
+        stt[i] = RB_ENOCONV;
+        changed = true;
+      }
+    if (changed)
+      RB_HIP(hipMemcpy(q.status, stt.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+  }
+}
+
+void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_stats>& stats) {
+  hipStream_t st = s();
+  final_true_residual();
+  if (x_user) launch_from_storage(*prob, B, x.as<double>(), ld(), x_user, user_ld, st);
+  std::vector<int> it(B), stt(B);
+  std::vector<double> rr(B), rec(B), fn(B);
+  RB_HIP(hipMemcpyAsync(it.data(), q.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipMemcpyAsync(stt.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipMemcpyAsync(rr.data(), q.scalar, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipMemcpyAsync(rec.data(), q.rel_rec, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipMemcpyAsync(fn.data(), q.fnorm2, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipStreamSynchronize(st));
+  stats.resize(B);
+  for (int i = 0; i < B; ++i) {
+    stats[i].iters = it[i];
+    stats[i].status = (rb_status)stt[i];
+    stats[i].rel_res_true = std::sqrt(rr[i] / fn[i]);
+    stats[i].rel_res_recursive = rec[i];
+  }
+}
+
+}  // namespace rb

@@ -1,0 +1,61 @@
+// Batched online solver: RBCG (Alg. 3), RBI (Alg. 2) and plain CG over B queries of
+// one problem and one basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace rb {
+
+struct BatchSolver {
+  rb_ctx* ctx;
+  const rb_problem* prob;
+  const rb_basis* basis;  // may be null (CG, or n = 0)
+  rb_solve_opts opt;
+  int B = 0;
+  int n = 0;        // basis columns used (max over queries)
+  int e_ld = 16;    // row stride of e
+  int pt = 4;       // nodes per thread in the stencil passes
+  int cN = 1, cR = 1, cB = 1;  // partial-sum chunks for all / red / black nodes
+  int pstride = 1;             // per-query stride of the partial-sum arrays
+  bool y32 = false;            // y stored in FP32
+  ProjPlan plan;
+  const void* Wsh = nullptr;   // basis in the preconditioner's precision
+
+  // device buffers
+  DevBuf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
+  DevBuf x, r0, r1, p0, p1, y, z;
+  DevBuf part_m, part_r0, part_r1, part_b0, part_b1;
+  DevBuf qbuf;  // QState arrays
+  QState q{};
+  const double* f_base = nullptr;  // right-hand side term(s), storage order
+  int64_t f_ld = 0;                // 0: one shared term scaled per query
+  DevBuf fb;                       // materialised f_b when R > 1
+  hipGraphExec_t graph = nullptr;
+  int graph_parity = 0;
+
+  BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b, const rb_solve_opts& o, int B_,
+              const double* theta, const double* phi, const int* n_use);
+  ~BatchSolver();
+
+  hipStream_t s() const { return ctx->stream; }
+  int64_t ld() const { return prob->ld; }
+  // RBCG / CG
+  void init_cg();
+  void iterate_cg(int k);
+  void precondition(const double* r, const double* r_old);
+  // RBI
+  void init_rbi();
+  void iterate_rbi(int k);
+  // driver
+  void run();
+  void final_true_residual();
+  void gather(double* x_user_nat, int64_t user_ld, std::vector<rb_query_stats>& stats);
+  void factor();
+};
+
+}  // namespace rb

@@ -1,0 +1,316 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances (FP64 path): single kernels 1e-13 relative (only the summation order
+differs); iterates after k RBCG steps 1e-10 relative; converged solutions: both
+reach a true relative residual <= 1e-10, iteration counts within one, and the
+solutions agree to 2 cond(A) 1e-10.  Mixed precision: true residual <= 1e-10 (the
+preconditioner's precision does not enter the FP64 residual) and the solution error
+against the oracle within the same bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import rb as orb
+from oracle.operator import BlockDiffusion
+from oracle.smoother import Smoother
+from workloads import log_uniform_mu, random_orthonormal, random_vectors
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [((31,), (2,)), ((15, 15), (2, 2)), ((63, 63), (4, 4)), ((7, 9, 5), (2, 2, 3)),
+         ((31, 31, 31), (2, 2, 2))]
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _setup(lib, ctx, dims, blocks, n, seed=0):
+    op = BlockDiffusion(dims, blocks)
+    prob = lib.Problem(ctx, dims, blocks)
+    W = random_orthonormal(seed, op.N, n) if n else np.zeros((op.N, 0))
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    return op, prob, W, basis
+
+
+def _cond(A):
+    import scipy.sparse.linalg as spla
+    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = spla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    return lmax / lmin
+
+
+def _snapshot_basis(op, n, seed):
+    mus = log_uniform_mu(seed, n, op.Q, 0.1, 10.0)
+    X = np.column_stack([orb.solve_rbcg(op, m, np.zeros((op.N, 0)), rtol=1e-12,
+                                        flexible=True).x for m in mus])
+    q, _ = np.linalg.qr(X)
+    return q
+
+
+# ---- single steps ----------------------------------------------------------------------
+@pytest.mark.parametrize("dims,blocks", GRIDS)
+def test_apply_matches_oracle(lib, ctx, dims, blocks):
+    op = BlockDiffusion(dims, blocks)
+    prob = lib.Problem(ctx, dims, blocks)
+    B = 5
+    theta = log_uniform_mu(1, B, op.Q, 0.01, 100.0)
+    u = random_vectors(2, B, op.N)
+    y = lib.apply_batch(ctx, prob, theta, _t(u)).cpu().numpy()
+    for b in range(B):
+        ref = op.assemble(theta[b]) @ u[b]
+        assert _rel(y[b], ref) <= 1e-13, (dims, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16", 3e-2)])
+@pytest.mark.parametrize("B", [1, 3, 17, 70, 130])
+def test_projection(lib, ctx, prec, tol, B):
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 37, seed=3)
+    r = random_vectors(4, B, op.N)
+    t = lib.project_batch(ctx, prob, basis, _t(r), prec=prec)
+    ref = r @ W
+    scale = np.linalg.norm(r, axis=1)[:, None]
+    assert np.abs(t - ref).max() / scale.max() <= tol
+
+
+def test_reduced_operators_and_cholesky(lib, ctx):
+    dims, blocks = (15, 15), (2, 2)
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 9, seed=5)
+    Wh, AN, fN = basis.info()
+    assert np.abs(Wh - W.T).max() == 0.0
+    ANo, fNo = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    assert np.abs(AN - ANo).max() <= 1e-12 * np.abs(ANo).max()
+    assert np.abs(fN - fNo).max() <= 1e-12 * np.abs(fNo).max()
+    theta = log_uniform_mu(6, 4, op.Q, 0.1, 10.0)
+    L, st = lib.reduced_factor_batch(ctx, basis, theta)
+    for b in range(4):
+        Lo = orb.cholesky(orb.assemble_reduced(ANo, theta[b]))
+        assert st[b] == lib.RB_OK
+        assert np.abs(L[b] - Lo).max() <= 1e-12 * np.abs(Lo).max()
+    # an indefinite reduced matrix is reported, the other queries are unaffected
+    bad = theta.copy()
+    bad[1] = -bad[1]
+    L2, st2 = lib.reduced_factor_batch(ctx, basis, bad)
+    assert st2[1] == lib.RB_ENOTSPD and st2[0] == lib.RB_OK and st2[2] == lib.RB_OK
+
+
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3)),
+                                         ((63, 63), (4, 4))])
+@pytest.mark.parametrize("smoother", ["rbgs", "rbgs_sym", "jacobi", "none"])
+def test_preconditioner_fp64(lib, ctx, dims, blocks, smoother):
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 6, seed=7)
+    B = 3
+    theta = log_uniform_mu(8, B, op.Q, 0.1, 10.0)
+    r = random_vectors(9, B, op.N)
+    y = lib.precond_batch(ctx, prob, basis, theta, _t(r), smoother=smoother).cpu().numpy()
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    for b in range(B):
+        A, M = orb.make_preconditioner(op, theta[b], W, AN, smoother_kind=smoother)
+        ref = M(r[b])
+        assert _rel(y[b], ref) <= 1e-12, (b, _rel(y[b], ref))
+
+
+def test_preconditioner_nested_n_use(lib, ctx):
+    dims, blocks = (15, 15), (2, 2)
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 8, seed=10)
+    theta = log_uniform_mu(11, 4, op.Q, 0.1, 10.0)
+    r = random_vectors(12, 4, op.N)
+    n_use = [0, 3, 8, 5]
+    y = lib.precond_batch(ctx, prob, basis, theta, _t(r), n_use=n_use).cpu().numpy()
+    for b in range(4):
+        Wb = W[:, :n_use[b]]
+        A, M = orb.make_preconditioner(op, theta[b], Wb)
+        assert _rel(y[b], M(r[b])) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 5e-2)])
+def test_preconditioner_mixed(lib, ctx, prec, tol):
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 12, seed=13)
+    theta = log_uniform_mu(14, 2, op.Q, 0.1, 10.0)
+    r = random_vectors(15, 2, op.N)
+    y = lib.precond_batch(ctx, prob, basis, theta, _t(r), prec=prec).cpu().numpy()
+    for b in range(2):
+        A, M = orb.make_preconditioner(op, theta[b], W)
+        assert _rel(y[b], M(r[b])) <= tol
+
+
+# ---- RBCG / RBI / CG -------------------------------------------------------------------
+@pytest.mark.parametrize("dims,blocks,n", [((15, 15), (2, 2), 4), ((63, 63), (2, 2), 6),
+                                           ((7, 9, 5), (2, 2, 3), 3),
+                                           ((31, 31, 31), (2, 2, 2), 5)])
+@pytest.mark.parametrize("flexible", [False, True])
+def test_rbcg_fixed_iterations(lib, ctx, dims, blocks, n, flexible):
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, n, seed=20)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(21, 4, op.Q, 0.1, 10.0)
+    k = 7
+    x, st = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, flexible=flexible)
+    x = x.cpu().numpy()
+    for b in range(4):
+        ref = orb.solve_rbcg(op, theta[b], W, AN, fixed_iters=k, flexible=flexible)
+        assert st.iters[b] == k
+        assert _rel(x[b], ref.x) <= 1e-10, (b, _rel(x[b], ref.x))
+
+
+@pytest.mark.parametrize("dims,blocks,n", [((63, 63), (2, 2), 8), ((31, 31, 31), (2, 2, 2), 6)])
+@pytest.mark.parametrize("graph", [False, True])
+def test_rbcg_converged(lib, ctx, dims, blocks, n, graph):
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, n, seed=30)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(31, 6, op.Q, 0.1, 10.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, graph=graph)
+    x = x.cpu().numpy()
+    for b in range(6):
+        ref = orb.solve_rbcg(op, theta[b], W, AN)
+        assert st.status[b] == lib.RB_OK
+        assert st.rel_res_true[b] <= 1e-10
+        assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
+        if st.iters[b] == ref.iters:
+            assert _rel(x[b], ref.x) <= 1e-9
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(lib, ctx):
+    dims, blocks = (63, 63), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 5, seed=33)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(34, 8, op.Q, 0.1, 10.0)
+    x1, s1 = lib.solve_batch(ctx, prob, basis, theta, graph=False, check_every=4)
+    x2, s2 = lib.solve_batch(ctx, prob, basis, theta, graph=True, check_every=4)
+    x3, s3 = lib.solve_batch(ctx, prob, basis, theta, graph=True, check_every=4)
+    assert np.array_equal(s1.iters, s2.iters) and np.array_equal(s2.iters, s3.iters)
+    assert (x1 == x2).all() and (x2 == x3).all()
+
+
+def test_plain_cg_parity(lib, ctx):
+    dims, blocks = (31, 31), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    prob = lib.Problem(ctx, dims, blocks)
+    theta = log_uniform_mu(40, 3, op.Q, 0.1, 10.0)
+    x, st = lib.solve_batch(ctx, prob, None, theta, solver="cg", fixed_iters=25)
+    x = x.cpu().numpy()
+    for b in range(3):
+        ref = orb.solve_cg(op, theta[b], fixed_iters=25)
+        assert _rel(x[b], ref.x) <= 1e-10
+    x, st = lib.solve_batch(ctx, prob, None, theta, solver="cg")
+    for b in range(3):
+        ref = orb.solve_cg(op, theta[b])
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        assert abs(st.iters[b] - ref.iters) <= 2
+
+
+@pytest.mark.parametrize("smoother", ["rbgs", "rbgs_sym"])
+def test_rbi_parity(lib, ctx, smoother):
+    dims, blocks = (31, 31), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 6, seed=41)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(42, 3, op.Q, 0.1, 10.0)
+    m = 12
+    x, st = lib.solve_batch(ctx, prob, basis, theta, solver="rbi", fixed_iters=m, smoother=smoother)
+    x = x.cpu().numpy()
+    for b in range(3):
+        xr, k, hist = orb.solve_rbi(op, theta[b], W, AN, m=m, rtol=0.0, smoother_kind=smoother)
+        assert k == m
+        assert _rel(x[b], xr) <= 1e-10
+
+
+def test_rbi_converges(lib, ctx):
+    dims, blocks = (31, 31), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 10, seed=43)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(44, 3, op.Q, 0.1, 10.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, solver="rbi", maxit=3000)
+    for b in range(3):
+        xr, k, hist = orb.solve_rbi(op, theta[b], W, AN, m=3000, rtol=1e-10)
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        assert abs(st.iters[b] - k) <= 1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_rbcg(lib, ctx, prec):
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 8, seed=50)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(51, 4, op.Q, 0.1, 10.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, prec=prec, flexible=True)
+    x = x.cpu().numpy()
+    for b in range(4):
+        ref = orb.solve_rbcg(op, theta[b], W, AN)
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        # two solutions with relative residual <= 1e-10 differ by <= 2 kappa(A) 1e-10
+        kappa = _cond(op.assemble(theta[b]))
+        assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
+
+
+# ---- failure handling ------------------------------------------------------------------
+def test_per_query_failures(lib, ctx):
+    dims, blocks = (15, 15), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 3, seed=60)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(61, 3, op.Q, 0.1, 10.0)
+    theta[1] = -theta[1]
+    x, st = lib.solve_batch(ctx, prob, basis, theta)
+    assert st.status[1] in (lib.RB_ENOTSPD, lib.RB_EBREAKDOWN)
+    assert st.status[0] == lib.RB_OK and st.status[2] == lib.RB_OK
+    x, st = lib.solve_batch(ctx, prob, basis, np.abs(theta), maxit=1)
+    assert (st.status == lib.RB_ENOCONV).all()
+    bad = theta.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(lib.RBError) as ei:
+        lib.solve_batch(ctx, prob, basis, bad)
+    assert ei.value.status == lib.RB_EINVAL
+
+
+def test_invalid_problems(lib, ctx):
+    with pytest.raises(lib.RBError):
+        lib.Problem(ctx, (6, 7), (2, 2))      # (n+1) % blocks
+    with pytest.raises(lib.RBError):
+        lib.Problem(ctx, (8, 7), (1, 1))      # even n_x in 2D
+
+
+def test_batch_composition_invariance(lib, ctx):
+    dims, blocks = (63, 63), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 5, seed=70)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(71, 9, op.Q, 0.1, 10.0)
+    xa, sa = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=10)
+    perm = np.random.default_rng(72).permutation(9)
+    xb, sb = lib.solve_batch(ctx, prob, basis, theta[perm], fixed_iters=10)
+    xa = xa.cpu().numpy()
+    xb = xb.cpu().numpy()
+    for i, p in enumerate(perm):
+        assert _rel(xb[i], xa[p]) <= 1e-13
+    x1, s1 = lib.solve_batch(ctx, prob, basis, theta[3:4], fixed_iters=10)
+    assert _rel(x1.cpu().numpy()[0], xa[3]) <= 1e-13
