@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of batched mixed-precision RB-PCG on one MI355X.
+
+Workload (synthetic, seeded): 3D 7-point diffusion on a 127^3 interior grid
+(N = 2,048,383), kappa constant on 2x2x2 octants with mu log-uniform in [0.1, 10]
+(P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, L1
+indicator) over 256 training parameters; 256 test parameters per call.  A step is
+one rb_solve_batch of the 256 queries to relative residual 1e-10 (RBCG of Alg. 3,
+FP32 preconditioner, FP64 CG).  value = converged mu-solves per second.
+
+Also reported: the plain path (same library, FP64 everywhere, one query per call),
+the roofline of the dominant kernel (pass B of the iteration: x += alpha p,
+r -= alpha A p), and the CPU oracle on a bounded sample.
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="3d127")
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--B", type=int, default=0, help="queries per call (default: workload's)")
+    ap.add_argument("--flexible", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--greedy", default="l1", choices=["l1", "residual"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the queries are independent and the build "
+              "has no multi-GPU path (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_06363_amd import rb
+    from workloads import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    B = args.B or w.B
+    N, Q = w.N, w.Q
+    log(f"workload {w.name}: N={N} Q={Q} n={w.n} B={B} prec={args.prec}")
+    ctx = rb.Context(0)
+    prob = rb.Problem(ctx, w.dims, w.blocks)
+    train = w.train_mu()
+    t0 = time.time()
+    basis, rep = rb.offline_build(ctx, prob, train, mu=train, n_max=w.n, indicator=args.greedy)
+    log(f"offline greedy: n={basis.n} in {time.time() - t0:.1f}s, snapshot iters "
+        f"{rep['snapshot_iters'][:5]}..{rep['snapshot_iters'][-3:]}")
+    test = w.test_mu(B)
+    x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
+    opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph))
+
+    for i in range(args.warmup):
+        _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=opts)
+        log(f"warmup {i}: iters mean {st.iters.mean():.1f} max {st.iters.max()} "
+            f"max rel res {st.rel_res_true.max():.2e} status {np.bincount(st.status)}")
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    iters_total = 0
+    conv = 0
+    stats = []
+    for i in range(args.steps):
+        _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=opts)
+        stats.append(st)
+        conv += int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+        iters_total += int(st.iters.sum())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    ctx.profile(False)
+    prof = ctx.profile_totals()
+    value = conv / elapsed
+    st = stats[-1]
+    log(f"timed: {args.steps} steps in {elapsed:.3f}s -> {value:.1f} mu-solves/s; "
+        f"iters mean {st.iters.mean():.1f} max rel res {st.rel_res_true.max():.2e}")
+    for k, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        log(f"  {k:14s} {ms:9.2f} ms  {n:6d} launches  {ms / max(n, 1) * 1e3:9.1f} us/launch")
+
+    # roofline of the dominant kernel: pass B reads x, p, r and writes x, r (FP64) for
+    # every active query: 40 algorithmic bytes per DOF per active query-iteration
+    ms_b, n_b = prof.get("pass_b", (0.0, 0))
+    bytes_b = 40.0 * N * iters_total
+    achieved = bytes_b / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0
+    roofline = {"kernel": "k_pass_b", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_launch": round(bytes_b / max(n_b, 1)),
+                "avg_launch_us": round(ms_b / max(n_b, 1) * 1e3, 1)}
+
+    # plain path: FP64 everywhere, one query per call, sequential
+    plain = None
+    if args.plain_sample > 0:
+        S = min(args.plain_sample, B)
+        popts = rb.solve_opts(prec="fp64")
+        xs = torch.empty((1, N), dtype=torch.float64, device="cuda:0")
+        rb.solve_batch(ctx, prob, basis, test[:1], x=xs, opts=popts)  # warm-up
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        pc = 0
+        pit = []
+        for b in range(S):
+            _, ps = rb.solve_batch(ctx, prob, basis, test[b:b + 1], x=xs, opts=popts)
+            pc += int(((ps.status == rb.RB_OK) & (ps.rel_res_true <= 1e-10)).sum())
+            pit.append(int(ps.iters[0]))
+        torch.cuda.synchronize()
+        pe = time.perf_counter() - tp
+        plain = {"value": round(pc / pe, 2), "sample": S, "iters_mean": float(np.mean(pit))}
+        log(f"plain FP64 B=1: {plain['value']} mu-solves/s over {S} queries, iters {np.mean(pit):.1f}")
+
+    cpu = None
+    if args.cpu_baseline:
+        cpu = cpu_baseline(basis, w, test[0])
+
+    out = {
+        "metric": "mu-solves/sec to rel. residual 1e-10 (batched mixed RB-PCG)",
+        "value": round(value, 2), "unit": "mu-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+" + args.prec, "data": "synthetic",
+        "config": {"workload": f"3D 7-pt diffusion 127^3 (N={N}), 2x2x2 kappa blocks, "
+                               f"n={basis.n}, B={B}, {args.prec} preconditioner",
+                   "N": N, "B": B, "n": basis.n, "Q": Q, "prec": args.prec,
+                   "beta": "flexible" if args.flexible else "literal",
+                   "graph": bool(args.graph), "parallelism": "single-gpu"},
+        "iters_mean": round(float(st.iters.mean()), 2), "iters_max": int(st.iters.max()),
+        "max_rel_res": float(st.rel_res_true.max()), "converged": conv,
+        "plain_fp64_b1": plain,
+        "speedup_vs_plain": round(value / plain["value"], 2) if plain and plain["value"] else None,
+        "roofline": roofline, "cpu_baseline": cpu,
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(basis, w, theta):
+    """The oracle's RBCG (NumPy/SciPy FP64) on one query of the same workload."""
+    from oracle import rb as orb
+    from oracle.operator import BlockDiffusion
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    log("cpu baseline: building the oracle operator")
+    op = BlockDiffusion(w.dims, w.blocks)
+    Wn, AN, fN = basis.info()
+    W = np.ascontiguousarray(Wn.T)
+    t = time.perf_counter()
+    res = orb.solve_rbcg(op, theta, W, AN, rtol=1e-10)
+    el = time.perf_counter() - t
+    log(f"cpu baseline: 1 solve in {el:.1f}s, iters {res.iters}, rel res {res.rel_res_true:.2e}")
+    return {"value": round(1.0 / el, 5), "unit": "mu-solves/s", "cores": cores, "kind": "oracle",
+            "sample": "1 query of the same workload (operator setup excluded; reduced "
+                      "assembly, Cholesky, RBCG iterations and true residual timed)",
+            "iters": res.iters}
+
+
+if __name__ == "__main__":
+    main()

@@ -67,13 +67,24 @@ typedef struct rb_ctx rb_ctx;
 typedef struct rb_problem rb_problem;
 typedef struct rb_basis rb_basis;
 
-/* Context: a device and a HIP stream (NULL = the null stream).  The stream must
- * outlive the context. */
+/* Context: a device and a HIP stream.  hip_stream == NULL: the library creates its
+ * own blocking stream (default priority), which orders after work on the null
+ * stream; otherwise the caller's stream is used and must outlive the context.
+ * HIP-graph replay (use_graph) needs a stream other than the null stream. */
 rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx** out);
 rb_status rb_ctx_destroy(rb_ctx* ctx);
 const char* rb_last_error(void);
 /* Library version string, e.g. "rb 0.1 gfx950". */
 const char* rb_version(void);
+
+/* Per-kernel timing: when on, every kernel class launched by the solvers is bracketed
+ * by HIP events on the context's stream (not inside captured graphs).  Entries are
+ * accumulated per kernel name; rb_profile_get returns entry idx (0-based) and fails
+ * with RB_EINVAL past the last one.  name is NUL-terminated, truncated to name_len. */
+rb_status rb_profile_enable(rb_ctx* ctx, int on);
+rb_status rb_profile_reset(rb_ctx* ctx);
+rb_status rb_profile_get(rb_ctx* ctx, int idx, char* name, size_t name_len, double* ms,
+                         int64_t* launches);
 
 /* ---- Problems: the affine operator of eq. (12) ------------------------------
  * Matrix-free block diffusion: -div(kappa grad u) = f on the unit square/cube,

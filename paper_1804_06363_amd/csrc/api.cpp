@@ -43,6 +43,42 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  RB_HIP(hipEventCreate(&e));
+  return e;
+}
+void Profiler::resolve() {
+  for (auto& p : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto it = std::find_if(totals.begin(), totals.end(),
+                             [&](const auto& t) { return t.first == p.name; });
+      if (it == totals.end()) {
+        totals.push_back({p.name, Total{}});
+        it = totals.end() - 1;
+      }
+      it->second.ms += ms;
+      it->second.launches += 1;
+    }
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+Profiler::~Profiler() {
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 template <typename F>
 static rb_status guarded(F&& f) {
   try {
@@ -143,6 +179,41 @@ rb_status rb_ctx_destroy(rb_ctx* ctx) {
       (void)hipStreamDestroy(ctx->stream);
     }
     delete ctx;
+  });
+}
+
+rb_status rb_profile_enable(rb_ctx* ctx, int on) {
+  return guarded([&] {
+    RB_REQUIRE(ctx, RB_EINVAL, "null context");
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    ctx->prof.on = on != 0;
+  });
+}
+
+rb_status rb_profile_reset(rb_ctx* ctx) {
+  return guarded([&] {
+    RB_REQUIRE(ctx, RB_EINVAL, "null context");
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    ctx->prof.totals.clear();
+  });
+}
+
+rb_status rb_profile_get(rb_ctx* ctx, int idx, char* name, size_t name_len, double* ms,
+                         int64_t* launches) {
+  return guarded([&] {
+    RB_REQUIRE(ctx, RB_EINVAL, "null context");
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    RB_REQUIRE(idx >= 0 && idx < (int)ctx->prof.totals.size(), RB_EINVAL, "no such entry");
+    const auto& t = ctx->prof.totals[idx];
+    if (name && name_len) {
+      std::strncpy(name, t.first.c_str(), name_len - 1);
+      name[name_len - 1] = 0;
+    }
+    if (ms) *ms = t.second.ms;
+    if (launches) *launches = t.second.launches;
   });
 }
 

@@ -73,12 +73,59 @@ struct StencilGeom {
   int ct_size;    // doubles per query (padded)
 };
 
+namespace rb {
+// Per-kernel timing with HIP events on the context's stream (off by default).
+struct Profiler {
+  bool on = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  struct Total {
+    double ms = 0.0;
+    int64_t launches = 0;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<std::string, Total>> totals;
+  hipEvent_t get();
+  void record(const char* name, hipEvent_t a, hipEvent_t b) { pending.push_back({name, a, b}); }
+  void resolve();  // after the stream has been synchronised
+  ~Profiler();
+};
+}  // namespace rb
+
 struct rb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipDeviceProp_t prop{};
+  rb::Profiler prof;
 };
+
+namespace rb {
+// Times the launches issued while it is alive (when profiling is on and the stream is
+// not being captured into a graph).
+struct ProfScope {
+  rb_ctx* ctx;
+  const char* name;
+  hipEvent_t a = nullptr;
+  ProfScope(rb_ctx* c, const char* n) : ctx(c), name(n) {
+    if (!ctx->prof.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return;
+    a = ctx->prof.get();
+    (void)hipEventRecord(a, ctx->stream);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = ctx->prof.get();
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->prof.record(name, a, b);
+  }
+};
+}  // namespace rb
 
 struct rb_problem {
   rb_ctx* ctx = nullptr;

@@ -164,10 +164,17 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   // sweep overwrites every red node and reads only black ones)
   void* zdst = full ? z.p : y.p;
   if (n > 0) {
-    launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st);
-    launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, plan.chunks, B, plan.nj, n,
-                        nuse_d.as<int>(), L.as<double>(), q.active, nullptr, e64.as<double>(),
-                        e32.as<float>(), e_ld, true, st);
+    {
+      ProfScope ps(ctx, "project");
+      launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st);
+    }
+    {
+      ProfScope ps(ctx, "reduced_solve");
+      launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, plan.chunks, B, plan.nj,
+                          n, nuse_d.as<int>(), L.as<double>(), q.active, nullptr,
+                          e64.as<double>(), e32.as<float>(), e_ld, true, st);
+    }
+    ProfScope ps(ctx, "prolong");
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
                    q.active, zdst, !y32, L_, full ? 0 : g.NR, g.N, false, st);
   } else {
@@ -182,6 +189,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   double* pb0 = part_b0.as<double>();
   double* pb1 = flex ? part_b1.as<double>() : nullptr;
   auto sweep = [&](int color, bool dots) {
+    ProfScope ps(ctx, color ? "gs_black" : "gs_red");
     if (y32)
       launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
                              flex ? r_old : nullptr, L_, q.active, dots ? (color ? pb0 : pr0) : nullptr,
@@ -251,20 +259,27 @@ void BatchSolver::iterate_cg(int k) {
   double* rin = (flex && (k & 1)) ? r1.as<double>() : r0.as<double>();
   double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
   // step 11 of the previous iteration fused with step 5's product: p = y + beta p; A p
+  {
+  ProfScope ps(ctx, "pass_a");
   if (y32)
     launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
                          q.beta, q.active, part_m.as<double>(), pt, st);
   else
     launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, pold, pnew,
                           q.beta, q.active, part_m.as<double>(), pt, st);
+  }
   launch_fin_alpha(part_m.as<double>(), cN, cN, q, B, st);
   // steps 6-7: x += alpha p, r -= alpha A p
-  launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
-                part_m.as<double>(), pt, st);
+  {
+    ProfScope ps(ctx, "pass_b");
+    launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
+                  part_m.as<double>(), pt, st);
+  }
   // step 8
   const bool fixed = opt.fixed_iters > 0;
   launch_fin_rr(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
+    ProfScope ps(ctx, "true_residual");
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
                  scale_d.as<double>(), q.flag, part_m.as<double>(), pt, st);
     launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st);
@@ -421,6 +436,7 @@ void BatchSolver::run() {
     if (fixed) continue;
     RB_HIP(hipMemcpyAsync(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     RB_HIP(hipStreamSynchronize(st));
+    ctx->prof.resolve();
     bool any = false;
     for (int i = 0; i < B; ++i) any |= act[i] != 0;
     if (!any) break;

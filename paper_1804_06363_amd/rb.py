@@ -93,6 +93,9 @@ rb_last_error = _sig("rb_last_error", [], C.c_char_p)
 rb_version = _sig("rb_version", [], C.c_char_p)
 _sig("rb_ctx_create", [C.c_int, _P, C.POINTER(_P)])
 _sig("rb_ctx_destroy", [_P])
+_sig("rb_profile_enable", [_P, C.c_int])
+_sig("rb_profile_reset", [_P])
+_sig("rb_profile_get", [_P, C.c_int, C.c_char_p, C.c_size_t, _D, C.POINTER(C.c_int64)])
 _sig("rb_problem_create_stencil", [_P, C.POINTER(StencilDesc), C.POINTER(_P)])
 _sig("rb_problem_set_rhs", [_P, C.c_int, _D])
 _sig("rb_problem_info", [_P, C.POINTER(C.c_int64), _I, _I])
@@ -117,6 +120,7 @@ _sig("rb_offline_build", [_P, _P, C.POINTER(GreedyOpts), C.c_int64, C.c_int, _D,
 
 EXPORTED = [
     "rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_version",
+    "rb_profile_enable", "rb_profile_reset", "rb_profile_get",
     "rb_problem_create_stencil", "rb_problem_set_rhs", "rb_problem_info", "rb_problem_destroy",
     "rb_basis_from_host", "rb_basis_info", "rb_basis_save", "rb_basis_load", "rb_basis_destroy",
     "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi", "rb_apply_batch",
@@ -158,6 +162,24 @@ class Context:
         _check(_lib.rb_ctx_create(device, sp, C.byref(h)))
         self.h = h
         self.device = device
+
+    def profile(self, on=True):
+        _check(_lib.rb_profile_enable(self.h, int(on)))
+
+    def profile_reset(self):
+        _check(_lib.rb_profile_reset(self.h))
+
+    def profile_totals(self):
+        """{kernel name: (total ms, launches)} accumulated while profiling was on."""
+        out = {}
+        i = 0
+        buf = C.create_string_buffer(64)
+        ms = C.c_double()
+        n = C.c_int64()
+        while _lib.rb_profile_get(self.h, i, buf, 64, C.byref(ms), C.byref(n)) == RB_OK:
+            out[buf.value.decode()] = (ms.value, n.value)
+            i += 1
+        return out
 
     def close(self):
         if self.h:

@@ -1,0 +1,71 @@
+"""GPU adaptive greedy (Alg. 4) against the oracle's greedy: same picks, same basis
+(up to the snapshot tolerance), orthonormal columns, and matching reduced operators."""
+import numpy as np
+import pytest
+
+from oracle import greedy as og
+from oracle import rb as orb
+from oracle.operator import BlockDiffusion
+from workloads import log_uniform_mu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+@pytest.mark.parametrize("indicator", ["l1", "residual"])
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3))])
+def test_greedy_matches_oracle(lib, ctx, indicator, dims, blocks):
+    op = BlockDiffusion(dims, blocks)
+    mus = log_uniform_mu(80, 24, op.Q, 0.1, 10.0)
+    n_max = 5
+    ref = og.adaptive_greedy(op, mus, n_max, indicator=indicator, snapshot_rtol=1e-12)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis, rep = lib.offline_build(ctx, prob, mus, mu=mus, n_max=n_max, indicator=indicator,
+                                   snapshot_rtol=1e-12)
+    assert rep["picks"] == ref.picks
+    W, AN, fN = basis.info()
+    assert np.abs(W @ W.T - np.eye(n_max)).max() <= 1e-13
+    for j in range(n_max):
+        assert np.linalg.norm(W[j] - ref.W[:, j]) <= 1e-7
+    assert np.abs(AN - ref.AN_q).max() <= 1e-7 * np.abs(ref.AN_q).max()
+    assert np.allclose(rep["max_indicator"], ref.max_indicator, rtol=1e-5, atol=1e-12)
+    assert rep["true_evals"] == n_max * len(mus)
+
+
+def test_greedy_degenerate_candidate_is_skipped(lib, ctx):
+    """A duplicated parameter gives a snapshot already in span(W): the greedy must skip
+    it (RB_EDEGENERATE inside) and take the next candidate."""
+    dims, blocks = (15, 15), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    mus = log_uniform_mu(81, 12, op.Q, 0.1, 10.0)
+    mus = np.vstack([mus, mus])   # every parameter twice
+    prob = lib.Problem(ctx, dims, blocks)
+    basis, rep = lib.offline_build(ctx, prob, mus, mu=mus, n_max=4, indicator="residual")
+    picks = rep["picks"]
+    assert len(set(picks)) == 4
+    assert len({p % 12 for p in picks}) == 4   # never a copy of an earlier pick
+    W, AN, fN = basis.info()
+    assert np.abs(W @ W.T - np.eye(4)).max() <= 1e-12
+
+
+def test_basis_save_load_roundtrip(lib, ctx, tmp_path):
+    dims, blocks = (15, 15), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    mus = log_uniform_mu(82, 10, op.Q, 0.1, 10.0)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis, rep = lib.offline_build(ctx, prob, mus, n_max=3, indicator="l1")
+    path = str(tmp_path / "basis.rb")
+    basis.save(path)
+    b2 = lib.Basis.load(ctx, prob, path)
+    W1, A1, f1 = basis.info()
+    W2, A2, f2 = b2.info()
+    assert np.array_equal(W1, W2)
+    assert np.abs(A1 - A2).max() <= 1e-12 * np.abs(A1).max()
+    theta = log_uniform_mu(83, 3, op.Q, 0.1, 10.0)
+    x1, s1 = lib.solve_batch(ctx, prob, basis, theta)
+    x2, s2 = lib.solve_batch(ctx, prob, b2, theta)
+    assert np.array_equal(s1.iters, s2.iters)
