@@ -3,7 +3,7 @@
 
 Workload (synthetic, seeded): 3D 7-point diffusion on a 127^3 interior grid
 (N = 2,048,383), kappa constant on 2x2x2 octants with mu log-uniform in [0.1, 10]
-(P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, L1
+(P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, residual
 indicator) over 256 training parameters; 256 test parameters per call.  A step is
 one rb_solve_batch of the 256 queries to relative residual 1e-10 (RBCG of Alg. 3,
 FP32 preconditioner, FP64 CG).  value = converged mu-solves per second.
@@ -45,7 +45,13 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--greedy", default="l1", choices=["l1", "residual"])
+    ap.add_argument("--greedy", default="residual", choices=["l1", "residual"])
+    ap.add_argument("--uneven", type=int, default=0,
+                    help="also time the uneven batch (1024 queries over four grids)")
+    ap.add_argument("--learned", type=int, default=0,
+                    help="also compare the surrogate-ranked greedy with the plain greedy")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run one device copy of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the queries are independent and the build "
@@ -56,6 +62,16 @@ def main():
     from paper_1804_06363_amd import rb
     from workloads import WORKLOADS
 
+    if args.copy_calib > 0:
+        # a plain copy of known size: the profiler's byte counters are scaled by what
+        # they read for this kernel
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib} MiB read + written")
+        del a, b
     w = WORKLOADS[args.workload]
     B = args.B or w.B
     N, Q = w.N, w.Q
@@ -133,6 +149,12 @@ def main():
     if args.cpu_baseline:
         cpu = cpu_baseline(basis, w, test[0])
 
+    extra = {}
+    if args.uneven:
+        extra["uneven_batch"] = uneven_leg(rb, torch)
+    if args.learned:
+        extra["learned_greedy"] = learned_leg(rb)
+
     out = {
         "metric": "mu-solves/sec to rel. residual 1e-10 (batched mixed RB-PCG)",
         "value": round(value, 2), "unit": "mu-solves/s", "n_gpus": 1, "steps": args.steps,
@@ -151,7 +173,87 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def uneven_leg(rb, torch):
+    """1024 queries mixing 2D 63^2, 255^2, 1023^2 (4x4 kappa blocks) and 3D 63^3 (2x2x2),
+    mu log-uniform in [0.01, 100], per-query basis sizes n in {10, 20, 40, 60} (leading
+    columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call."""
+    from workloads import UNEVEN_GRIDS, uneven_batch
+    ctx = rb.Context(0)
+    probs, bases = [], []
+    t0 = time.time()
+    for wk in UNEVEN_GRIDS:
+        pr = rb.Problem(ctx, wk.dims, wk.blocks)
+        tr = wk.train_mu()
+        b, _ = rb.offline_build(ctx, pr, tr, mu=tr, n_max=60, indicator="l1")
+        probs.append(pr)
+        bases.append(b)
+    log(f"uneven: four bases in {time.time() - t0:.1f}s")
+    qs = uneven_batch()
+    xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda:0") for g, _, _ in qs]
+    queries = [(g, nu, mu, None, x) for (g, nu, mu), x in zip(qs, xs)]
+    opts = rb.solve_opts(prec="fp32", flexible=True)
+    rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = rb.solve_multi(ctx, probs, bases, queries, opts=opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+    log(f"uneven: {len(qs)} queries in {el:.3f}s -> {ok / el:.1f} mu-solves/s, "
+        f"iters mean {st.iters.mean():.1f}, max rel res {st.rel_res_true.max():.2e}")
+    return {"value": round(ok / el, 2), "unit": "mu-solves/s", "queries": len(qs),
+            "converged": ok, "seconds": round(el, 4), "iters_mean": round(float(st.iters.mean()), 2),
+            "max_rel_res": float(st.rel_res_true.max())}
+
+
+def learned_leg(rb):
+    """Adaptive greedy on 3D 63^3 (P = 8, M = 1e4 training parameters log-uniform in
+    [0.1, 10]) to n = 60 with the plain residual sweep vs the MLP-ranked sweep; the
+    final bases are compared on 1000 held-out parameters by the largest residual
+    indicator, computed with the library's own FP64 path (one RBCG-free evaluation:
+    x_hat = W a(mu), residual by rb_apply_batch)."""
+    import torch
+    from workloads import WORKLOADS
+    w = WORKLOADS["3d63"]
+    ctx = rb.Context(0)
+    prob = rb.Problem(ctx, w.dims, w.blocks)
+    train = w.train_mu()
+    held = w.test_mu(1000)
+    res = {}
+    for name, kw in (("plain", {}), ("surrogate", dict(use_surrogate=1, topk=256, explore=64,
+                                                      warmup_full_sweeps=4, full_sweep_every=10,
+                                                      train_steps=50, lr=1e-3, mu_lo=0.1,
+                                                      mu_hi=10.0, seed=1004))):
+        basis, rep = rb.offline_build(ctx, prob, train, mu=train, n_max=w.n,
+                                      indicator="residual", **kw)
+        Wn, AN, fN = basis.info()
+        worst = held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch)
+        res[name] = {"seconds": round(rep["seconds"], 3), "true_evals": rep["true_evals"],
+                     "full_sweeps": rep["full_sweeps"], "fallbacks": rep["surrogate_fallbacks"],
+                     "held_out_max_eta": worst}
+        log(f"learned greedy [{name}]: {rep['seconds']:.2f}s, {rep['true_evals']} true "
+            f"evaluations, held-out max eta {worst:.3e}")
+    return res
+
+
+def held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch):
+    """max over held-out mu of ||f - A(mu) W a(mu)|| / ||f|| (a by a dense FP64 solve of
+    the n x n reduced system on the host, A(mu) applied by the library)."""
+    worst = 0.0
+    f = torch.ones(prob.N, dtype=torch.float64, device="cuda:0")
+    Wt = torch.from_numpy(np.ascontiguousarray(Wn)).cuda()
+    for i in range(0, len(held), 100):
+        th = held[i:i + 100]
+        a = np.stack([np.linalg.solve(np.tensordot(t, AN, axes=1), fN[0]) for t in th])
+        xh = (torch.from_numpy(a).cuda() @ Wt).contiguous()
+        Ax = rb.apply_batch(ctx, prob, th, xh)
+        eta = torch.linalg.norm(f[None, :] - Ax, dim=1) / torch.linalg.norm(f)
+        worst = max(worst, float(eta.max()))
+    return worst
 
 
 def cpu_baseline(basis, w, theta):

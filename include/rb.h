@@ -236,12 +236,35 @@ typedef struct {
   int64_t true_evals;      /* candidates whose true indicator was computed */
   int full_sweeps;
   double seconds;
-  double mlp_loss;         /* last training loss (surrogate) */
+  double mlp_loss;         /* last training loss (surrogate, standardised targets) */
+  int surrogate_fallbacks; /* surrogate steps that fell back to a full sweep */
 } rb_greedy_report;
 
 rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob, const rb_greedy_opts* opts,
                            int64_t M, int P, const double* mu, const double* theta,
                            const double* phi, rb_basis** out, rb_greedy_report* rep);
+
+/* ---- MLP surrogate of the greedy indicator (not in the paper) ----------------
+ * Diagnostics of the network rb_offline_build trains when use_surrogate is set.
+ * Network P -> H -> H -> 1 with exact-erf GELU; params is FP32 packed in the order
+ * W1 [H][P], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1] (H*P + H*H + 3H + 1 values).
+ * prec: RB_PREC_BF16 = every product on BF16 MFMA with FP32 accumulation (operands
+ * rounded to BF16 when loaded); RB_PREC_FP32 = FP32 MFMA.  Requires 1 <= P <= 64 and
+ * H a multiple of 16 in [16, 512].  X [m][P], y [m], out [m] host. */
+rb_status rb_mlp_forward(rb_ctx* ctx, int P, int H, rb_prec prec, const float* params, int m,
+                         const float* X, float* out);
+/* MSE loss mean_m (out_m - y_m)^2 and its gradient w.r.t. params (same packing). */
+rb_status rb_mlp_loss_grad(rb_ctx* ctx, int P, int H, rb_prec prec, const float* params, int m,
+                           const float* X, const float* y, float* loss, float* grad);
+/* `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8, bias-corrected) from
+ * params, updated in place; loss = loss after the last step. */
+rb_status rb_mlp_train(rb_ctx* ctx, int P, int H, rb_prec prec, float* params, int m,
+                       const float* X, const float* y, int steps, double lr, float* loss);
+/* Indices of the K largest v[m] among the entries with excluded[m] == 0 (excluded may be
+ * NULL), as a set: ties at the K-th value go to the lowest indices.  out [>= K] host,
+ * count = number written (min(K, available)). */
+rb_status rb_topk(rb_ctx* ctx, int M, int K, const float* v, const int* excluded, int* out,
+                  int* count);
 
 #ifdef __cplusplus
 }

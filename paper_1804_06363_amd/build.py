@@ -20,15 +20,15 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str = OUT, defines=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *FLAGS, *sources(), "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, *[f"-D{d}" for d in defines], *sources(), "-o", tmp]
     if verbose:
         print("[build]", " ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

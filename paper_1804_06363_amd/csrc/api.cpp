@@ -129,7 +129,7 @@ const void* rb_basis::shadow(rb_prec prec) {
   DevBuf& dst = prec == RB_PREC_FP32 ? W32 : W16;
   if (!dst.p) {
     const size_t es = prec == RB_PREC_FP32 ? sizeof(float) : sizeof(uint16_t);
-    dst.alloc(es * (size_t)std::max(n, 1) * ld);
+    dst.alloc(es * ((size_t)basis_rows(n) * ld + kBasisTail));
     if (n > 0) launch_cast(W64.as<double>(), dst.p, (int64_t)n * ld, prec, ctx->stream);
   }
   return dst.p;
@@ -359,7 +359,7 @@ void compute_reduced(rb_basis* bs, int j0) {
       launch_coef_tables(g, nn, th.as<double>(), nullptr, coef.as<double>(), st);
       // V_j = A_q w_{j0+j}
       launch_apply(g, ld, nn, coef.as<double>(), bs->W64.as<double>() + (size_t)j0 * ld,
-                   V.as<double>(), 0, nullptr, 0, nullptr, nullptr, nullptr, 4, st);
+                   V.as<double>(), 0, nullptr, 0, nullptr, nullptr, nullptr, st);
       // t[j][i] = w_i^T V_j for i < n
       launch_projection(pl, RB_PREC_FP64, V.as<double>(), ld, bs->W64.p, ld, n, nn, ones.as<int>(),
                         part.p, st);
@@ -411,7 +411,7 @@ static rb_basis* basis_upload(rb_ctx* ctx, const rb_problem* p, int n, const dou
   bs->prob = p;
   bs->n = n;
   bs->ld = p->ld;
-  bs->W64.alloc(sizeof(double) * (size_t)std::max(n, 1) * p->ld);
+  bs->W64.alloc(sizeof(double) * ((size_t)basis_rows(n) * p->ld + kBasisTail));
   if (n > 0) {
     DevBuf nat(sizeof(double) * (size_t)n * p->N);
     RB_HIP(hipMemcpy(nat.p, W, sizeof(double) * (size_t)n * p->N, hipMemcpyHostToDevice));
@@ -609,7 +609,7 @@ rb_status rb_apply_batch(rb_ctx* ctx, const rb_problem* p, int B, const double* 
     DevBuf us(sizeof(double) * (size_t)B * p->ld), ys(sizeof(double) * (size_t)B * p->ld);
     launch_to_storage(*p, B, u, p->N, us.as<double>(), p->ld, st);
     launch_apply(p->g, p->ld, B, coef.as<double>(), us.as<double>(), ys.as<double>(), 0, nullptr,
-                 0, nullptr, nullptr, nullptr, 4, st);
+                 0, nullptr, nullptr, nullptr, st);
     launch_from_storage(*p, B, ys.as<double>(), p->ld, y, p->N, st);
     RB_HIP(hipStreamSynchronize(st));
   });

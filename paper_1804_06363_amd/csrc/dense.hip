@@ -7,6 +7,8 @@
 //  * deterministic finalisation of per-block partial sums and the CG scalars of Alg. 3
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -51,7 +53,9 @@ __device__ __forceinline__ int acc_row(int g, int i) {
   return sizeof(TW) == 8 ? g + 4 * i : 4 * g + i;
 }
 
-template <typename TW, int QT, int JT>
+// PADDED: R has a multiple of 16*QT rows and W round_up(n, 16) rows, zero beyond B and
+// n, so the loads need no bounds checks (no branches between them).
+template <typename TW, int QT, int JT, bool PADDED>
 __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t r_ld,
                                           const TW* __restrict__ W, int64_t w_ld, int n,
                                           int q_base, int B, const int* __restrict__ active,
@@ -63,7 +67,7 @@ __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t 
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     const int q = q_base + 16 * t + qi;
-    if (q < B && active[q]) {
+    if (PADDED || (q < B && active[q])) {
       const double2* src = reinterpret_cast<const double2*>(R + (size_t)q * r_ld + kk);
       const double2 v0 = src[0], v1 = src[1];
       a[t][0] = v0.x; a[t][1] = v0.y; a[t][2] = v1.x; a[t][3] = v1.y;
@@ -76,7 +80,7 @@ __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t 
 #pragma unroll
     for (int u = 0; u < JT; ++u) {
       const int j = 16 * u + qi;
-      if (j < n) {
+      if (PADDED || j < n) {
         const double2* src = reinterpret_cast<const double2*>(W + (size_t)j * w_ld + kk);
         const double2 v0 = src[0], v1 = src[1];
         w[u][0] = v0.x; w[u][1] = v0.y; w[u][2] = v1.x; w[u][3] = v1.y;
@@ -96,7 +100,7 @@ __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t 
 #pragma unroll
     for (int u = 0; u < JT; ++u) {
       const int j = 16 * u + qi;
-      if (j < n) {
+      if (PADDED || j < n) {
         const float4 v = *reinterpret_cast<const float4*>(W + (size_t)j * w_ld + kk);
         w[u][0] = v.x; w[u][1] = v.y; w[u][2] = v.z; w[u][3] = v.w;
       } else {
@@ -116,7 +120,7 @@ __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t 
 #pragma unroll
     for (int u = 0; u < JT; ++u) {
       const int j = 16 * u + qi;
-      if (j < n) {
+      if (PADDED || j < n) {
         const uint2 v = *reinterpret_cast<const uint2*>(W + (size_t)j * w_ld + kk);
         w[u][0] = (short)(v.x & 0xffff); w[u][1] = (short)(v.x >> 16);
         w[u][2] = (short)(v.y & 0xffff); w[u][3] = (short)(v.y >> 16);
@@ -139,7 +143,7 @@ __device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t 
 // WSPLIT = true: the block's 4 waves split the DOF range of one query tile and are
 // reduced through LDS (small batches).  WSPLIT = false: the 4 waves own 4 query tiles
 // over the same DOF range (large batches).
-template <typename TW, int QT, int JT, bool WSPLIT>
+template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED>
 __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, int64_t r_ld,
                                                  const TW* __restrict__ W, int64_t w_ld, int n,
                                                  int B, int kend, int steps,
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
 #pragma unroll
     for (int u = 0; u < JT; ++u) acc[t][u] = Vec{0, 0, 0, 0};
   for (int k0 = k_begin; k0 < k_stop; k0 += 16)
-    proj_step<TW, QT, JT>(R, r_ld, W, w_ld, n, q_base, B, active, k0, acc);
+    proj_step<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active, k0, acc);
 
   const int qi = lane & 15, kg = lane >> 4;
   if (!WSPLIT) {
@@ -211,7 +215,9 @@ ProjPlan plan_projection(int N, int B, int n, int target_blocks) {
     p.qt = 1;
     p.qgroups = (B + 15) / 16;
     // steps per wave so that chunks*qgroups ~ target
-    int chunks_wanted = target_blocks / p.qgroups;
+    // one block per CU is enough for a GEMV-like pass; fewer chunks keep the
+    // finalising reduction short
+    int chunks_wanted = std::min(target_blocks, 256) / p.qgroups;
     if (chunks_wanted < 1) chunks_wanted = 1;
     p.steps = (nsteps + 4 * chunks_wanted - 1) / (4 * chunks_wanted);
     if (p.steps < 1) p.steps = 1;
@@ -238,11 +244,14 @@ static void launch_proj_t(const ProjPlan& pl, const double* R, int64_t r_ld, con
   using Acc = typename ProjTraits<TW>::Acc;
   const dim3 grid(pl.chunks, pl.qgroups);
   if (pl.wsplit)
-    hipLaunchKernelGGL((k_project<TW, QT, JT, true>), grid, dim3(256), 0, s, R, r_ld, W, w_ld, n,
-                       B, pl.kend, pl.steps, active, (Acc*)part);
+    hipLaunchKernelGGL((k_project<TW, QT, JT, true, false>), grid, dim3(256), 0, s, R, r_ld, W,
+                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
+  else if (pl.padded)
+    hipLaunchKernelGGL((k_project<TW, QT, JT, false, true>), grid, dim3(256), 0, s, R, r_ld, W,
+                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
   else
-    hipLaunchKernelGGL((k_project<TW, QT, JT, false>), grid, dim3(256), 0, s, R, r_ld, W, w_ld, n,
-                       B, pl.kend, pl.steps, active, (Acc*)part);
+    hipLaunchKernelGGL((k_project<TW, QT, JT, false, false>), grid, dim3(256), 0, s, R, r_ld, W,
+                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
 }
 
 template <typename TW, int QT>
@@ -323,6 +332,79 @@ __global__ __launch_bounds__(256) void k_prolong(const TW* __restrict__ W, int64
   }
 }
 
+// Batched prolongation on MFMA (FP32 / BF16 bases, B >= 16): the product
+// Z[q][pos] = sum_j e_q[j] W[j][pos] as 16x16 MFMA tiles with queries as rows and
+// nodes as columns, K = basis index in steps of 4 (v_mfma_f32_16x16x4f32; BF16 basis
+// entries widen exactly to FP32).  A block is 4 waves x 16 queries over a run of
+// 16*TP consecutive nodes: every wave writes 64*TP contiguous bytes per query row
+// (DRAM-friendly) and the block's waves share the W tile through L1.  Lane l supplies
+// e[q0 + l%16][j0 + l/16] and W[j0 + l/16][pos0 + 16p + l%16] and receives rows
+// 4(l/16)+i (queries) of column l%16 (node).  Blocks are remapped so that the query
+// groups of one node run sit on one XCD (their W tile is fetched once).
+template <typename TW, typename TO, int TP, bool ADD>
+__global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, int64_t w_ld, int n,
+                                                      const float* __restrict__ e, int e_ld, int B,
+                                                      const int* __restrict__ active,
+                                                      TO* __restrict__ out, int64_t o_ld, int lo,
+                                                      int hi, int qgroups) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // XCD-aware remap of the 1D grid: consecutive remapped ids share the node run
+  const int total = gridDim.x;
+  const int qd = total / 8, rd = total % 8;
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int id = xcd < rd ? xcd * (qd + 1) + slot : rd * (qd + 1) + (xcd - rd) * qd + slot;
+  const int run = id / qgroups, qg = id % qgroups;
+  const int pos0 = lo + run * 16 * TP;
+  const int q0 = (qg * 4 + wave) * 16;
+  const int r = lane & 15, g = lane >> 4;
+  floatx4 acc[TP];
+#pragma unroll
+  for (int p = 0; p < TP; ++p) acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // Loads are unconditional: the caller pads e to round_up(B, 64) zero rows and at
+  // least round_up(n, 4) columns, and W to round_up(n, 4) + 1 rows (zero beyond n),
+  // so every address is inside its buffer; columns pos >= hi are not stored.
+  for (int j0 = 0; j0 < n; j0 += 4) {
+    const int j = j0 + g;
+    const float ev = e[(size_t)(q0 + r) * e_ld + j];
+    const TW* wr = W + (size_t)j * w_ld + pos0 + r;
+#pragma unroll
+    for (int p = 0; p < TP; ++p) {
+      float wv;
+      if constexpr (sizeof(TW) == 2)
+        wv = rbk::bf16_to_f32(wr[16 * p]);
+      else
+        wv = (float)wr[16 * p];
+      acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev, wv, acc[p], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + 4 * g + i;
+    if (q >= B || !active[q]) continue;
+    TO* o = out + (size_t)q * o_ld + pos0 + r;
+#pragma unroll
+    for (int p = 0; p < TP; ++p) {
+      if (pos0 + 16 * p + r < hi) {
+        if (ADD)
+          o[16 * p] += (TO)acc[p][i];
+        else
+          o[16 * p] = (TO)acc[p][i];
+      }
+    }
+  }
+}
+
+template <typename TW, typename TO, bool ADD>
+static void launch_prolong_mfma(const TW* W, int64_t w_ld, int n, const float* e, int e_ld, int B,
+                                const int* active, TO* out, int64_t o_ld, int lo, int hi,
+                                hipStream_t s) {
+  constexpr int TP = 16;
+  const int runs = (hi - lo + 16 * TP - 1) / (16 * TP);
+  const int qgroups = (B + 63) / 64;
+  hipLaunchKernelGGL((k_prolong_mfma<TW, TO, TP, ADD>), dim3(runs * qgroups), dim3(256), 0, s, W,
+                     w_ld, n, e, e_ld, B, active, out, o_ld, lo, hi, qgroups);
+}
+
 template <typename TW, typename TA, typename TO, bool ADD>
 static void launch_prolong_t(const TW* W, int64_t w_ld, int n, const TA* e, int e_ld, int B,
                              const int* active, TO* out, int64_t o_ld, int lo, int hi,
@@ -345,6 +427,31 @@ void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const doub
     else
       launch_prolong_t<double, double, double, false>((const double*)W, w_ld, n, e64, e_ld, B,
                                                       active, (double*)out, o_ld, lo, hi, s);
+    return;
+  }
+  if (B >= 16) {
+#define PM(TW)                                                                                   \
+  if (out_is_double) {                                                                           \
+    if (add)                                                                                     \
+      launch_prolong_mfma<TW, double, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,         \
+                                            (double*)out, o_ld, lo, hi, s);                      \
+    else                                                                                         \
+      launch_prolong_mfma<TW, double, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,        \
+                                             (double*)out, o_ld, lo, hi, s);                     \
+  } else {                                                                                       \
+    if (add)                                                                                     \
+      launch_prolong_mfma<TW, float, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,          \
+                                           (float*)out, o_ld, lo, hi, s);                        \
+    else                                                                                         \
+      launch_prolong_mfma<TW, float, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,         \
+                                            (float*)out, o_ld, lo, hi, s);                       \
+  }
+    if (prec == RB_PREC_FP32) {
+      PM(float)
+    } else {
+      PM(uint16_t)
+    }
+#undef PM
     return;
   }
 #define PR(TW)                                                                                   \
@@ -624,6 +731,7 @@ __global__ __launch_bounds__(256) void k_reduce_solve(const Acc* __restrict__ pa
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int j = lane; j < nj; j += 64) {
     double s = 0.0;
+#pragma unroll 8
     for (int c = wave; c < chunks; c += 4) s += (double)part[((size_t)c * B + b) * nj + j];
     sh[wave][j] = s;
   }
@@ -863,11 +971,12 @@ __global__ __launch_bounds__(256) void k_init_rhs(const double* __restrict__ f, 
   const double s = rbk::block_sum_256(acc, sh);
   if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
-void launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
-                     int64_t ld, int B, double* part, int per_thread, hipStream_t s) {
+int launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
+                    int64_t ld, int B, double* part, int per_thread, hipStream_t s) {
   const int chunks = (N + 256 * per_thread - 1) / (256 * per_thread);
   hipLaunchKernelGGL(k_init_rhs, dim3(chunks, B), dim3(256), 0, s, f, f_ld, scale, N, r, ld, part,
                      per_thread);
+  return chunks;
 }
 
 // precision shadows of the basis (round to nearest even)

@@ -95,12 +95,35 @@ struct Profiler {
 };
 }  // namespace rb
 
+namespace rb {
+// Non-owning view of a device buffer.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+enum WsSlot {
+  WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
+  WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PR0, WS_PR1, WS_PB0, WS_PB1, WS_Q, WS_COUNT
+};
+}  // namespace rb
+
 struct rb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipDeviceProp_t prop{};
   rb::Profiler prof;
+  // Solver workspace, grown on demand and kept until the context is destroyed (one
+  // solver runs at a time per context).  Contents are not preserved between solves.
+  rb::DevBuf ws[rb::WS_COUNT];
+  rb::Buf get_ws(int slot, size_t bytes) {
+    if (ws[slot].bytes < bytes) {
+      (void)hipStreamSynchronize(stream);
+      ws[slot].alloc(bytes);
+    }
+    return rb::Buf{ws[slot].p, ws[slot].bytes};
+  }
 };
 
 namespace rb {

@@ -27,39 +27,53 @@ struct QState {
 
 struct ProjPlan {
   bool wsplit = false;
+  bool padded = false;  // R rows padded to a multiple of 64*qt (zero), W to round_up(n, 16)
   int qt = 1, jt = 1, nj = 16;
   int qgroups = 1, chunks = 1, steps = 1;
   int kend = 0;
 };
 
 // stencil.hip
-int stencil_chunks(int count, int per_thread);
+// rows allocated for a basis of n vectors: padded so that the batched contraction
+// kernels can read whole 16-row tiles plus one row of overrun without bounds checks;
+// allocations add kBasisTail elements so a 256-node run may overrun the last row.
+inline int basis_rows(int n) { return (n + 15) / 16 * 16 + 1; }
+constexpr size_t kBasisTail = 1024;
+// rows allocated for per-query vectors that the batched projection reads
+inline int padded_queries(int B) { return (B + 255) / 256 * 256; }
+
+// partial-sum chunks of a stencil pass over `count` storage positions
+int stencil_chunks(int count);
+// partial-sum chunks of an all-node stencil pass (apply, pass A/B, Jacobi)
+int stencil_chunks_all(int N);
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, int per_thread, hipStream_t s);
+                  const int* flag, double* part, hipStream_t s);
 template <typename TY>
 void launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                    int64_t y_ld, const double* p_old, double* p_new, const double* beta,
-                   const int* active, double* part, int per_thread, hipStream_t s);
+                   const int* active, double* part, hipStream_t s);
 void launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                    double* x, const double* r_in, double* r_out, const double* alpha,
-                   const int* active, double* part, int per_thread, hipStream_t s);
+                   const int* active, double* part, hipStream_t s);
 template <typename TY>
 void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
                      int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                      const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                     double* part1, int per_thread, hipStream_t s);
+                     double* part1, hipStream_t s);
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
                    int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                   double* part1, int per_thread, hipStream_t s);
+                   double* part1, hipStream_t s);
 
 // dense.hip
 ProjPlan plan_projection(int N, int B, int n, int target_blocks);
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
                        const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
                        hipStream_t s);
+// MFMA path (FP32/BF16, B >= 16): e must have round_up(B, 64) rows, zero beyond B, and
+// W basis_rows(n) rows plus kBasisTail elements, zero beyond n.
 void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const double* e64,
                     const float* e32, int e_ld, int B, const int* active, void* out,
                     bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s);
@@ -81,8 +95,9 @@ void launch_fin_sum(const double* part, int stride, int cnt, double* out, const 
                     int B, hipStream_t s);
 template <typename T>
 void launch_fill(T* dst, int64_t ld, int64_t n, int B, T value, hipStream_t s);
-void launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
-                     int64_t ld, int B, double* part, int per_thread, hipStream_t s);
+// returns the number of partial sums per query
+int launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
+                    int64_t ld, int B, double* part, int per_thread, hipStream_t s);
 void launch_cast(const double* src, void* dst, int64_t n, rb_prec prec, hipStream_t s);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
 void compute_reduced(rb_basis* bs, int j0);

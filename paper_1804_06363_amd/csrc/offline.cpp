@@ -56,9 +56,9 @@ GreedyState::GreedyState(rb_ctx* c, const rb_problem* p, const rb_greedy_opts& o
   bs->prob = p;
   bs->n = 0;
   bs->ld = p->ld;
-  bs->W64.alloc(sizeof(double) * (size_t)o.n_max * p->ld);
+  bs->W64.alloc(sizeof(double) * ((size_t)basis_rows(o.n_max) * p->ld + kBasisTail));
   w.alloc(sizeof(double) * p->ld);
-  const int ncN = stencil_chunks(p->g.N, 4);
+  const int ncN = stencil_chunks_all(p->g.N);
   part.alloc(sizeof(double) * (size_t)std::max(ncN, 1) * 8);
   // ||f||^2 of the shared right-hand side (R = 1); scaled by phi^2 per candidate
   const int nc = launch_dot(p->f.as<double>(), p->f.as<double>(), p->ld, p->g.N, 1,
@@ -182,7 +182,7 @@ void GreedyState::sweep(const std::vector<int>& idx) {
     DevBuf X(sizeof(double) * (size_t)CB * ld), Rv(sizeof(double) * (size_t)CB * ld);
     DevBuf coef(sizeof(double) * (size_t)CB * p->g.ct_size);
     DevBuf ones(sizeof(int) * CB), sc(sizeof(double) * CB), s2(sizeof(double) * CB);
-    const int ncN = stencil_chunks(p->g.N, 4);
+    const int ncN = stencil_chunks_all(p->g.N);
     DevBuf prt(sizeof(double) * (size_t)CB * ncN);
     launch_fill<int>(ones.as<int>(), 0, CB, 1, 1, st);
     std::vector<double> scale(CB), ss(CB);
@@ -198,7 +198,7 @@ void GreedyState::sweep(const std::vector<int>& idx) {
                      nullptr, a_ld, cb, ones.as<int>(), X.p, true, ld, 0, p->g.N, false, st);
       launch_coef_tables(p->g, cb, th_d + (size_t)c0 * Q, nullptr, coef.as<double>(), st);
       launch_apply(p->g, ld, cb, coef.as<double>(), X.as<double>(), Rv.as<double>(), 1,
-                   p->f.as<double>(), 0, sc.as<double>(), ones.as<int>(), prt.as<double>(), 4, st);
+                   p->f.as<double>(), 0, sc.as<double>(), ones.as<int>(), prt.as<double>(), st);
       launch_fin_sum(prt.as<double>(), ncN, ncN, s2.as<double>(), nullptr, cb, st);
       RB_HIP(hipMemcpyAsync(ss.data(), s2.p, sizeof(double) * cb, hipMemcpyDeviceToHost, st));
       RB_HIP(hipStreamSynchronize(st));
@@ -332,6 +332,7 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
       rep->seconds =
           std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       rep->mlp_loss = sur ? sur->last_loss : 0.0;
+      rep->surrogate_fallbacks = sur ? sur->fallbacks : 0;
     }
     *out = gs.bs.release();
     return RB_OK;

@@ -44,6 +44,7 @@ struct Surrogate {
   GreedyState& gs;
   int P;
   double last_loss = 0.0;
+  int fallbacks = 0;  // steps whose ranking check failed (full sweep instead)
   struct Impl;
   std::unique_ptr<Impl> impl;
   Surrogate(GreedyState& g, const double* mu, int P);

@@ -31,24 +31,23 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     }
   e_ld = std::max(16, (n + 15) / 16 * 16);
   y32 = opt.precond_prec != RB_PREC_FP64 && opt.solver != RB_SOLVER_RBI;
-  pt = g.N >= (1 << 20) ? 8 : 4;
-  cN = stencil_chunks(g.N, pt);
-  cR = stencil_chunks(g.NR, pt);
-  cB = stencil_chunks(g.N - g.NR, pt);
-  pstride = cN;
+  cN = stencil_chunks_all(g.N);
+  cR = stencil_chunks(g.NR);
+  cB = stencil_chunks(g.N - g.NR);
+  pstride = std::max(cN, std::max(cR, (g.N + 1023) / 1024));
   const int64_t L_ = ld();
   hipStream_t st = s();
 
   // per-query inputs
-  theta_d.alloc(sizeof(double) * B * Q);
+  theta_d = ctx->get_ws(WS_THETA, sizeof(double) * B * Q);
   RB_HIP(hipMemcpyAsync(theta_d.p, theta, sizeof(double) * B * Q, hipMemcpyHostToDevice, st));
   const int R = prob->R;
   std::vector<double> sc(B, 1.0);
   if (R == 1 && phi)
     for (int i = 0; i < B; ++i) sc[i] = phi[i];
-  scale_d.alloc(sizeof(double) * B);
+  scale_d = ctx->get_ws(WS_SCALE, sizeof(double) * B);
   RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-  nuse_d.alloc(sizeof(int) * B);
+  nuse_d = ctx->get_ws(WS_NUSE, sizeof(int) * B);
   RB_HIP(hipMemcpyAsync(nuse_d.p, nu.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
   if (R == 1) {
     f_base = prob->f.as<double>();
@@ -76,45 +75,51 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
   }
 
-  coef.alloc(sizeof(double) * B * g.ct_size);
+  coef = ctx->get_ws(WS_COEF, sizeof(double) * B * g.ct_size);
   launch_coef_tables(g, B, theta_d.as<double>(), nullptr, coef.as<double>(), st);
 
+  // projection plan first: for batches it reads residual rows in whole query tiles
+  if (n > 0) {
+    plan = plan_projection(g.N, B, n, 4 * ctx->prop.multiProcessorCount);
+    plan.padded = !plan.wsplit;
+  }
+  rrows = (n > 0 && plan.padded) ? plan.qgroups * 64 * plan.qt : B;
   // state vectors
   const size_t vb = sizeof(double) * (size_t)B * L_;
-  x.alloc(vb);
-  r0.alloc(vb);
+  const size_t vr = sizeof(double) * (size_t)rrows * L_;
+  x = ctx->get_ws(WS_X, vb);
+  r0 = ctx->get_ws(WS_R0, vr);
   if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
-    r1.alloc(vb);
+    r1 = ctx->get_ws(WS_R1, vr);
   if (opt.solver != RB_SOLVER_RBI) {
-    p0.alloc(vb);
-    p1.alloc(vb);
-    y.alloc((y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+    p0 = ctx->get_ws(WS_P0, vb);
+    p1 = ctx->get_ws(WS_P1, vb);
+    y = ctx->get_ws(WS_Y, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
     if (opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
-      z.alloc((y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+      z = ctx->get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
   }
-  part_m.alloc(sizeof(double) * (size_t)B * pstride);
-  part_r0.alloc(sizeof(double) * (size_t)B * pstride);
-  part_r1.alloc(sizeof(double) * (size_t)B * pstride);
-  part_b0.alloc(sizeof(double) * (size_t)B * pstride);
-  part_b1.alloc(sizeof(double) * (size_t)B * pstride);
+  part_m = ctx->get_ws(WS_PM, sizeof(double) * (size_t)B * pstride);
+  part_r0 = ctx->get_ws(WS_PR0, sizeof(double) * (size_t)B * pstride);
+  part_r1 = ctx->get_ws(WS_PR1, sizeof(double) * (size_t)B * pstride);
+  part_b0 = ctx->get_ws(WS_PB0, sizeof(double) * (size_t)B * pstride);
+  part_b1 = ctx->get_ws(WS_PB1, sizeof(double) * (size_t)B * pstride);
 
   // reduced basis data
   if (n > 0) {
     Wsh = const_cast<rb_basis*>(basis)->shadow(opt.precond_prec);
-    plan = plan_projection(g.N, B, n, 2 * ctx->prop.multiProcessorCount * 4);
     const size_t acc = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
-    projpart.alloc(acc * (size_t)plan.chunks * B * plan.nj);
-    L.alloc(sizeof(double) * (size_t)B * n * n);
-    // the prolongation reads e in groups of 8 queries: pad and zero the rows
-    const int Bp = (B + 7) / 8 * 8;
-    e64.alloc(sizeof(double) * (size_t)Bp * e_ld);
-    e32.alloc(sizeof(float) * (size_t)Bp * e_ld);
+    projpart = ctx->get_ws(WS_PROJ, acc * (size_t)plan.chunks * B * plan.nj);
+    L = ctx->get_ws(WS_L, sizeof(double) * (size_t)B * n * n);
+    // the prolongations read e in groups of up to 256 queries: pad and zero the rows
+    const int Bp = padded_queries(B);
+    e64 = ctx->get_ws(WS_E64, sizeof(double) * (size_t)Bp * e_ld);
+    e32 = ctx->get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
     launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
     launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
   }
 
   // per-query scalars
-  qbuf.alloc((sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
+  qbuf = ctx->get_ws(WS_Q, (sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
@@ -156,7 +161,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   if (opt.solver == RB_SOLVER_CG) {  // identity: y = r
     launch_jacobi<double>(g, B, coef.as<double>(), r, y.as<double>(), L_, 0.0, r, L_,
                           flex ? r_old : nullptr, L_, q.active, part_r0.as<double>(),
-                          flex ? part_r1.as<double>() : nullptr, pt, st);
+                          flex ? part_r1.as<double>() : nullptr, st);
     return;
   }
   const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
@@ -193,12 +198,12 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     if (y32)
       launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
                              flex ? r_old : nullptr, L_, q.active, dots ? (color ? pb0 : pr0) : nullptr,
-                             dots ? (color ? pb1 : pr1) : nullptr, pt, st);
+                             dots ? (color ? pb1 : pr1) : nullptr, st);
     else
       launch_gs_color<double>(g, color, B, coef.as<double>(), y.as<double>(), L_, r, L_, nullptr,
                               flex ? r_old : nullptr, L_, q.active,
                               dots ? (color ? pb0 : pr0) : nullptr,
-                              dots ? (color ? pb1 : pr1) : nullptr, pt, st);
+                              dots ? (color ? pb1 : pr1) : nullptr, st);
   };
   switch (opt.smoother) {
     case RB_SMOOTH_RBGS:
@@ -214,10 +219,10 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
       const double om = opt.smoother == RB_SMOOTH_JACOBI ? 2.0 / 3.0 : 0.0;
       if (y32)
         launch_jacobi<float>(g, B, coef.as<double>(), z.as<float>(), y.as<float>(), L_, om, r, L_,
-                             flex ? r_old : nullptr, L_, q.active, pr0, pr1, pt, st);
+                             flex ? r_old : nullptr, L_, q.active, pr0, pr1, st);
       else
         launch_jacobi<double>(g, B, coef.as<double>(), z.as<double>(), y.as<double>(), L_, om, r,
-                              L_, flex ? r_old : nullptr, L_, q.active, pr0, pr1, pt, st);
+                              L_, flex ? r_old : nullptr, L_, q.active, pr0, pr1, st);
     }
   }
 }
@@ -235,11 +240,11 @@ void BatchSolver::init_cg() {
   launch_fill<double>(x.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(p0.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(p1.as<double>(), L_, L_, B, 0.0, st);
-  launch_fill<double>(r0.as<double>(), L_, L_, B, 0.0, st);  // also zeroes the padding
-  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, B, 0.0, st);
-  launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_, B,
-                  part_m.as<double>(), pt, st);
-  launch_fin_sum(part_m.as<double>(), cN, cN, q.fnorm2, nullptr, B, st);
+  launch_fill<double>(r0.as<double>(), L_, L_, rrows, 0.0, st);  // also zeroes the padding
+  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, rrows, 0.0, st);
+  const int ci = launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_,
+                                 B, part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), ci, ci, q.fnorm2, nullptr, B, st);
   factor();
   launch_fill<int>(q.restart, 0, B, 1, 1, st);
   precondition(r0.as<double>(), nullptr);
@@ -263,17 +268,17 @@ void BatchSolver::iterate_cg(int k) {
   ProfScope ps(ctx, "pass_a");
   if (y32)
     launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
-                         q.beta, q.active, part_m.as<double>(), pt, st);
+                         q.beta, q.active, part_m.as<double>(), st);
   else
     launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, pold, pnew,
-                          q.beta, q.active, part_m.as<double>(), pt, st);
+                          q.beta, q.active, part_m.as<double>(), st);
   }
   launch_fin_alpha(part_m.as<double>(), cN, cN, q, B, st);
   // steps 6-7: x += alpha p, r -= alpha A p
   {
     ProfScope ps(ctx, "pass_b");
     launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
-                  part_m.as<double>(), pt, st);
+                  part_m.as<double>(), st);
   }
   // step 8
   const bool fixed = opt.fixed_iters > 0;
@@ -281,7 +286,7 @@ void BatchSolver::iterate_cg(int k) {
   if (!fixed) {
     ProfScope ps(ctx, "true_residual");
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
-                 scale_d.as<double>(), q.flag, part_m.as<double>(), pt, st);
+                 scale_d.as<double>(), q.flag, part_m.as<double>(), st);
     launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st);
   }
   // steps 9-10
@@ -318,11 +323,11 @@ void BatchSolver::init_rbi() {
   const int64_t L_ = ld();
   hipStream_t st = s();
   launch_fill<double>(x.as<double>(), L_, L_, B, 0.0, st);
-  launch_fill<double>(r0.as<double>(), L_, L_, B, 0.0, st);
-  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, B, 0.0, st);
-  launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_, B,
-                  part_m.as<double>(), pt, st);
-  launch_fin_sum(part_m.as<double>(), cN, cN, q.fnorm2, nullptr, B, st);
+  launch_fill<double>(r0.as<double>(), L_, L_, rrows, 0.0, st);
+  if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, rrows, 0.0, st);
+  const int ci = launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_,
+                                 B, part_m.as<double>(), pt, st);
+  launch_fin_sum(part_m.as<double>(), ci, ci, q.fnorm2, nullptr, B, st);
   factor();
 }
 
@@ -334,7 +339,7 @@ void BatchSolver::iterate_rbi(int k) {
   double* xc = x.as<double>();
   // step 2: r = f - A x, ||r||^2  (the active flags select the queries)
   launch_apply(g, L_, B, coef.as<double>(), xc, r0.as<double>(), 1, f_base, f_ld,
-               scale_d.as<double>(), q.active, part_m.as<double>(), pt, st);
+               scale_d.as<double>(), q.active, part_m.as<double>(), st);
   launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, q.active, B, st);
   // step 3
   const bool fixed = opt.fixed_iters > 0;
@@ -354,7 +359,7 @@ void BatchSolver::iterate_rbi(int k) {
   // step 7: x = S(A, f, x)
   auto sweep = [&](int color) {
     launch_gs_color<double>(g, color, B, coef.as<double>(), xc, L_, f_base, f_ld,
-                            scale_d.as<double>(), nullptr, 0, q.active, nullptr, nullptr, pt, st);
+                            scale_d.as<double>(), nullptr, 0, q.active, nullptr, nullptr, st);
   };
   switch (opt.smoother) {
     case RB_SMOOTH_RBGS:
@@ -370,7 +375,7 @@ void BatchSolver::iterate_rbi(int k) {
       RB_REQUIRE(f_ld == L_ || prob->R == 1, RB_EUNSUPPORTED, "Jacobi RBI");
       // x_new = x + omega D^-1 (f - A x) into r1, copied back into x
       launch_jacobi<double>(g, B, coef.as<double>(), xc, r1.as<double>(), L_, 2.0 / 3.0, f_base,
-                            f_ld, nullptr, 0, q.active, nullptr, nullptr, pt, st);
+                            f_ld, nullptr, 0, q.active, nullptr, nullptr, st);
       RB_HIP(hipMemcpyAsync(xc, r1.p, sizeof(double) * (size_t)B * L_, hipMemcpyDeviceToDevice,
                             st));
       break;
@@ -389,7 +394,7 @@ void BatchSolver::final_true_residual() {
   launch_fill<int>(ones.as<int>(), 0, B, 1, 1, st);
   double* tmp = r0.as<double>();
   launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), tmp, 1, f_base, f_ld,
-               scale_d.as<double>(), ones.as<int>(), part_m.as<double>(), pt, st);
+               scale_d.as<double>(), ones.as<int>(), part_m.as<double>(), st);
   launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, nullptr, B, st);
   RB_HIP(hipStreamSynchronize(st));
 }

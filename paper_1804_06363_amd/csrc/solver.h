@@ -19,18 +19,19 @@ struct BatchSolver {
   int B = 0;
   int n = 0;        // basis columns used (max over queries)
   int e_ld = 16;    // row stride of e
-  int pt = 4;       // nodes per thread in the stencil passes
+  const int pt = 4;  // nodes per thread of the init/dot kernels (matches stencil_chunks)
   int cN = 1, cR = 1, cB = 1;  // partial-sum chunks for all / red / black nodes
   int pstride = 1;             // per-query stride of the partial-sum arrays
   bool y32 = false;            // y stored in FP32
+  int rrows = 0;               // rows allocated for r (padded for the projection)
   ProjPlan plan;
   const void* Wsh = nullptr;   // basis in the preconditioner's precision
 
-  // device buffers
-  DevBuf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
-  DevBuf x, r0, r1, p0, p1, y, z;
-  DevBuf part_m, part_r0, part_r1, part_b0, part_b1;
-  DevBuf qbuf;  // QState arrays
+  // device buffers (views of the context's workspace)
+  Buf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
+  Buf x, r0, r1, p0, p1, y, z;
+  Buf part_m, part_r0, part_r1, part_b0, part_b1;
+  Buf qbuf;  // QState arrays
   QState q{};
   const double* f_base = nullptr;  // right-hand side term(s), storage order
   int64_t f_ld = 0;                // 0: one shared term scaled per query

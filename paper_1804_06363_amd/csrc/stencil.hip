@@ -15,6 +15,8 @@
 // contiguous ranges.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -76,18 +78,21 @@ void launch_coef_tables(const StencilGeom& g, int B, const double* theta, const 
 }
 
 // ---- per-node stencil geometry ---------------------------------------------------
+// nb[f] is the storage position of the neighbour across face f; at the boundary it is
+// the node itself (a valid address) and bit f of `inner` is clear, so the loaded value
+// is replaced by zero instead of the load being branched around: all the loads of a
+// node can be in flight together.
 template <int DIM>
 struct Node {
-  int L;            // lexicographic index
-  int nb[2 * DIM];  // storage positions of the neighbours (-1: boundary)
+  int nb[2 * DIM];  // storage positions of the neighbours (self at the boundary)
   int ci[2 * DIM];  // coefficient-table index of each face
+  unsigned inner;   // bit f: face f has an interior neighbour
 };
 
 template <int DIM>
 __device__ __forceinline__ void node_at(const StencilGeom& g, int pos, Node<DIM>& n) {
   const int c = pos >= g.NR;
   const int L = c ? 2 * (pos - g.NR) + 1 : 2 * pos;
-  n.L = L;
   const int other = c ? 0 : g.NR;
   int i, j = 0, k = 0;
   if (DIM == 1) {
@@ -105,268 +110,405 @@ __device__ __forceinline__ void node_at(const StencilGeom& g, int pos, Node<DIM>
   const uint32_t ty = DIM >= 2 ? g.tab[1][j] : 0u;
   const uint32_t tz = DIM >= 3 ? g.tab[2][k] : 0u;
   const int sx = tx & 0xff, sy = ty & 0xff, sz = tz & 0xff;
+  unsigned inner = 0;
   // x faces: tangential (y, z)
   n.ci[0] = g.ct_off[0] + ((int)((tx >> 8) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0] + sz;
   n.ci[1] = g.ct_off[0] + ((int)((tx >> 16) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0] + sz;
-  n.nb[0] = i > 0 ? other + ((L - 1) >> 1) : -1;
-  n.nb[1] = i < g.nx - 1 ? other + ((L + 1) >> 1) : -1;
+  const bool xl = i > 0, xh = i < g.nx - 1;
+  n.nb[0] = xl ? other + ((L - 1) >> 1) : pos;
+  n.nb[1] = xh ? other + ((L + 1) >> 1) : pos;
+  inner |= (xl ? 1u : 0u) | (xh ? 2u : 0u);
   if (DIM >= 2) {  // y faces: tangential (x, z)
     n.ci[2] = g.ct_off[1] + ((int)((ty >> 8) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1] + sz;
     n.ci[3] = g.ct_off[1] + ((int)((ty >> 16) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1] + sz;
-    n.nb[2] = j > 0 ? other + ((L - g.nx) >> 1) : -1;
-    n.nb[3] = j < g.ny - 1 ? other + ((L + g.nx) >> 1) : -1;
+    const bool yl = j > 0, yh = j < g.ny - 1;
+    n.nb[2] = yl ? other + ((L - g.nx) >> 1) : pos;
+    n.nb[3] = yh ? other + ((L + g.nx) >> 1) : pos;
+    inner |= (yl ? 4u : 0u) | (yh ? 8u : 0u);
   }
   if (DIM >= 3) {  // z faces: tangential (x, y)
     n.ci[4] = g.ct_off[2] + ((int)((tz >> 8) & 0xff) * g.ct_s1[2] + sx) * g.ct_s2[2] + sy;
     n.ci[5] = g.ct_off[2] + ((int)((tz >> 16) & 0xff) * g.ct_s1[2] + sx) * g.ct_s2[2] + sy;
-    n.nb[4] = k > 0 ? other + ((L - g.nxy) >> 1) : -1;
-    n.nb[5] = k < g.nz - 1 ? other + ((L + g.nxy) >> 1) : -1;
+    const bool zl = k > 0, zh = k < g.nz - 1;
+    n.nb[4] = zl ? other + ((L - g.nxy) >> 1) : pos;
+    n.nb[5] = zh ? other + ((L + g.nxy) >> 1) : pos;
+    inner |= (zl ? 16u : 0u) | (zh ? 32u : 0u);
   }
+  n.inner = inner;
 }
 
 // (A v)_p given a functor V(pos) returning the vector value at a storage position.
 template <int DIM, typename T, typename V>
 __device__ __forceinline__ T apply_at(const Node<DIM>& n, const T* __restrict__ cf, T vp,
                                       V val, T& diag) {
+  T vals[2 * DIM];
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) vals[f] = val(n.nb[f]);
   T d = T(0), off = T(0);
 #pragma unroll
   for (int f = 0; f < 2 * DIM; ++f) {
     const T c = cf[n.ci[f]];
     d += c;
-    if (n.nb[f] >= 0) off += c * val(n.nb[f]);
+    // select the value, not the coefficient: the self-load at the boundary may hold
+    // anything (0 * NaN would poison the sum)
+    off += c * (((n.inner >> f) & 1u) ? vals[f] : T(0));
   }
   diag = d;
   return d * vp - off;
 }
 
-// Loads the query's coefficient table into LDS (as T).
-template <typename T>
-__device__ __forceinline__ void load_coef(const StencilGeom& g, const double* coef, int b,
-                                          T* sh) {
-  const double* src = coef + (size_t)b * g.ct_size;
-  for (int e = threadIdx.x; e < g.ct_size; e += blockDim.x) sh[e] = (T)src[e];
-  __syncthreads();
+// ---- batched pass kernels -------------------------------------------------------------
+// Every pass below runs on a 1D grid of (query group) x (node chunk) blocks.  A block
+// owns QPB consecutive queries and kPT*256 consecutive storage positions: each thread
+// decodes the geometry of its nodes once and applies it to the QPB queries (their
+// loads are independent, which keeps many requests in flight).  Block ids are
+// remapped so that each XCD (blocks are dealt round-robin to the 8 XCDs) streams one
+// contiguous range of (group, chunk) pairs and finds the row/plane neighbours of its
+// nodes in its own L2.  Partial sums go to part[b][chunk] (stride = chunks).
+constexpr int kThreads = 256;
+#ifndef RB_KPT
+#define RB_KPT 4
+#endif
+#ifndef RB_KPH
+#define RB_KPH 2
+#endif
+#ifndef RB_QPB_MAX
+#define RB_QPB_MAX 8
+#endif
+constexpr int kPT = RB_KPT;  // positions per thread in the one-colour passes
+constexpr int kPH = RB_KPH;  // positions per thread and colour in the all-node passes
+constexpr int kXCD = 8;
+
+// All-node passes: chunk c holds red positions [c*CH, (c+1)*CH) and the black positions
+// NR + [c*CH, (c+1)*CH) (CH = 256*kPH), so the red and black neighbours of a node are
+// loaded by the same block and the plane neighbours by the chunks next to it.
+__device__ __forceinline__ int paired_pos(const StencilGeom& g, int chunk, int t) {
+  const int half = t / kPH, u = t % kPH;
+  const int off = chunk * kThreads * kPH + u * kThreads + (int)threadIdx.x;
+  if (half == 0) return off < g.NR ? off : -1;
+  return g.NR + off < g.N ? g.NR + off : -1;
 }
 
-constexpr int kThreads = 256;
-constexpr int kMaxCoef = 1024;  // doubles per query table (host checks)
+__device__ __forceinline__ int xcd_remap(int b, int total) {
+  const int q = total / kXCD, r = total % kXCD;
+  const int xcd = b % kXCD, slot = b / kXCD;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
 
-// ---- y = A(theta) u, plus optional ||rhs - A u||^2 ------------------------------
-// Grid: (chunks, B).  mode 0: y = A u.  mode 1: y = rhs - A u for queries with
-// flag[b] != 0 (others skipped), partial sums of y^2 in part[b][chunk].
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, const double* coef,
+struct Tile {
+  int chunk, q0;
+};
+__device__ __forceinline__ Tile tile_of(int chunks) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  return Tile{blk % chunks, (blk / chunks)};
+}
+
+// Loads the coefficient tables of queries q0..q0+QPB-1 into LDS (as T); returns the
+// mask of queries that exist and are active.
+template <int QPB, typename T>
+__device__ __forceinline__ unsigned load_group(const StencilGeom& g, const double* coef, int q0,
+                                               int B, const int* active, T* sh) {
+  unsigned mask = 0;
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) {
+    const int b = q0 + k;
+    if (b < B && (!active || active[b])) mask |= 1u << k;
+  }
+  if (mask)
+    for (int e = threadIdx.x; e < QPB * g.ct_size; e += blockDim.x) {
+      const int k = e / g.ct_size;
+      sh[e] = (q0 + k < B) ? (T)coef[(size_t)(q0 + k) * g.ct_size + (e - k * g.ct_size)] : T(0);
+    }
+  __syncthreads();
+  return mask;
+}
+
+template <int QPB>
+__device__ __forceinline__ void store_partials(const double (&acc)[QPB], unsigned mask, int q0,
+                                               int chunk, int chunks, double* part,
+                                               double* red /* 4*QPB */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) {
+    const double v = rbk::wave_sum(acc[k]);
+    if (lane == 0) red[k * 4 + w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < QPB && ((mask >> threadIdx.x) & 1u)) {
+    const int k = threadIdx.x;
+    part[(size_t)(q0 + k) * chunks + chunk] =
+        (red[k * 4 + 0] + red[k * 4 + 1]) + (red[k * 4 + 2] + red[k * 4 + 3]);
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T diag_of(const Node<DIM>& n, const T* cf) {
+  T d = T(0);
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) d += cf[n.ci[f]];
+  return d;
+}
+
+// ---- y = A(theta) u, or y = rhs - A u with partial ||y||^2 ------------------------------
+// mode 0: y = A u for every query.  mode 1: y = rhs_scale[b] * rhs_b - A u for queries
+// with flag[b] != 0 (others untouched) and partial sums of y^2.
+template <int DIM, int QPB>
+__global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, int B, int chunks,
+                                                    const double* coef,
                                                     const double* __restrict__ u,
                                                     double* __restrict__ y, int mode,
                                                     const double* __restrict__ rhs,
-                                                    int64_t rhs_ld, const double* __restrict__ rhs_scale,
+                                                    int64_t rhs_ld,
+                                                    const double* __restrict__ rhs_scale,
                                                     const int* __restrict__ flag,
-                                                    double* __restrict__ part, int per_thread) {
-  __shared__ double cf[kMaxCoef];
-  __shared__ double red[4];
-  const int b = blockIdx.y;
-  if (mode == 1 && flag[b] == 0) return;
-  load_coef(g, coef, b, cf);
-  const double* ub = u + (size_t)b * ld;
-  double* yb = y + (size_t)b * ld;
-  const double* fb = mode == 1 ? rhs + (size_t)b * rhs_ld : nullptr;
-  const double fs = mode == 1 ? rhs_scale[b] : 0.0;
-  double acc = 0.0;
-  const int base = blockIdx.x * kThreads * per_thread;
-  for (int t = 0; t < per_thread; ++t) {
-    const int pos = base + t * kThreads + threadIdx.x;
-    if (pos >= g.N) break;
-    Node<DIM> n;
-    node_at<DIM>(g, pos, n);
-    double d;
-    const double Au = apply_at<DIM, double>(n, cf, ub[pos], [&](int q) { return ub[q]; }, d);
-    if (mode == 0) {
-      yb[pos] = Au;
-    } else {
-      const double r = fs * fb[pos] - Au;
-      yb[pos] = r;
-      acc += r * r;
+                                                    double* __restrict__ part) {
+  extern __shared__ double dyn[];
+  __shared__ double red[4 * QPB];
+  const Tile tl = tile_of(chunks);
+  const int q0 = tl.q0 * QPB;
+  const unsigned mask = load_group<QPB>(g, coef, q0, B, mode == 1 ? flag : nullptr, dyn);
+  if (!mask) return;
+  double acc[QPB];
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2 * kPH; ++t) {
+    const int pos = paired_pos(g, tl.chunk, t);
+    if (pos >= 0) {
+      Node<DIM> n;
+      node_at<DIM>(g, pos, n);
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const double* cf = dyn + k * g.ct_size;
+        const double* ub = u + (size_t)(q0 + k) * ld;
+        double d;
+        const double Au = apply_at<DIM, double>(n, cf, ub[pos], [&](int s) { return ub[s]; }, d);
+        if (mode == 0) {
+          y[(size_t)(q0 + k) * ld + pos] = Au;
+        } else {
+          const double r = rhs_scale[q0 + k] * rhs[(size_t)(q0 + k) * rhs_ld + pos] - Au;
+          y[(size_t)(q0 + k) * ld + pos] = r;
+          acc[k] += r * r;
+        }
+      }
     }
   }
-  if (mode == 1) {
-    const double s = rbk::block_sum_256(acc, red);
-    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
-  }
+  if (mode == 1) store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
 }
 
-// ---- pass A: p_new = y + beta p_old; q = A p_new; partial p_new^T q -------------
-template <int DIM, typename TY>
-__global__ __launch_bounds__(kThreads) void k_pass_a(StencilGeom g, int64_t ld, const double* coef,
+// ---- pass A: p_new = y + beta p_old; q = A p_new; partial p_new^T q -------------------
+template <int DIM, int QPB, typename TY>
+__global__ __launch_bounds__(kThreads) void k_pass_a(StencilGeom g, int64_t ld, int B, int chunks,
+                                                     const double* coef,
                                                      const TY* __restrict__ y, int64_t y_ld,
                                                      const double* __restrict__ p_old,
                                                      double* __restrict__ p_new,
                                                      const double* __restrict__ beta,
                                                      const int* __restrict__ active,
-                                                     double* __restrict__ part, int per_thread) {
-  __shared__ double cf[kMaxCoef];
-  __shared__ double red[4];
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  load_coef(g, coef, b, cf);
-  const double be = beta[b];
-  const TY* yb = y + (size_t)b * y_ld;
-  const double* po = p_old + (size_t)b * ld;
-  double* pn = p_new + (size_t)b * ld;
-  double acc = 0.0;
-  const int base = blockIdx.x * kThreads * per_thread;
-  for (int t = 0; t < per_thread; ++t) {
-    const int pos = base + t * kThreads + threadIdx.x;
-    if (pos >= g.N) break;
-    Node<DIM> n;
-    node_at<DIM>(g, pos, n);
-    const double pp = (double)yb[pos] + be * po[pos];
-    double d;
-    const double q = apply_at<DIM, double>(
-        n, cf, pp, [&](int s) { return (double)yb[s] + be * po[s]; }, d);
-    pn[pos] = pp;
-    acc += pp * q;
+                                                     double* __restrict__ part) {
+  extern __shared__ double dyn[];
+  __shared__ double red[4 * QPB];
+  const Tile tl = tile_of(chunks);
+  const int q0 = tl.q0 * QPB;
+  const unsigned mask = load_group<QPB>(g, coef, q0, B, active, dyn);
+  if (!mask) return;
+  double acc[QPB], be[QPB];
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) {
+    acc[k] = 0.0;
+    be[k] = ((mask >> k) & 1u) ? beta[q0 + k] : 0.0;
   }
-  const double s = rbk::block_sum_256(acc, red);
-  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+  for (int t = 0; t < 2 * kPH; ++t) {
+    const int pos = paired_pos(g, tl.chunk, t);
+    if (pos >= 0) {
+      Node<DIM> n;
+      node_at<DIM>(g, pos, n);
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const double* cf = dyn + k * g.ct_size;
+        const TY* yb = y + (size_t)(q0 + k) * y_ld;
+        const double* po = p_old + (size_t)(q0 + k) * ld;
+        const double b_ = be[k];
+        const double pp = (double)yb[pos] + b_ * po[pos];
+        double d;
+        const double q = apply_at<DIM, double>(
+            n, cf, pp, [&](int s) { return (double)yb[s] + b_ * po[s]; }, d);
+        p_new[(size_t)(q0 + k) * ld + pos] = pp;
+        acc[k] += pp * q;
+      }
+    }
+  }
+  store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
 }
 
-// ---- pass B: x += alpha p; r_out = r_in - alpha A p; partial ||r_out||^2 ----------
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, const double* coef,
+// ---- pass B: x += alpha p; r_out = r_in - alpha A p; partial ||r_out||^2 ----------------
+template <int DIM, int QPB>
+__global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, int B, int chunks,
+                                                     const double* coef,
                                                      const double* __restrict__ p,
                                                      double* __restrict__ x,
                                                      const double* r_in, double* r_out,
                                                      const double* __restrict__ alpha,
                                                      const int* __restrict__ active,
-                                                     double* __restrict__ part, int per_thread) {
-  __shared__ double cf[kMaxCoef];
-  __shared__ double red[4];
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  load_coef(g, coef, b, cf);
-  const double al = alpha[b];
-  const double* pb = p + (size_t)b * ld;
-  double* xb = x + (size_t)b * ld;
-  const double* ri = r_in + (size_t)b * ld;
-  double* ro = r_out + (size_t)b * ld;
-  double acc = 0.0;
-  const int base = blockIdx.x * kThreads * per_thread;
-  for (int t = 0; t < per_thread; ++t) {
-    const int pos = base + t * kThreads + threadIdx.x;
-    if (pos >= g.N) break;
-    Node<DIM> n;
-    node_at<DIM>(g, pos, n);
-    const double pp = pb[pos];
-    double d;
-    const double q = apply_at<DIM, double>(n, cf, pp, [&](int s) { return pb[s]; }, d);
-    xb[pos] += al * pp;
-    const double r = ri[pos] - al * q;
-    ro[pos] = r;
-    acc += r * r;
+                                                     double* __restrict__ part) {
+  extern __shared__ double dyn[];
+  __shared__ double red[4 * QPB];
+  const Tile tl = tile_of(chunks);
+  const int q0 = tl.q0 * QPB;
+  const unsigned mask = load_group<QPB>(g, coef, q0, B, active, dyn);
+  if (!mask) return;
+  double acc[QPB], al[QPB];
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) {
+    acc[k] = 0.0;
+    al[k] = ((mask >> k) & 1u) ? alpha[q0 + k] : 0.0;
   }
-  const double s = rbk::block_sum_256(acc, red);
-  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+  for (int t = 0; t < 2 * kPH; ++t) {
+    const int pos = paired_pos(g, tl.chunk, t);
+    if (pos >= 0) {
+      Node<DIM> n;
+      node_at<DIM>(g, pos, n);
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const double* cf = dyn + k * g.ct_size;
+        const size_t o = (size_t)(q0 + k) * ld;
+        const double* pb = p + o;
+        const double pp = pb[pos];
+        double d;
+        const double q = apply_at<DIM, double>(n, cf, pp, [&](int s) { return pb[s]; }, d);
+        x[o + pos] += al[k] * pp;
+        const double r = r_in[o + pos] - al[k] * q;
+        r_out[o + pos] = r;
+        acc[k] += r * r;
+      }
+    }
+  }
+  store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
 }
 
-// ---- one colour half-sweep of Gauss-Seidel on A y = rhs ---------------------------
+// ---- one colour half-sweep of Gauss-Seidel on A y = rhs ---------------------------------
 // For every node of colour `color`: y_p = (rhs_p - sum_nb A_p,nb y_nb) / A_pp with
-// A_p,nb = -c_f (the neighbours all have the other colour).  rhs_b = rhs_scale[b] * rhs[b*rhs_ld + p].
-// Partial sums over the updated nodes: y_p rhs_p (dot0) and y_p rhs2_p (dot1).
-template <int DIM, typename TY>
-__global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color, const double* coef,
+// A_p,nb = -c_f (the neighbours all have the other colour).  rhs_b = rhs_scale[b] *
+// rhs[b*rhs_ld + p].  Partial sums over the updated nodes: y_p rhs_p (part0) and
+// y_p rhs2_p (part1).  Arithmetic in TY (the smoother's precision).
+template <int DIM, int QPB, typename TY>
+__global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color, int B, int chunks,
+                                                       const double* coef,
                                                        TY* __restrict__ y, int64_t y_ld,
-                                                       const double* __restrict__ rhs, int64_t rhs_ld,
+                                                       const double* __restrict__ rhs,
+                                                       int64_t rhs_ld,
                                                        const double* __restrict__ rhs_scale,
                                                        const double* __restrict__ rhs2,
                                                        int64_t rhs2_ld,
                                                        const int* __restrict__ active,
                                                        double* __restrict__ part0,
-                                                       double* __restrict__ part1,
-                                                       int per_thread) {
-  using TC = TY;  // coefficient arithmetic in the smoother's precision
-  __shared__ TC cf[kMaxCoef];
-  __shared__ double red[4];
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  load_coef(g, coef, b, cf);
-  TY* yb = y + (size_t)b * y_ld;
-  const double* fb = rhs + (size_t)b * rhs_ld;
-  const double fs = rhs_scale ? rhs_scale[b] : 1.0;
-  const double* f2 = rhs2 ? rhs2 + (size_t)b * rhs2_ld : nullptr;
+                                                       double* __restrict__ part1) {
+  extern __shared__ double dyn[];
+  TY* cfs = reinterpret_cast<TY*>(dyn);
+  __shared__ double red[4 * QPB];
+  const Tile tl = tile_of(chunks);
+  const int q0 = tl.q0 * QPB;
+  const unsigned mask = load_group<QPB>(g, coef, q0, B, active, cfs);
+  if (!mask) return;
   const int lo = color ? g.NR : 0;
   const int hi = color ? g.N : g.NR;
-  double a0 = 0.0, a1 = 0.0;
-  const int base = lo + blockIdx.x * kThreads * per_thread;
-  for (int t = 0; t < per_thread; ++t) {
-    const int pos = base + t * kThreads + threadIdx.x;
-    if (pos >= hi) break;
-    Node<DIM> n;
-    node_at<DIM>(g, pos, n);
-    TC d = TC(0), off = TC(0);
+  double a0[QPB], a1[QPB], fsc[QPB];
 #pragma unroll
-    for (int f = 0; f < 2 * DIM; ++f) {
-      const TC c = cf[n.ci[f]];
-      d += c;
-      if (n.nb[f] >= 0) off += c * yb[n.nb[f]];
+  for (int k = 0; k < QPB; ++k) {
+    a0[k] = a1[k] = 0.0;
+    fsc[k] = (rhs_scale && ((mask >> k) & 1u)) ? rhs_scale[q0 + k] : 1.0;
+  }
+  const int base = lo + tl.chunk * kThreads * kPT;
+#pragma unroll
+  for (int t = 0; t < kPT; ++t) {
+    const int pos = base + t * kThreads + threadIdx.x;
+    if (pos < hi) {
+      Node<DIM> n;
+      node_at<DIM>(g, pos, n);
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const TY* cf = cfs + k * g.ct_size;
+        TY* yb = y + (size_t)(q0 + k) * y_ld;
+        TY nv[2 * DIM];
+#pragma unroll
+        for (int f = 0; f < 2 * DIM; ++f) nv[f] = yb[n.nb[f]];
+        TY d = TY(0), off = TY(0);
+#pragma unroll
+        for (int f = 0; f < 2 * DIM; ++f) {
+          const TY c = cf[n.ci[f]];
+          d += c;
+          off += c * (((n.inner >> f) & 1u) ? nv[f] : TY(0));
+        }
+        const double fp = fsc[k] * rhs[(size_t)(q0 + k) * rhs_ld + pos];
+        const TY v = (TY)(((TY)fp + off) / d);
+        yb[pos] = v;
+        a0[k] += (double)v * fp;
+        if (rhs2) a1[k] += (double)v * rhs2[(size_t)(q0 + k) * rhs2_ld + pos];
+      }
     }
-    // the off-diagonal entries of A are -c: y_p = (rhs_p + sum_nb c y_nb) / d_p
-    const double fp = fs * fb[pos];
-    const TY v = (TY)(((TC)fp + off) / d);
-    yb[pos] = v;
-    a0 += (double)v * fp;
-    if (f2) a1 += (double)v * f2[pos];
   }
-  if (part0) {
-    const double s0 = rbk::block_sum_256(a0, red);
-    if (threadIdx.x == 0) part0[(size_t)b * gridDim.x + blockIdx.x] = s0;
-  }
+  if (part0) store_partials<QPB>(a0, mask, q0, tl.chunk, chunks, part0, red);
   if (part1) {
-    const double s1 = rbk::block_sum_256(a1, red);
-    if (threadIdx.x == 0) part1[(size_t)b * gridDim.x + blockIdx.x] = s1;
+    __syncthreads();
+    store_partials<QPB>(a1, mask, q0, tl.chunk, chunks, part1, red);
   }
 }
 
-// ---- damped Jacobi: y = z + omega D^-1 (rhs - A z), partial y^T rhs (and y^T rhs2)
-template <int DIM, typename TY>
-__global__ __launch_bounds__(kThreads) void k_jacobi(StencilGeom g, const double* coef,
-                                                     const TY* __restrict__ z, TY* __restrict__ y,
-                                                     int64_t y_ld, double omega,
-                                                     const double* __restrict__ rhs, int64_t rhs_ld,
-                                                     const double* __restrict__ rhs2, int64_t rhs2_ld,
+// ---- damped Jacobi: y = z + omega D^-1 (rhs - A z), partial y^T rhs (and y^T rhs2) ------
+template <int DIM, int QPB, typename TY>
+__global__ __launch_bounds__(kThreads) void k_jacobi(StencilGeom g, int B, int chunks,
+                                                     const double* coef,
+                                                     const TY* __restrict__ z,
+                                                     TY* __restrict__ y, int64_t y_ld,
+                                                     double omega,
+                                                     const double* __restrict__ rhs,
+                                                     int64_t rhs_ld,
+                                                     const double* __restrict__ rhs2,
+                                                     int64_t rhs2_ld,
                                                      const int* __restrict__ active,
                                                      double* __restrict__ part0,
-                                                     double* __restrict__ part1, int per_thread) {
-  __shared__ TY cf[kMaxCoef];
-  __shared__ double red[4];
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  load_coef(g, coef, b, cf);
-  const TY* zb = z + (size_t)b * y_ld;
-  TY* yb = y + (size_t)b * y_ld;
-  const double* fb = rhs + (size_t)b * rhs_ld;
-  const double* f2 = rhs2 ? rhs2 + (size_t)b * rhs2_ld : nullptr;
-  double a0 = 0.0, a1 = 0.0;
-  const int base = blockIdx.x * kThreads * per_thread;
-  for (int t = 0; t < per_thread; ++t) {
-    const int pos = base + t * kThreads + threadIdx.x;
-    if (pos >= g.N) break;
-    Node<DIM> n;
-    node_at<DIM>(g, pos, n);
-    TY d;
-    const TY Az = apply_at<DIM, TY>(n, cf, zb[pos], [&](int s) { return zb[s]; }, d);
-    const double fp = fb[pos];
-    const TY v = zb[pos] + (TY)omega * (((TY)fp - Az) / d);
-    yb[pos] = v;
-    a0 += (double)v * fp;
-    if (f2) a1 += (double)v * f2[pos];
+                                                     double* __restrict__ part1) {
+  extern __shared__ double dyn[];
+  TY* cfs = reinterpret_cast<TY*>(dyn);
+  __shared__ double red[4 * QPB];
+  const Tile tl = tile_of(chunks);
+  const int q0 = tl.q0 * QPB;
+  const unsigned mask = load_group<QPB>(g, coef, q0, B, active, cfs);
+  if (!mask) return;
+  double a0[QPB], a1[QPB];
+#pragma unroll
+  for (int k = 0; k < QPB; ++k) a0[k] = a1[k] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2 * kPH; ++t) {
+    const int pos = paired_pos(g, tl.chunk, t);
+    if (pos >= 0) {
+      Node<DIM> n;
+      node_at<DIM>(g, pos, n);
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const TY* cf = cfs + k * g.ct_size;
+        const TY* zb = z + (size_t)(q0 + k) * y_ld;
+        TY d;
+        const TY Az = apply_at<DIM, TY>(n, cf, zb[pos], [&](int s) { return zb[s]; }, d);
+        const double fp = rhs[(size_t)(q0 + k) * rhs_ld + pos];
+        const TY v = zb[pos] + (TY)omega * (((TY)fp - Az) / d);
+        y[(size_t)(q0 + k) * y_ld + pos] = v;
+        a0[k] += (double)v * fp;
+        if (rhs2) a1[k] += (double)v * rhs2[(size_t)(q0 + k) * rhs2_ld + pos];
+      }
+    }
   }
-  if (part0) {
-    const double s0 = rbk::block_sum_256(a0, red);
-    if (threadIdx.x == 0) part0[(size_t)b * gridDim.x + blockIdx.x] = s0;
-  }
+  if (part0) store_partials<QPB>(a0, mask, q0, tl.chunk, chunks, part0, red);
   if (part1) {
-    const double s1 = rbk::block_sum_256(a1, red);
-    if (threadIdx.x == 0) part1[(size_t)b * gridDim.x + blockIdx.x] = s1;
+    __syncthreads();
+    store_partials<QPB>(a1, mask, q0, tl.chunk, chunks, part1, red);
   }
 }
 
@@ -406,97 +548,127 @@ void launch_from_storage(const rb_problem& p, int B, const double* sto, int64_t 
 }
 
 // ---- launchers -----------------------------------------------------------------------
-int stencil_chunks(int count, int per_thread) {
-  const int per_block = kThreads * per_thread;
-  return (count + per_block - 1) / per_block;
+int stencil_chunks(int count) { return (count + kThreads * kPT - 1) / (kThreads * kPT); }
+int stencil_chunks_all(int N) {
+  const int NR = (N + 1) / 2;
+  return (NR + kThreads * kPH - 1) / (kThreads * kPH);
 }
 
-#define RB_DIM_DISPATCH(dim, F) \
-  switch (dim) {                \
-    case 1: F(1); break;        \
-    case 2: F(2); break;        \
-    default: F(3); break;       \
+// queries per block: up to `cap` while the group's tables stay within 16 KB of LDS.
+// Measured on the 127^3 workload (B = 256): pass A (two arrays read at the
+// neighbours) is fastest with 1-2 queries per block, the one-colour sweeps with 4.
+static int pick_qpb(const StencilGeom& g, int B, int tsize, int cap = 4) {
+  int q = cap < RB_QPB_MAX ? cap : RB_QPB_MAX;
+  while (q > 1 && (q > B || q * g.ct_size * tsize > 16384)) q >>= 1;
+  return q;
+}
+
+template <typename F>
+static void dispatch(int dim, int qpb, F&& f) {
+#define RB_Q(D)                                                    \
+  switch (qpb) {                                                   \
+    case 8: f(std::integral_constant<int, D>{}, std::integral_constant<int, 8>{}); break; \
+    case 4: f(std::integral_constant<int, D>{}, std::integral_constant<int, 4>{}); break; \
+    case 2: f(std::integral_constant<int, D>{}, std::integral_constant<int, 2>{}); break; \
+    default: f(std::integral_constant<int, D>{}, std::integral_constant<int, 1>{}); break; \
   }
+  switch (dim) {
+    case 1: RB_Q(1) break;
+    case 2: RB_Q(2) break;
+    default: RB_Q(3) break;
+  }
+#undef RB_Q
+}
+
+static dim3 grid_for(int chunks, int B, int qpb) {
+  const long total = (long)chunks * ((B + qpb - 1) / qpb);
+  return dim3((unsigned)total);
+}
 
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, int per_thread, hipStream_t s) {
-  const dim3 grid(stencil_chunks(g.N, per_thread), B);
-#define F(D)                                                                                 \
-  hipLaunchKernelGGL(k_apply<D>, grid, dim3(kThreads), 0, s, g, ld, coef, u, y, mode, rhs, \
-                     rhs_ld, rhs_scale, flag, part, per_thread)
-  RB_DIM_DISPATCH(g.dim, F)
-#undef F
+                  const int* flag, double* part, hipStream_t s) {
+  const int chunks = stencil_chunks_all(g.N);
+  const int qpb = pick_qpb(g, B, 8);
+  dispatch(g.dim, qpb, [&](auto D, auto Q) {
+    hipLaunchKernelGGL((k_apply<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
+                       Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, u, y, mode, rhs, rhs_ld,
+                       rhs_scale, flag, part);
+  });
 }
 
 template <typename TY>
 void launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                    int64_t y_ld, const double* p_old, double* p_new, const double* beta,
-                   const int* active, double* part, int per_thread, hipStream_t s) {
-  const dim3 grid(stencil_chunks(g.N, per_thread), B);
-#define F(D)                                                                               \
-  hipLaunchKernelGGL((k_pass_a<D, TY>), grid, dim3(kThreads), 0, s, g, ld, coef, y, y_ld, \
-                     p_old, p_new, beta, active, part, per_thread)
-  RB_DIM_DISPATCH(g.dim, F)
-#undef F
+                   const int* active, double* part, hipStream_t s) {
+  const int chunks = stencil_chunks_all(g.N);
+  const int qpb = pick_qpb(g, B, 8, 2);
+  dispatch(g.dim, qpb, [&](auto D, auto Q) {
+    hipLaunchKernelGGL((k_pass_a<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
+                       dim3(kThreads), Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, y, y_ld,
+                       p_old, p_new, beta, active, part);
+  });
 }
 template void launch_pass_a<double>(const StencilGeom&, int64_t, int, const double*,
                                     const double*, int64_t, const double*, double*,
-                                    const double*, const int*, double*, int, hipStream_t);
+                                    const double*, const int*, double*, hipStream_t);
 template void launch_pass_a<float>(const StencilGeom&, int64_t, int, const double*, const float*,
                                    int64_t, const double*, double*, const double*, const int*,
-                                   double*, int, hipStream_t);
+                                   double*, hipStream_t);
 
 void launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                    double* x, const double* r_in, double* r_out, const double* alpha,
-                   const int* active, double* part, int per_thread, hipStream_t s) {
-  const dim3 grid(stencil_chunks(g.N, per_thread), B);
-#define F(D)                                                                                \
-  hipLaunchKernelGGL(k_pass_b<D>, grid, dim3(kThreads), 0, s, g, ld, coef, p, x, r_in, r_out, \
-                     alpha, active, part, per_thread)
-  RB_DIM_DISPATCH(g.dim, F)
-#undef F
+                   const int* active, double* part, hipStream_t s) {
+  const int chunks = stencil_chunks_all(g.N);
+  const int qpb = pick_qpb(g, B, 8);
+  dispatch(g.dim, qpb, [&](auto D, auto Q) {
+    hipLaunchKernelGGL((k_pass_b<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
+                       Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, p, x, r_in, r_out,
+                       alpha, active, part);
+  });
 }
 
 template <typename TY>
 void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
                      int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                      const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                     double* part1, int per_thread, hipStream_t s) {
-  const int count = color ? g.N - g.NR : g.NR;
-  const dim3 grid(stencil_chunks(count, per_thread), B);
-#define F(D)                                                                                  \
-  hipLaunchKernelGGL((k_gs_color<D, TY>), grid, dim3(kThreads), 0, s, g, color, coef, y, y_ld, \
-                     rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active, part0, part1, per_thread)
-  RB_DIM_DISPATCH(g.dim, F)
-#undef F
+                     double* part1, hipStream_t s) {
+  const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
+  const int qpb = pick_qpb(g, B, (int)sizeof(TY));
+  dispatch(g.dim, qpb, [&](auto D, auto Q) {
+    hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
+                       dim3(kThreads), Q.value * g.ct_size * (int)sizeof(TY), s, g, color, B,
+                       chunks, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                       part0, part1);
+  });
 }
 template void launch_gs_color<double>(const StencilGeom&, int, int, const double*, double*,
                                       int64_t, const double*, int64_t, const double*,
-                                      const double*, int64_t, const int*, double*, double*, int,
+                                      const double*, int64_t, const int*, double*, double*,
                                       hipStream_t);
 template void launch_gs_color<float>(const StencilGeom&, int, int, const double*, float*, int64_t,
                                      const double*, int64_t, const double*, const double*,
-                                     int64_t, const int*, double*, double*, int, hipStream_t);
+                                     int64_t, const int*, double*, double*, hipStream_t);
 
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
                    int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                   double* part1, int per_thread, hipStream_t s) {
-  const dim3 grid(stencil_chunks(g.N, per_thread), B);
-#define F(D)                                                                                   \
-  hipLaunchKernelGGL((k_jacobi<D, TY>), grid, dim3(kThreads), 0, s, g, coef, z, y, y_ld, omega, \
-                     rhs, rhs_ld, rhs2, rhs2_ld, active, part0, part1, per_thread)
-  RB_DIM_DISPATCH(g.dim, F)
-#undef F
+                   double* part1, hipStream_t s) {
+  const int chunks = stencil_chunks_all(g.N);
+  const int qpb = pick_qpb(g, B, (int)sizeof(TY));
+  dispatch(g.dim, qpb, [&](auto D, auto Q) {
+    hipLaunchKernelGGL((k_jacobi<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
+                       dim3(kThreads), Q.value * g.ct_size * (int)sizeof(TY), s, g, B, chunks,
+                       coef, z, y, y_ld, omega, rhs, rhs_ld, rhs2, rhs2_ld, active, part0, part1);
+  });
 }
 template void launch_jacobi<double>(const StencilGeom&, int, const double*, const double*,
                                     double*, int64_t, double, const double*, int64_t,
-                                    const double*, int64_t, const int*, double*, double*, int,
+                                    const double*, int64_t, const int*, double*, double*,
                                     hipStream_t);
 template void launch_jacobi<float>(const StencilGeom&, int, const double*, const float*, float*,
                                    int64_t, double, const double*, int64_t, const double*,
-                                   int64_t, const int*, double*, double*, int, hipStream_t);
+                                   int64_t, const int*, double*, double*, hipStream_t);
 
 }  // namespace rb

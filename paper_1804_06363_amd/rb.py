@@ -4,6 +4,7 @@ the solvers runs in the library's HIP kernels.  PyTorch provides device memory
 
 The library must be built (``python -m paper_1804_06363_amd.build`` or
 ``__graft_entry__.build()``); importing this module without it raises at once.
+RB_LIBRARY_PATH overrides the library file (e.g. a build with other tile constants).
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librb.so")
+LIB_PATH = os.environ.get("RB_LIBRARY_PATH") or os.path.join(_HERE, "librb.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"librb.so is not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -74,7 +75,7 @@ class GreedyReport(C.Structure):
     _fields_ = [("n_built", C.c_int), ("picks", C.POINTER(C.c_int64)),
                 ("max_indicator", C.POINTER(C.c_double)), ("snapshot_iters", C.POINTER(C.c_int)),
                 ("true_evals", C.c_int64), ("full_sweeps", C.c_int), ("seconds", C.c_double),
-                ("mlp_loss", C.c_double)]
+                ("mlp_loss", C.c_double), ("surrogate_fallbacks", C.c_int)]
 
 
 _P = C.c_void_p
@@ -114,6 +115,11 @@ _sig("rb_apply_batch", [_P, _P, C.c_int, _D, _P, _P])
 _sig("rb_precond_batch", [_P, _P, _P, C.POINTER(SolveOpts), C.c_int, _D, _I, _P, _P])
 _sig("rb_project_batch", [_P, _P, _P, C.c_int, C.c_int, _P, _D])
 _sig("rb_reduced_factor_batch", [_P, _P, C.c_int, _D, _D, _I])
+_F = C.POINTER(C.c_float)
+_sig("rb_mlp_forward", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F])
+_sig("rb_mlp_loss_grad", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F, _F, _F])
+_sig("rb_mlp_train", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F, C.c_int, C.c_double, _F])
+_sig("rb_topk", [_P, C.c_int, C.c_int, _F, _I, _I, _I])
 _sig("rb_greedy_opts_default", [C.POINTER(GreedyOpts)], None)
 _sig("rb_offline_build", [_P, _P, C.POINTER(GreedyOpts), C.c_int64, C.c_int, _D, _D, _D,
                           C.POINTER(_P), C.POINTER(GreedyReport)])
@@ -126,6 +132,7 @@ EXPORTED = [
     "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi", "rb_apply_batch",
     "rb_precond_batch", "rb_project_batch", "rb_reduced_factor_batch",
     "rb_greedy_opts_default", "rb_offline_build",
+    "rb_mlp_forward", "rb_mlp_loss_grad", "rb_mlp_train", "rb_topk",
 ]
 
 
@@ -405,5 +412,51 @@ def offline_build(ctx, prob, theta, mu=None, phi=None, **kw):
     nb = rep.n_built
     report = {"n_built": nb, "picks": picks[:nb].tolist(), "max_indicator": maxind[:nb].tolist(),
               "snapshot_iters": sit[:nb].tolist(), "true_evals": rep.true_evals,
-              "full_sweeps": rep.full_sweeps, "seconds": rep.seconds, "mlp_loss": rep.mlp_loss}
+              "full_sweeps": rep.full_sweeps, "seconds": rep.seconds, "mlp_loss": rep.mlp_loss,
+              "surrogate_fallbacks": rep.surrogate_fallbacks}
     return Basis(ctx, prob, h), report
+
+
+# ---- MLP surrogate diagnostics ------------------------------------------------------------
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mlp_forward(ctx, P, H, params, X, prec="bf16"):
+    params, X = _f32(params), _f32(X)
+    out = np.empty(X.shape[0], dtype=np.float32)
+    _check(_lib.rb_mlp_forward(ctx.h, P, H, PREC[prec], _fptr(params), X.shape[0], _fptr(X),
+                               _fptr(out)))
+    return out
+
+
+def mlp_loss_grad(ctx, P, H, params, X, y, prec="bf16"):
+    params, X, y = _f32(params), _f32(X), _f32(y)
+    g = np.empty_like(params)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(_lib.rb_mlp_loss_grad(ctx.h, P, H, PREC[prec], _fptr(params), X.shape[0], _fptr(X),
+                                 _fptr(y), _fptr(loss), _fptr(g)))
+    return float(loss[0]), g
+
+
+def mlp_train(ctx, P, H, params, X, y, steps, lr, prec="bf16"):
+    params, X, y = _f32(params).copy(), _f32(X), _f32(y)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(_lib.rb_mlp_train(ctx.h, P, H, PREC[prec], _fptr(params), X.shape[0], _fptr(X),
+                             _fptr(y), steps, lr, _fptr(loss)))
+    return params, float(loss[0])
+
+
+def topk(ctx, v, K, excluded=None):
+    v = _f32(v)
+    M = v.shape[0]
+    ex = None if excluded is None else np.ascontiguousarray(excluded, dtype=np.int32)
+    out = np.empty(max(K, 1), dtype=np.int32)
+    cnt = C.c_int()
+    _check(_lib.rb_topk(ctx.h, M, K, _fptr(v), ex.ctypes.data_as(_I) if ex is not None else None,
+                        out.ctypes.data_as(_I), C.byref(cnt)))
+    return out[:cnt.value]
