@@ -51,7 +51,7 @@ def main():
     ap.add_argument("--learned", type=int, default=0,
                     help="also compare the surrogate-ranked greedy with the plain greedy")
     ap.add_argument("--copy-calib", type=int, default=0,
-                    help="also run one device copy of this many MiB (profiler calibration)")
+                    help="also fill and sum a buffer of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the queries are independent and the build "
@@ -65,13 +65,13 @@ def main():
     if args.copy_calib > 0:
         # a plain copy of known size: the profiler's byte counters are scaled by what
         # they read for this kernel
+        # a fill kernel writes exactly this many bytes and a sum kernel reads them
         n = args.copy_calib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
+        s_ = float(a.sum())
         torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_calib} MiB read + written")
-        del a, b
+        log(f"counter calibration: fill writes and sum reads {args.copy_calib} MiB ({s_:.0f})")
+        del a
     w = WORKLOADS[args.workload]
     B = args.B or w.B
     N, Q = w.N, w.Q
@@ -87,8 +87,11 @@ def main():
     x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
     opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph))
 
+    # warm-up solves autotune the batched kernels' tiles (kept in the context)
+    wopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
+                          autotune=True)
     for i in range(args.warmup):
-        _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=opts)
+        _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=wopts)
         log(f"warmup {i}: iters mean {st.iters.mean():.1f} max {st.iters.max()} "
             f"max rel res {st.rel_res_true.max():.2e} status {np.bincount(st.status)}")
     ctx.profile(True)
@@ -150,10 +153,14 @@ def main():
         cpu = cpu_baseline(basis, w, test[0])
 
     extra = {}
-    if args.uneven:
-        extra["uneven_batch"] = uneven_leg(rb, torch)
-    if args.learned:
-        extra["learned_greedy"] = learned_leg(rb)
+    for flag, name, fn in ((args.uneven, "uneven_batch", lambda: uneven_leg(rb, torch)),
+                           (args.learned, "learned_greedy", lambda: learned_leg(rb))):
+        if flag:
+            try:
+                extra[name] = fn()
+            except Exception as exc:  # a failed extra leg is reported, not fatal
+                log(f"{name} failed: {exc}")
+                extra[name] = {"error": str(exc)}
 
     out = {
         "metric": "mu-solves/sec to rel. residual 1e-10 (batched mixed RB-PCG)",
@@ -188,14 +195,17 @@ def uneven_leg(rb, torch):
     for wk in UNEVEN_GRIDS:
         pr = rb.Problem(ctx, wk.dims, wk.blocks)
         tr = wk.train_mu()
-        b, _ = rb.offline_build(ctx, pr, tr, mu=tr, n_max=60, indicator="l1")
+        # the first snapshot is smoother-only PCG (W_0 empty): on 1023^2 with a kappa
+        # contrast of 1e4 it needs far more than the default 5000 iterations
+        b, _ = rb.offline_build(ctx, pr, tr, mu=tr, n_max=60, indicator="l1",
+                                snapshot_maxit=100000)
         probs.append(pr)
         bases.append(b)
     log(f"uneven: four bases in {time.time() - t0:.1f}s")
     qs = uneven_batch()
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda:0") for g, _, _ in qs]
     queries = [(g, nu, mu, None, x) for (g, nu, mu), x in zip(qs, xs)]
-    opts = rb.solve_opts(prec="fp32", flexible=True)
+    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True)
     rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()

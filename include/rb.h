@@ -144,6 +144,10 @@ typedef struct {
   int use_graph;
   int fixed_iters;
   int check_every; /* iterations between host checks of the active count; 0 = auto */
+  int autotune;    /* 1: time candidate tiles of the batched kernels the first time a
+                      (problem shape, batch, basis size, precision) is solved and keep
+                      the fastest in the context (and in the JSON file named by
+                      RB_AUTOTUNE_CACHE, if set); 0: cached choice or built-in default */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 

@@ -552,7 +552,9 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
     RB_REQUIRE(ctx && probs && qs && stats && nprob >= 1 && B >= 0, RB_EINVAL,
                "bad multi-solve arguments");
     check_opts(o);
-    // group the queries by problem; each group is one batched solve
+    // group the queries by problem; each group is one batched solver.  The groups run
+    // concurrently, each on its own stream with its own workspace (the first group
+    // uses the context's), and the host issues their iteration chunks round-robin.
     std::map<int, std::vector<int>> groups;
     for (int i = 0; i < B; ++i) {
       RB_REQUIRE(qs[i].problem >= 0 && qs[i].problem < nprob && qs[i].theta && qs[i].x,
@@ -560,37 +562,89 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       groups[qs[i].problem].push_back(i);
     }
     DeviceGuard dg(ctx->device);
-    for (auto& kv : groups) {
-      const rb_problem* p = probs[kv.first];
-      const rb_basis* bs = bases ? bases[kv.first] : nullptr;
-      RB_REQUIRE(p, RB_EINVAL, "null problem");
-      const std::vector<int>& idx = kv.second;
-      const int Bg = (int)idx.size();
-      const int Q = p->g.Q, R = p->R;
-      std::vector<double> th((size_t)Bg * Q), ph((size_t)Bg * R, 1.0);
-      std::vector<int> nu(Bg);
+    struct Group {
+      const rb_problem* p;
+      std::vector<int> idx;
+      std::vector<double> th, ph;
+      std::vector<int> nu;
       bool any_phi = false;
+      hipStream_t st = nullptr;
+      std::unique_ptr<Workspace> ws;
+      std::unique_ptr<BatchSolver> solver;
+      bool running = false;
+    };
+    std::vector<Group> gs;
+    for (auto& kv : groups) {
+      Group g;
+      g.p = probs[kv.first];
+      const rb_basis* bs = bases ? bases[kv.first] : nullptr;
+      RB_REQUIRE(g.p, RB_EINVAL, "null problem");
+      RB_REQUIRE(!bs || bs->prob == g.p, RB_EINVAL, "basis belongs to another problem");
+      g.idx = kv.second;
+      const int Bg = (int)g.idx.size();
+      const int Q = g.p->g.Q, R = g.p->R;
+      g.th.resize((size_t)Bg * Q);
+      g.ph.assign((size_t)Bg * R, 1.0);
+      g.nu.resize(Bg);
       for (int k = 0; k < Bg; ++k) {
-        const rb_query& q = qs[idx[k]];
-        std::copy(q.theta, q.theta + Q, th.begin() + (size_t)k * Q);
+        const rb_query& q = qs[g.idx[k]];
+        std::copy(q.theta, q.theta + Q, g.th.begin() + (size_t)k * Q);
         if (q.phi) {
-          any_phi = true;
-          std::copy(q.phi, q.phi + R, ph.begin() + (size_t)k * R);
+          g.any_phi = true;
+          std::copy(q.phi, q.phi + R, g.ph.begin() + (size_t)k * R);
         }
-        nu[k] = (q.n_use <= 0 && bs) ? bs->n : q.n_use;
+        g.nu[k] = (q.n_use <= 0 && bs) ? bs->n : q.n_use;
       }
-      check_finite(th.data(), th.size(), "theta");
-      BatchSolver s(ctx, p, bs, *o, Bg, th.data(), any_phi ? ph.data() : nullptr, nu.data());
-      s.run();
+      check_finite(g.th.data(), g.th.size(), "theta");
+      gs.push_back(std::move(g));
+    }
+    // streams and workspaces; destroyed on every exit path
+    struct Streams {
+      std::vector<hipStream_t> v;
+      ~Streams() {
+        for (auto s : v) (void)hipStreamDestroy(s);
+      }
+    } own;
+    for (size_t i = 0; i < gs.size(); ++i) {
+      if (i == 0) {
+        gs[i].st = ctx->stream;
+      } else {
+        RB_HIP(hipStreamCreate(&gs[i].st));  // blocking, default priority
+        own.v.push_back(gs[i].st);
+        gs[i].ws = std::make_unique<Workspace>();
+      }
+    }
+    for (auto& g : gs) {
+      const rb_basis* bs = bases ? bases[g.idx.empty() ? 0 : qs[g.idx[0]].problem] : nullptr;
+      g.solver = std::make_unique<BatchSolver>(ctx, g.p, bs, *o, (int)g.idx.size(), g.th.data(),
+                                               g.any_phi ? g.ph.data() : nullptr, g.nu.data(),
+                                               g.st, g.ws ? g.ws.get() : &ctx->ws);
+      g.solver->start();
+      g.running = true;
+    }
+    bool any = true;
+    while (any) {
+      for (auto& g : gs)
+        if (g.running) g.solver->issue(g.solver->chunk_);
+      any = false;
+      for (auto& g : gs)
+        if (g.running) {
+          g.running = g.solver->poll();
+          any |= g.running;
+        }
+    }
+    for (auto& g : gs) {
+      BatchSolver& sv = *g.solver;
+      sv.finish();
       std::vector<rb_query_stats> st;
-      DevBuf xs(sizeof(double) * (size_t)Bg * p->N);
-      s.gather(xs.as<double>(), p->N, st);
-      for (int k = 0; k < Bg; ++k) {
-        RB_HIP(hipMemcpyAsync(qs[idx[k]].x, xs.as<double>() + (size_t)k * p->N,
-                              sizeof(double) * p->N, hipMemcpyDeviceToDevice, ctx->stream));
-        stats[idx[k]] = st[k];
+      DevBuf xs(sizeof(double) * g.idx.size() * g.p->N);
+      sv.gather(xs.as<double>(), g.p->N, st);
+      for (size_t k = 0; k < g.idx.size(); ++k) {
+        RB_HIP(hipMemcpyAsync(qs[g.idx[k]].x, xs.as<double>() + k * g.p->N,
+                              sizeof(double) * g.p->N, hipMemcpyDeviceToDevice, sv.s()));
+        stats[g.idx[k]] = st[k];
       }
-      RB_HIP(hipStreamSynchronize(ctx->stream));
+      RB_HIP(hipStreamSynchronize(sv.s()));
     }
   });
 }

@@ -102,9 +102,42 @@ struct Buf {
   size_t bytes = 0;
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
+// Tile choices of the batched kernels (0 = built-in heuristic), per solve.
+struct TuneConfig {
+  int qpb_a = 0, qpb_b = 0, qpb_gs = 0;  // queries per block of pass A / pass B / sweeps
+  int proj_target = 0;                   // projection: target number of blocks
+};
+// Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
+struct Tuner {
+  bool loaded = false;
+  std::string path;
+  std::vector<std::pair<std::string, TuneConfig>> table;
+  const TuneConfig* find(const std::string& key) const;
+  void put(const std::string& key, const TuneConfig& c);
+  void load();
+  void save() const;
+};
+// Tiles the stencil launchers use on the calling thread (set by the solver).
+void set_stencil_tiles(const TuneConfig& c);
+TuneConfig stencil_tiles();
+
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
   WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PR0, WS_PR1, WS_PB0, WS_PB1, WS_Q, WS_COUNT
+};
+}  // namespace rb
+
+namespace rb {
+// Solver workspace, grown on demand.  Contents are not preserved between solves.
+struct Workspace {
+  DevBuf slot[WS_COUNT];
+  Buf get(int i, size_t bytes, hipStream_t s) {
+    if (slot[i].bytes < bytes) {
+      (void)hipStreamSynchronize(s);
+      slot[i].alloc(bytes);
+    }
+    return Buf{slot[i].p, slot[i].bytes};
+  }
 };
 }  // namespace rb
 
@@ -114,16 +147,11 @@ struct rb_ctx {
   bool own_stream = false;
   hipDeviceProp_t prop{};
   rb::Profiler prof;
-  // Solver workspace, grown on demand and kept until the context is destroyed (one
-  // solver runs at a time per context).  Contents are not preserved between solves.
-  rb::DevBuf ws[rb::WS_COUNT];
-  rb::Buf get_ws(int slot, size_t bytes) {
-    if (ws[slot].bytes < bytes) {
-      (void)hipStreamSynchronize(stream);
-      ws[slot].alloc(bytes);
-    }
-    return rb::Buf{ws[slot].p, ws[slot].bytes};
-  }
+  rb::Tuner tuner;
+  // the context's workspace, kept until the context is destroyed (one solver at a time
+  // uses it; concurrent groups of rb_solve_multi get their own)
+  rb::Workspace ws;
+  rb::Buf get_ws(int slot, size_t bytes) { return ws.get(slot, bytes, stream); }
 };
 
 namespace rb {
@@ -133,8 +161,9 @@ struct ProfScope {
   rb_ctx* ctx;
   const char* name;
   hipEvent_t a = nullptr;
-  ProfScope(rb_ctx* c, const char* n) : ctx(c), name(n) {
-    if (!ctx->prof.on) return;
+  // timing only on the context's own stream
+  ProfScope(rb_ctx* c, const char* n, hipStream_t on = nullptr) : ctx(c), name(n) {
+    if (!ctx->prof.on || (on && on != ctx->stream)) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
       return;

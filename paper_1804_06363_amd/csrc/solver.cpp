@@ -14,8 +14,9 @@ static int64_t align64(int64_t v) { return (v + 63) / 64 * 64; }
 
 BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
                          const rb_solve_opts& o, int B_, const double* theta, const double* phi,
-                         const int* n_use)
-    : ctx(c), prob(p), basis(b), opt(o), B(B_) {
+                         const int* n_use, hipStream_t stream, Workspace* ws)
+    : ctx(c), prob(p), basis(b), opt(o), B(B_), stream_(stream ? stream : c->stream),
+      ws_(ws ? ws : &c->ws) {
   const StencilGeom& g = prob->g;
   const int Q = g.Q;
   if (opt.solver == RB_SOLVER_CG) {
@@ -39,15 +40,15 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   hipStream_t st = s();
 
   // per-query inputs
-  theta_d = ctx->get_ws(WS_THETA, sizeof(double) * B * Q);
+  theta_d = get_ws(WS_THETA, sizeof(double) * B * Q);
   RB_HIP(hipMemcpyAsync(theta_d.p, theta, sizeof(double) * B * Q, hipMemcpyHostToDevice, st));
   const int R = prob->R;
   std::vector<double> sc(B, 1.0);
   if (R == 1 && phi)
     for (int i = 0; i < B; ++i) sc[i] = phi[i];
-  scale_d = ctx->get_ws(WS_SCALE, sizeof(double) * B);
+  scale_d = get_ws(WS_SCALE, sizeof(double) * B);
   RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-  nuse_d = ctx->get_ws(WS_NUSE, sizeof(int) * B);
+  nuse_d = get_ws(WS_NUSE, sizeof(int) * B);
   RB_HIP(hipMemcpyAsync(nuse_d.p, nu.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
   if (R == 1) {
     f_base = prob->f.as<double>();
@@ -75,51 +76,65 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
   }
 
-  coef = ctx->get_ws(WS_COEF, sizeof(double) * B * g.ct_size);
+  coef = get_ws(WS_COEF, sizeof(double) * B * g.ct_size);
   launch_coef_tables(g, B, theta_d.as<double>(), nullptr, coef.as<double>(), st);
 
+  // tile choices: cached by the autotuner for this shape, else the defaults
+  {
+    auto lg = [](int64_t v) { int k = 0; while ((1ll << (k + 1)) <= v) ++k; return k; };
+    std::string arch = ctx->prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    tune_key = arch + "|d" + std::to_string(g.dim) + "|N" + std::to_string(lg(g.N)) + "|B" +
+               std::to_string(lg(B)) + "|n" + std::to_string((n + 15) / 16) + "|p" +
+               std::to_string((int)opt.precond_prec) + "|s" + std::to_string((int)opt.smoother);
+    ctx->tuner.load();
+    if (const TuneConfig* c = ctx->tuner.find(tune_key)) tc = *c;
+  }
   // projection plan first: for batches it reads residual rows in whole query tiles
   if (n > 0) {
-    plan = plan_projection(g.N, B, n, 4 * ctx->prop.multiProcessorCount);
+    plan = plan_projection(g.N, B, n,
+                           tc.proj_target ? tc.proj_target : 4 * ctx->prop.multiProcessorCount);
     plan.padded = !plan.wsplit;
   }
   rrows = (n > 0 && plan.padded) ? plan.qgroups * 64 * plan.qt : B;
   // state vectors
   const size_t vb = sizeof(double) * (size_t)B * L_;
   const size_t vr = sizeof(double) * (size_t)rrows * L_;
-  x = ctx->get_ws(WS_X, vb);
-  r0 = ctx->get_ws(WS_R0, vr);
+  x = get_ws(WS_X, vb);
+  r0 = get_ws(WS_R0, vr);
   if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
-    r1 = ctx->get_ws(WS_R1, vr);
+    r1 = get_ws(WS_R1, vr);
   if (opt.solver != RB_SOLVER_RBI) {
-    p0 = ctx->get_ws(WS_P0, vb);
-    p1 = ctx->get_ws(WS_P1, vb);
-    y = ctx->get_ws(WS_Y, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+    p0 = get_ws(WS_P0, vb);
+    p1 = get_ws(WS_P1, vb);
+    y = get_ws(WS_Y, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
     if (opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
-      z = ctx->get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+      z = get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
   }
-  part_m = ctx->get_ws(WS_PM, sizeof(double) * (size_t)B * pstride);
-  part_r0 = ctx->get_ws(WS_PR0, sizeof(double) * (size_t)B * pstride);
-  part_r1 = ctx->get_ws(WS_PR1, sizeof(double) * (size_t)B * pstride);
-  part_b0 = ctx->get_ws(WS_PB0, sizeof(double) * (size_t)B * pstride);
-  part_b1 = ctx->get_ws(WS_PB1, sizeof(double) * (size_t)B * pstride);
+  part_m = get_ws(WS_PM, sizeof(double) * (size_t)B * pstride);
+  part_r0 = get_ws(WS_PR0, sizeof(double) * (size_t)B * pstride);
+  part_r1 = get_ws(WS_PR1, sizeof(double) * (size_t)B * pstride);
+  part_b0 = get_ws(WS_PB0, sizeof(double) * (size_t)B * pstride);
+  part_b1 = get_ws(WS_PB1, sizeof(double) * (size_t)B * pstride);
 
   // reduced basis data
   if (n > 0) {
     Wsh = const_cast<rb_basis*>(basis)->shadow(opt.precond_prec);
     const size_t acc = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
-    projpart = ctx->get_ws(WS_PROJ, acc * (size_t)plan.chunks * B * plan.nj);
-    L = ctx->get_ws(WS_L, sizeof(double) * (size_t)B * n * n);
+    // room for the largest candidate plan of the autotuner
+    const ProjPlan big = plan_projection(g.N, B, n, 4096);
+    projpart = get_ws(WS_PROJ, acc * (size_t)std::max(plan.chunks, big.chunks) * B * plan.nj);
+    L = get_ws(WS_L, sizeof(double) * (size_t)B * n * n);
     // the prolongations read e in groups of up to 256 queries: pad and zero the rows
     const int Bp = padded_queries(B);
-    e64 = ctx->get_ws(WS_E64, sizeof(double) * (size_t)Bp * e_ld);
-    e32 = ctx->get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
+    e64 = get_ws(WS_E64, sizeof(double) * (size_t)Bp * e_ld);
+    e32 = get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
     launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
     launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
   }
 
   // per-query scalars
-  qbuf = ctx->get_ws(WS_Q, (sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
+  qbuf = get_ws(WS_Q, (sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
@@ -170,16 +185,16 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   void* zdst = full ? z.p : y.p;
   if (n > 0) {
     {
-      ProfScope ps(ctx, "project");
+      ProfScope ps(ctx, "project", st);
       launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st);
     }
     {
-      ProfScope ps(ctx, "reduced_solve");
+      ProfScope ps(ctx, "reduced_solve", st);
       launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, plan.chunks, B, plan.nj,
                           n, nuse_d.as<int>(), L.as<double>(), q.active, nullptr,
                           e64.as<double>(), e32.as<float>(), e_ld, true, st);
     }
-    ProfScope ps(ctx, "prolong");
+    ProfScope ps(ctx, "prolong", st);
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
                    q.active, zdst, !y32, L_, full ? 0 : g.NR, g.N, false, st);
   } else {
@@ -194,7 +209,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   double* pb0 = part_b0.as<double>();
   double* pb1 = flex ? part_b1.as<double>() : nullptr;
   auto sweep = [&](int color, bool dots) {
-    ProfScope ps(ctx, color ? "gs_black" : "gs_red");
+    ProfScope ps(ctx, color ? "gs_black" : "gs_red", st);
     if (y32)
       launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
                              flex ? r_old : nullptr, L_, q.active, dots ? (color ? pb0 : pr0) : nullptr,
@@ -265,7 +280,7 @@ void BatchSolver::iterate_cg(int k) {
   double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
   // step 11 of the previous iteration fused with step 5's product: p = y + beta p; A p
   {
-  ProfScope ps(ctx, "pass_a");
+  ProfScope ps(ctx, "pass_a", st);
   if (y32)
     launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
                          q.beta, q.active, part_m.as<double>(), st);
@@ -276,7 +291,7 @@ void BatchSolver::iterate_cg(int k) {
   launch_fin_alpha(part_m.as<double>(), cN, cN, q, B, st);
   // steps 6-7: x += alpha p, r -= alpha A p
   {
-    ProfScope ps(ctx, "pass_b");
+    ProfScope ps(ctx, "pass_b", st);
     launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
                   part_m.as<double>(), st);
   }
@@ -284,7 +299,7 @@ void BatchSolver::iterate_cg(int k) {
   const bool fixed = opt.fixed_iters > 0;
   launch_fin_rr(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
-    ProfScope ps(ctx, "true_residual");
+    ProfScope ps(ctx, "true_residual", st);
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
                  scale_d.as<double>(), q.flag, part_m.as<double>(), st);
     launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st);
@@ -399,68 +414,181 @@ void BatchSolver::final_true_residual() {
   RB_HIP(hipStreamSynchronize(st));
 }
 
-void BatchSolver::run() {
+// Times candidate tiles on this solve's own (not yet initialised) buffers and keeps the
+// fastest: queries per block of pass A, pass B and the colour sweeps, and the number of
+// projection blocks.  Runs before init, so the values it computes are overwritten.
+void BatchSolver::autotune() {
+  if (!opt.autotune || ctx->tuner.find(tune_key) || opt.solver == RB_SOLVER_RBI) return;
+  const StencilGeom& g = prob->g;
+  const int64_t L_ = ld();
   hipStream_t st = s();
-  const bool rbi = opt.solver == RB_SOLVER_RBI;
-  if (rbi)
+  hipEvent_t e0, e1;
+  RB_HIP(hipEventCreate(&e0));
+  RB_HIP(hipEventCreate(&e1));
+  auto timed = [&](auto&& launch) {
+    launch();  // warm
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      RB_HIP(hipEventRecord(e0, st));
+      launch();
+      RB_HIP(hipEventRecord(e1, st));
+      RB_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      RB_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  const int caps[4] = {1, 2, 4, 8};
+  TuneConfig best = tc, cur = tc;
+  float ta = 1e30f, tb = 1e30f, tg = 1e30f;
+  for (int c : caps) {
+    if (c > B) break;
+    cur = best;
+    cur.qpb_a = c;
+    set_stencil_tiles(cur);
+    const float t1 = timed([&] {
+      if (y32)
+        launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, p0.as<double>(),
+                             p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
+      else
+        launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, p0.as<double>(),
+                              p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
+    });
+    if (t1 < ta) { ta = t1; best.qpb_a = c; }
+    cur = best;
+    cur.qpb_b = c;
+    set_stencil_tiles(cur);
+    const float t2 = timed([&] {
+      launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(), r0.as<double>(),
+                    r0.as<double>(), q.alpha, q.active, part_m.as<double>(), st);
+    });
+    if (t2 < tb) { tb = t2; best.qpb_b = c; }
+    cur = best;
+    cur.qpb_gs = c;
+    set_stencil_tiles(cur);
+    const float t3 = timed([&] {
+      if (y32)
+        launch_gs_color<float>(g, 0, B, coef.as<double>(), y.as<float>(), L_, r0.as<double>(), L_,
+                               nullptr, nullptr, L_, q.active, part_r0.as<double>(), nullptr, st);
+      else
+        launch_gs_color<double>(g, 0, B, coef.as<double>(), y.as<double>(), L_, r0.as<double>(),
+                                L_, nullptr, nullptr, L_, q.active, part_r0.as<double>(), nullptr,
+                                st);
+    });
+    if (t3 < tg) { tg = t3; best.qpb_gs = c; }
+  }
+  if (n > 0 && !plan.wsplit) {
+    float tp = 1e30f;
+    for (int target : {256, 512, 1024, 2048, 4096}) {
+      ProjPlan pl = plan_projection(g.N, B, n, target);
+      pl.padded = true;
+      if (pl.chunks == 0) continue;
+      const float t = timed([&] {
+        launch_projection(pl, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
+                          projpart.p, st);
+      });
+      if (t < tp) { tp = t; best.proj_target = target; }
+    }
+    plan = plan_projection(g.N, B, n, best.proj_target);
+    plan.padded = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tc = best;
+  set_stencil_tiles(tc);
+  ctx->tuner.put(tune_key, tc);
+  ctx->tuner.save();
+}
+
+void BatchSolver::start() {
+  rbi_ = opt.solver == RB_SOLVER_RBI;
+  set_stencil_tiles(tc);
+  autotune();
+  if (rbi_)
     init_rbi();
   else
     init_cg();
-  const bool fixed = opt.fixed_iters > 0;
-  int k = 0;
-  int chunk = opt.check_every > 0 ? opt.check_every : (prob->g.N >= (1 << 18) ? 4 : 16);
-  if (opt.use_graph && chunk % 2) ++chunk;
-  std::vector<int> act(B);
+  fixed_ = opt.fixed_iters > 0;
+  k_ = 0;
+  chunk_ = opt.check_every > 0 ? opt.check_every : (prob->g.N >= (1 << 18) ? 4 : 16);
+  if (opt.use_graph && chunk_ % 2) ++chunk_;
+  act_.assign(B, 1);
   // RBI: iteration k checks the residual of the k-th iterate first; maxit + 1 checks
-  const int limit = fixed ? opt.fixed_iters : (rbi ? opt.maxit + 1 : opt.maxit);
-  while (k < limit) {
-    int todo = std::min(chunk, limit - k);
-    if (opt.use_graph && !rbi && todo >= 2) {
-      if (!graph) {
-        hipGraph_t gr;
-        RB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        iterate_cg(0);
-        iterate_cg(1);
-        RB_HIP(hipStreamEndCapture(st, &gr));
-        RB_HIP(hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0));
-        RB_HIP(hipGraphDestroy(gr));
-      }
-      // the graph holds iterations (even, odd); k is even here
-      while (todo >= 2) {
-        RB_HIP(hipGraphLaunch(graph, st));
-        k += 2;
-        todo -= 2;
-      }
+  limit_ = fixed_ ? opt.fixed_iters : (rbi_ ? opt.maxit + 1 : opt.maxit);
+}
+
+// Issues up to `iters` iterations (fewer at the limit) on this solver's stream.
+void BatchSolver::issue(int iters) {
+  hipStream_t st = s();
+  set_stencil_tiles(tc);
+  int todo = std::min(iters, limit_ - k_);
+  if (opt.use_graph && !rbi_ && todo >= 2 && k_ % 2 == 0) {
+    if (!graph) {
+      hipGraph_t gr;
+      RB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      iterate_cg(0);
+      iterate_cg(1);
+      RB_HIP(hipStreamEndCapture(st, &gr));
+      RB_HIP(hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0));
+      RB_HIP(hipGraphDestroy(gr));
     }
-    for (; todo > 0; --todo, ++k) {
-      if (rbi)
-        iterate_rbi(k);
-      else
-        iterate_cg(k);
+    // the graph holds iterations (even, odd); k_ is even here
+    while (todo >= 2) {
+      RB_HIP(hipGraphLaunch(graph, st));
+      k_ += 2;
+      todo -= 2;
     }
-    if (fixed) continue;
-    RB_HIP(hipMemcpyAsync(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-    RB_HIP(hipStreamSynchronize(st));
-    ctx->prof.resolve();
-    bool any = false;
-    for (int i = 0; i < B; ++i) any |= act[i] != 0;
-    if (!any) break;
   }
+  for (; todo > 0; --todo, ++k_) {
+    if (rbi_)
+      iterate_rbi(k_);
+    else
+      iterate_cg(k_);
+  }
+  if (!fixed_)
+    RB_HIP(hipMemcpyAsync(act_.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+}
+
+bool BatchSolver::poll() {
+  RB_HIP(hipStreamSynchronize(s()));
+  if (s() == ctx->stream) ctx->prof.resolve();
+  if (k_ >= limit_) return false;
+  if (fixed_) return true;
+  for (int i = 0; i < B; ++i)
+    if (act_[i]) return true;
+  return false;
+}
+
+void BatchSolver::finish() {
+  hipStream_t st = s();
   RB_HIP(hipStreamSynchronize(st));
+  set_stencil_tiles(TuneConfig{});
   // queries still active after maxit did not converge
-  if (!fixed) {
-    std::vector<int> stt(B);
-    RB_HIP(hipMemcpy(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost));
-    RB_HIP(hipMemcpy(stt.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost));
+  if (!fixed_) {
+    std::vector<int> act(B), stt(B);
+    RB_HIP(hipMemcpyAsync(act.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipMemcpyAsync(stt.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
     bool changed = false;
     for (int i = 0; i < B; ++i)
       if (act[i]) {
         stt[i] = RB_ENOCONV;
         changed = true;
       }
-    if (changed)
-      RB_HIP(hipMemcpy(q.status, stt.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+    if (changed) {
+      RB_HIP(hipMemcpyAsync(q.status, stt.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      RB_HIP(hipStreamSynchronize(st));
+    }
   }
+}
+
+void BatchSolver::run() {
+  start();
+  do {
+    issue(chunk_);
+  } while (poll());
+  finish();
 }
 
 void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_stats>& stats) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -36,14 +37,22 @@ struct BatchSolver {
   const double* f_base = nullptr;  // right-hand side term(s), storage order
   int64_t f_ld = 0;                // 0: one shared term scaled per query
   DevBuf fb;                       // materialised f_b when R > 1
+  TuneConfig tc;                    // tile choices of this solve
+  std::string tune_key;
   hipGraphExec_t graph = nullptr;
   int graph_parity = 0;
 
+  hipStream_t stream_;
+  Workspace* ws_;
+  Buf get_ws(int slot, size_t bytes) { return ws_->get(slot, bytes, stream_); }
+
+  // stream / workspace default to the context's
   BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b, const rb_solve_opts& o, int B_,
-              const double* theta, const double* phi, const int* n_use);
+              const double* theta, const double* phi, const int* n_use,
+              hipStream_t stream = nullptr, Workspace* ws = nullptr);
   ~BatchSolver();
 
-  hipStream_t s() const { return ctx->stream; }
+  hipStream_t s() const { return stream_; }
   int64_t ld() const { return prob->ld; }
   // RBCG / CG
   void init_cg();
@@ -52,11 +61,19 @@ struct BatchSolver {
   // RBI
   void init_rbi();
   void iterate_rbi(int k);
-  // driver
+  // driver: run() = start(); while (issue(chunk), poll()); finish()
   void run();
+  void start();
+  void issue(int iters);
+  bool poll();  // synchronises this solver's stream; true while queries are active
+  void finish();
+  int k_ = 0, limit_ = 0, chunk_ = 0;
+  bool fixed_ = false, rbi_ = false;
+  std::vector<int> act_;
   void final_true_residual();
   void gather(double* x_user_nat, int64_t user_ld, std::vector<rb_query_stats>& stats);
   void factor();
+  void autotune();
 };
 
 }  // namespace rb

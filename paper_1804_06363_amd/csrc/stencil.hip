@@ -190,6 +190,9 @@ __device__ __forceinline__ int paired_pos(const StencilGeom& g, int chunk, int t
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int total) {
+#ifdef RB_NO_XCD_REMAP
+  return b;
+#endif
   const int q = total / kXCD, r = total % kXCD;
   const int xcd = b % kXCD, slot = b / kXCD;
   return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
@@ -554,11 +557,16 @@ int stencil_chunks_all(int N) {
   return (NR + kThreads * kPH - 1) / (kThreads * kPH);
 }
 
+static thread_local TuneConfig t_tiles;
+void set_stencil_tiles(const TuneConfig& c) { t_tiles = c; }
+TuneConfig stencil_tiles() { return t_tiles; }
+
 // queries per block: up to `cap` while the group's tables stay within 16 KB of LDS.
 // Measured on the 127^3 workload (B = 256): pass A (two arrays read at the
 // neighbours) is fastest with 1-2 queries per block, the one-colour sweeps with 4.
 static int pick_qpb(const StencilGeom& g, int B, int tsize, int cap = 4) {
-  int q = cap < RB_QPB_MAX ? cap : RB_QPB_MAX;
+  int q = 1;
+  while (q * 2 <= cap && q * 2 <= RB_QPB_MAX) q *= 2;
   while (q > 1 && (q > B || q * g.ct_size * tsize > 16384)) q >>= 1;
   return q;
 }
@@ -602,7 +610,7 @@ void launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, 
                    int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                    const int* active, double* part, hipStream_t s) {
   const int chunks = stencil_chunks_all(g.N);
-  const int qpb = pick_qpb(g, B, 8, 2);
+  const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_a ? t_tiles.qpb_a : 2);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     hipLaunchKernelGGL((k_pass_a<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
                        dim3(kThreads), Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, y, y_ld,
@@ -620,7 +628,7 @@ void launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, 
                    double* x, const double* r_in, double* r_out, const double* alpha,
                    const int* active, double* part, hipStream_t s) {
   const int chunks = stencil_chunks_all(g.N);
-  const int qpb = pick_qpb(g, B, 8);
+  const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 4);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     hipLaunchKernelGGL((k_pass_b<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
                        Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, p, x, r_in, r_out,
@@ -634,7 +642,7 @@ void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef,
                      const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                      double* part1, hipStream_t s) {
   const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
-  const int qpb = pick_qpb(g, B, (int)sizeof(TY));
+  const int qpb = pick_qpb(g, B, (int)sizeof(TY), t_tiles.qpb_gs ? t_tiles.qpb_gs : 4);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
                        dim3(kThreads), Q.value * g.ct_size * (int)sizeof(TY), s, g, color, B,

@@ -48,7 +48,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("solver", C.c_int), ("precond_prec", C.c_int),
                 ("smoother", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
                 ("beta_flexible", C.c_int), ("use_graph", C.c_int), ("fixed_iters", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("autotune", C.c_int)]
 
 
 class QueryStats(C.Structure):
@@ -273,7 +273,7 @@ class Basis:
 
 
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,
-               flexible=False, graph=False, fixed_iters=0, check_every=0):
+               flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False):
     o = SolveOpts()
     _lib.rb_solve_opts_default(C.byref(o))
     o.solver = SOLVER[solver]
@@ -285,6 +285,7 @@ def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=20
     o.use_graph = int(graph)
     o.fixed_iters = fixed_iters
     o.check_every = check_every
+    o.autotune = int(autotune)
     return o
 
 

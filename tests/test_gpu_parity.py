@@ -348,3 +348,22 @@ def test_solve_multi_uneven(lib, ctx):
         assert abs(st.iters[k] - ref.iters) <= 1
         kappa = _cond(op.assemble(th))
         assert _rel(x.cpu().numpy(), ref.x) <= 2 * kappa * 1e-10
+
+
+def test_autotuned_solve_matches_default(lib, ctx, tmp_path, monkeypatch):
+    """Tile choices change only the speed: the stencil passes give bitwise-identical
+    results for every queries-per-block choice, the projection's chunking changes the
+    summation order only."""
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 6, seed=110)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(111, 40, op.Q, 0.1, 10.0)
+    x0, s0 = lib.solve_batch(ctx, prob, basis, theta, prec="fp32", fixed_iters=8)
+    c2 = lib.Context(0)
+    x1, s1 = lib.solve_batch(c2, prob, basis, theta, prec="fp32", fixed_iters=8, autotune=True)
+    x2, s2 = lib.solve_batch(c2, prob, basis, theta, prec="fp32", fixed_iters=8)
+    a0, a1, a2 = (t.cpu().numpy() for t in (x0, x1, x2))
+    assert np.array_equal(a1, a2)
+    assert np.abs(a1 - a0).max() <= 1e-12 * np.abs(a0).max()
