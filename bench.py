@@ -50,6 +50,8 @@ def main():
                     help="also time the uneven batch (1024 queries over four grids)")
     ap.add_argument("--learned", type=int, default=0,
                     help="also compare the surrogate-ranked greedy with the plain greedy")
+    ap.add_argument("--basis", default="",
+                    help="load the basis from this file if it exists, else build and save it")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also fill and sum a buffer of this many MiB (profiler calibration)")
     args = ap.parse_args()
@@ -80,9 +82,16 @@ def main():
     prob = rb.Problem(ctx, w.dims, w.blocks)
     train = w.train_mu()
     t0 = time.time()
-    basis, rep = rb.offline_build(ctx, prob, train, mu=train, n_max=w.n, indicator=args.greedy)
-    log(f"offline greedy: n={basis.n} in {time.time() - t0:.1f}s, snapshot iters "
-        f"{rep['snapshot_iters'][:5]}..{rep['snapshot_iters'][-3:]}")
+    if args.basis and os.path.exists(args.basis):
+        basis = rb.Basis.load(ctx, prob, args.basis)
+        log(f"basis n={basis.n} loaded from {args.basis}")
+    else:
+        basis, rep = rb.offline_build(ctx, prob, train, mu=train, n_max=w.n,
+                                      indicator=args.greedy)
+        log(f"offline greedy: n={basis.n} in {time.time() - t0:.1f}s, snapshot iters "
+            f"{rep['snapshot_iters'][:5]}..{rep['snapshot_iters'][-3:]}")
+        if args.basis:
+            basis.save(args.basis)
     test = w.test_mu(B)
     x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
     opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph))
@@ -150,7 +159,7 @@ def main():
 
     cpu = None
     if args.cpu_baseline:
-        cpu = cpu_baseline(basis, w, test[0])
+        cpu = cpu_baseline(basis, w, test[:2])
 
     extra = {}
     for flag, name, fn in ((args.uneven, "uneven_batch", lambda: uneven_leg(rb, torch)),
@@ -168,7 +177,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+" + args.prec, "data": "synthetic",
-        "config": {"workload": f"3D 7-pt diffusion 127^3 (N={N}), 2x2x2 kappa blocks, "
+        "config": {"workload": f"{len(w.dims)}D {2 * len(w.dims) + 1}-pt diffusion "
+                               f"{'x'.join(map(str, w.dims))} (N={N}), "
+                               f"{'x'.join(map(str, w.blocks))} kappa blocks, "
                                f"n={basis.n}, B={B}, {args.prec} preconditioner",
                    "N": N, "B": B, "n": basis.n, "Q": Q, "prec": args.prec,
                    "beta": "flexible" if args.flexible else "literal",
@@ -187,7 +198,9 @@ def main():
 def uneven_leg(rb, torch):
     """1024 queries mixing 2D 63^2, 255^2, 1023^2 (4x4 kappa blocks) and 3D 63^3 (2x2x2),
     mu log-uniform in [0.01, 100], per-query basis sizes n in {10, 20, 40, 60} (leading
-    columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call."""
+    columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call.
+    Target true relative residual 1e-10, 1e-9 on 1023^2 (the FP64 rounding floor of that
+    grid's residual is about 1e-10)."""
     from workloads import UNEVEN_GRIDS, uneven_batch
     ctx = rb.Context(0)
     probs, bases = [], []
@@ -198,13 +211,14 @@ def uneven_leg(rb, torch):
         # the first snapshot is smoother-only PCG (W_0 empty): on 1023^2 with a kappa
         # contrast of 1e4 it needs far more than the default 5000 iterations
         b, _ = rb.offline_build(ctx, pr, tr, mu=tr, n_max=60, indicator="l1",
-                                snapshot_maxit=100000)
+                                snapshot_maxit=100000, snapshot_rtol=wk.rtol)
         probs.append(pr)
         bases.append(b)
     log(f"uneven: four bases in {time.time() - t0:.1f}s")
     qs = uneven_batch()
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda:0") for g, _, _ in qs]
-    queries = [(g, nu, mu, None, x) for (g, nu, mu), x in zip(qs, xs)]
+    queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
+    tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
     opts = rb.solve_opts(prec="fp32", flexible=True, graph=True)
     rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
     torch.cuda.synchronize()
@@ -212,12 +226,12 @@ def uneven_leg(rb, torch):
     st = rb.solve_multi(ctx, probs, bases, queries, opts=opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+    ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= tol)).sum())
     log(f"uneven: {len(qs)} queries in {el:.3f}s -> {ok / el:.1f} mu-solves/s, "
         f"iters mean {st.iters.mean():.1f}, max rel res {st.rel_res_true.max():.2e}")
     return {"value": round(ok / el, 2), "unit": "mu-solves/s", "queries": len(qs),
             "converged": ok, "seconds": round(el, 4), "iters_mean": round(float(st.iters.mean()), 2),
-            "max_rel_res": float(st.rel_res_true.max())}
+            "max_rel_res_over_rtol": float((st.rel_res_true / tol).max())}
 
 
 def learned_leg(rb):
@@ -266,8 +280,8 @@ def held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch):
     return worst
 
 
-def cpu_baseline(basis, w, theta):
-    """The oracle's RBCG (NumPy/SciPy FP64) on one query of the same workload."""
+def cpu_baseline(basis, w, thetas):
+    """The oracle's RBCG (NumPy/SciPy FP64) on a few queries of the same workload."""
     from oracle import rb as orb
     from oracle.operator import BlockDiffusion
     try:
@@ -280,13 +294,18 @@ def cpu_baseline(basis, w, theta):
     Wn, AN, fN = basis.info()
     W = np.ascontiguousarray(Wn.T)
     t = time.perf_counter()
-    res = orb.solve_rbcg(op, theta, W, AN, rtol=1e-10)
+    its, ok = [], 0
+    for th in thetas:
+        res = orb.solve_rbcg(op, th, W, AN, rtol=1e-10)
+        its.append(res.iters)
+        ok += int(res.converged and res.rel_res_true <= 1e-10)
     el = time.perf_counter() - t
-    log(f"cpu baseline: 1 solve in {el:.1f}s, iters {res.iters}, rel res {res.rel_res_true:.2e}")
-    return {"value": round(1.0 / el, 5), "unit": "mu-solves/s", "cores": cores, "kind": "oracle",
-            "sample": "1 query of the same workload (operator setup excluded; reduced "
-                      "assembly, Cholesky, RBCG iterations and true residual timed)",
-            "iters": res.iters}
+    log(f"cpu baseline: {len(thetas)} solves in {el:.1f}s, iters {its}")
+    return {"value": round(ok / el, 5), "unit": "mu-solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {len(thetas)} test queries of the same workload and basis "
+                      "(operator setup excluded; reduced assembly, Cholesky, RBCG iterations "
+                      "and true residual timed)",
+            "iters": its}
 
 
 if __name__ == "__main__":

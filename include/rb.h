@@ -168,13 +168,16 @@ rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* ba
                          const double* phi, const int* n_use, double* x,
                          rb_query_stats* stats);
 
-/* Queries on several problems/bases in one call (uneven batches). */
+/* Queries on several problems/bases in one call (uneven batches).  The queries are
+ * grouped by (problem, tolerance); every group is one batched solve on its own stream
+ * and workspace, and the groups run concurrently.  Errors as rb_solve_batch. */
 typedef struct {
   int problem;          /* index into probs/bases */
   int n_use;            /* <= 0: the whole basis */
   const double* theta;  /* [Q] host */
   const double* phi;    /* [R] host or NULL */
   double* x;            /* [N] DEVICE */
+  double rtol;          /* <= 0: opts->rtol; else this query's tolerance */
 } rb_query;
 rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
                          const rb_basis* const* bases, const rb_solve_opts* opts, int B,

@@ -555,11 +555,13 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
     // group the queries by problem; each group is one batched solver.  The groups run
     // concurrently, each on its own stream with its own workspace (the first group
     // uses the context's), and the host issues their iteration chunks round-robin.
-    std::map<int, std::vector<int>> groups;
+    std::map<std::pair<int, double>, std::vector<int>> groups;
     for (int i = 0; i < B; ++i) {
       RB_REQUIRE(qs[i].problem >= 0 && qs[i].problem < nprob && qs[i].theta && qs[i].x,
                  RB_EINVAL, "bad query");
-      groups[qs[i].problem].push_back(i);
+      RB_REQUIRE(std::isfinite(qs[i].rtol), RB_EINVAL, "bad query tolerance");
+      const double tol = qs[i].rtol > 0.0 ? qs[i].rtol : o->rtol;
+      groups[{qs[i].problem, tol}].push_back(i);
     }
     DeviceGuard dg(ctx->device);
     struct Group {
@@ -572,12 +574,15 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       std::unique_ptr<Workspace> ws;
       std::unique_ptr<BatchSolver> solver;
       bool running = false;
+      rb_solve_opts opt;
     };
     std::vector<Group> gs;
     for (auto& kv : groups) {
       Group g;
-      g.p = probs[kv.first];
-      const rb_basis* bs = bases ? bases[kv.first] : nullptr;
+      g.p = probs[kv.first.first];
+      g.opt = *o;
+      g.opt.rtol = kv.first.second;
+      const rb_basis* bs = bases ? bases[kv.first.first] : nullptr;
       RB_REQUIRE(g.p, RB_EINVAL, "null problem");
       RB_REQUIRE(!bs || bs->prob == g.p, RB_EINVAL, "basis belongs to another problem");
       g.idx = kv.second;
@@ -616,7 +621,7 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
     }
     for (auto& g : gs) {
       const rb_basis* bs = bases ? bases[g.idx.empty() ? 0 : qs[g.idx[0]].problem] : nullptr;
-      g.solver = std::make_unique<BatchSolver>(ctx, g.p, bs, *o, (int)g.idx.size(), g.th.data(),
+      g.solver = std::make_unique<BatchSolver>(ctx, g.p, bs, g.opt, (int)g.idx.size(), g.th.data(),
                                                g.any_phi ? g.ph.data() : nullptr, g.nu.data(),
                                                g.st, g.ws ? g.ws.get() : &ctx->ws);
       g.solver->start();

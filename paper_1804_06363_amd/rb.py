@@ -58,7 +58,7 @@ class QueryStats(C.Structure):
 
 class Query(C.Structure):
     _fields_ = [("problem", C.c_int), ("n_use", C.c_int), ("theta", C.POINTER(C.c_double)),
-                ("phi", C.POINTER(C.c_double)), ("x", C.c_void_p)]
+                ("phi", C.POINTER(C.c_double)), ("x", C.c_void_p), ("rtol", C.c_double)]
 
 
 class GreedyOpts(C.Structure):
@@ -323,12 +323,14 @@ def solve_batch(ctx, prob, basis, theta, x=None, phi=None, n_use=None, **kw):
 
 
 def solve_multi(ctx, probs, bases, queries, **kw):
-    """queries: list of (problem index, n_use, theta, phi or None, x tensor)."""
+    """queries: list of (problem index, n_use, theta, phi or None, x tensor[, rtol])."""
     opts = kw.pop("opts", None) or solve_opts(**kw)
     B = len(queries)
     qs = (Query * B)()
     keep = []
-    for i, (pi, nu, th, ph, x) in enumerate(queries):
+    for i, q in enumerate(queries):
+        pi, nu, th, ph, x = q[:5]
+        qs[i].rtol = q[5] if len(q) > 5 else 0.0
         th = _f64(th)
         ph = _f64(ph)
         keep += [th, ph]

@@ -52,6 +52,7 @@ class Workload:
     seed_train: int
     seed_test: int
     note: str = ""
+    rtol: float = 1e-10            # target true relative residual of the solves
 
     @property
     def N(self) -> int:
@@ -82,11 +83,15 @@ WORKLOADS = {
                       "3D 7-point, 255^3 interior, HBM-bound large case"),
 }
 
-# Uneven batch: grids mixed within one call.
+# Uneven batch: grids mixed within one call.  On 1023^2 with a kappa contrast of 1e4
+# the FP64 residual of the exact solution rounded to doubles is already 3e-11..1e-10
+# (eps * || |A| |x| || / ||f||; measured by sparse direct solves on 511^2 and scaled by
+# the h^-2 growth), so 1e-10 is at the rounding floor there and that grid targets 1e-9.
 UNEVEN_GRIDS = (
     Workload("u2d63", (63, 63), (4, 4), (0.01, 100.0), 60, 256, 256, 1003, 2003),
     Workload("u2d255", (255, 255), (4, 4), (0.01, 100.0), 60, 256, 256, 1003, 2003),
-    Workload("u2d1023", (1023, 1023), (4, 4), (0.01, 100.0), 60, 256, 256, 1003, 2003),
+    Workload("u2d1023", (1023, 1023), (4, 4), (0.01, 100.0), 60, 256, 256, 1003, 2003,
+             rtol=1e-9),
     Workload("u3d63", (63, 63, 63), (2, 2, 2), (0.01, 100.0), 60, 256, 256, 1003, 2003),
 )
 UNEVEN_N_CHOICES = (10, 20, 40, 60)
