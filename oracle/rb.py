@@ -19,6 +19,12 @@ Readings where the paper is silent (each also listed in the design notes):
     solves (same result as re-inverting each iteration)
   - beta is the ratio of step 10 of Alg. 3; "flexible" uses y_{k+1}^T (r_{k+1} - r_k)
   - iteration count = number of products A p
+  - adaptive basis size (Sec. 4.1, last paragraph): after each iteration, if
+    ||r_in|| / ||r_{k+1}|| < gamma, with r_in the residual the current search direction
+    was preconditioned from (r_k, or the replaced true residual after a restart), the
+    number of basis vectors used by the next preconditioner application grows by one,
+    up to the size of the basis; the preconditioner with n vectors uses the leading n
+    columns of W and the leading n x n block of A_N
 """
 from __future__ import annotations
 
@@ -122,17 +128,32 @@ class SolveResult:
 
 
 def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None,
-         keep_iterates=False, keep_vectors=False):
+         keep_iterates=False, keep_vectors=False, adapt=None):
     """x = RBCG(A, b, W) (Alg. 3) with the stopping rule described in the module doc.
 
-    precond: callable r -> y (one RBI step, or identity for plain CG).
+    precond: callable r -> y (one RBI step, or identity for plain CG); with adapt,
+        callable (r, n) -> y using the leading n basis vectors.
     fixed_iters: run exactly this many products A p (no stopping test) for iterate parity.
     keep_vectors: record every r_k and p_k (for orthogonality checks).
+    adapt: (gamma, n0, n_max) for the adaptive basis size of Sec. 4.1; the sizes used
+        by the successive preconditioner applications are returned in n_history.
     """
     nb = np.linalg.norm(b)
+    n = adapt[1] if adapt is not None else None
+    n_hist = []
+    r_in = [0.0]
+
+    def M(v):
+        r_in[0] = np.linalg.norm(v)
+        if adapt is None:
+            return precond(v)
+        n_hist.append(n)
+        return precond(v, n)
+
+    precond_call = M
     x = np.zeros_like(b)                    # step 0
     r = b.copy()                            # step 1 (x0 = 0, no product needed)
-    y = precond(r)                          # step 2
+    y = precond_call(r)                     # step 2
     p = y.copy()                            # step 3
     rho = r @ y
     it = 0
@@ -161,16 +182,18 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
         hist.append(rel_rec)
         if keep_iterates:
             iterates.append(x.copy())
+        if adapt is not None and r_in[0] < adapt[0] * np.linalg.norm(r):
+            n = min(n + 1, adapt[2])        # residual fell by less than gamma
         if fixed_iters is None and rel_rec <= rtol:   # step 8
             rt = b - A @ x
             if np.linalg.norm(rt) / nb <= rtol:
                 break
             r = rt                          # residual replacement and restart
-            y = precond(r)
+            y = precond_call(r)
             p = y.copy()
             rho = r @ y
             continue
-        y = precond(r)                      # step 9
+        y = precond_call(r)                 # step 9
         rho_new = y @ r
         if flexible:
             beta = (y @ (r - r_old)) / rho
@@ -185,6 +208,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
     converged = status == "ok" and rel_true <= rtol
     out = SolveResult(x, it, converged, rel_true, rel_rec, status, hist, iterates)
     out.vectors = vecs
+    out.n_history = n_hist
     return out
 
 
@@ -231,6 +255,34 @@ def make_preconditioner(op, theta, W, AN_q=None, smoother_kind=RBGS):
 def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, **kw):
     A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
     return rbcg(A, op.rhs(), M, **kw)
+
+
+class NestedRBPreconditioner:
+    """RBI preconditioners of every basis size n <= W.shape[1] for one parameter: the
+    leading n columns of W and the Cholesky factor of the leading n x n block of
+    A_N(theta), each factored on first use."""
+
+    def __init__(self, A, W, AN, smoother: Smoother):
+        self.A, self.W, self.AN, self.S = A, W, AN, smoother
+        self.cache = {}
+
+    def __call__(self, r, n):
+        if n not in self.cache:
+            Wn = self.W[:, :n]
+            L = cholesky(self.AN[:n, :n]) if n > 0 else None
+            self.cache[n] = RBPreconditioner(self.A, Wn, L, self.S)
+        return self.cache[n](r)
+
+
+def solve_rbcg_adaptive(op, theta, W, gamma, n0, AN_q=None, smoother_kind=RBGS, **kw):
+    """RBCG with the adaptive basis size (Sec. 4.1): starts with the leading n0 vectors
+    of W and grows by one whenever the residual falls by less than gamma per step."""
+    A = op.assemble(theta)
+    S = Smoother(A, op.colors(), smoother_kind)
+    if AN_q is None:
+        AN_q, _ = reduced_operators(op.A_q, [op.rhs()], W)
+    M = NestedRBPreconditioner(A, W, assemble_reduced(AN_q, theta), S)
+    return rbcg(A, op.rhs(), M, adapt=(gamma, n0, W.shape[1]), **kw)
 
 
 def solve_cg(op, theta, **kw):

@@ -231,3 +231,71 @@ def test_mgs_orthonormal_and_span():
         assert np.linalg.norm(X[:, j] - W @ (W.T @ X[:, j])) <= 1e-12 * np.linalg.norm(X[:, j])
     with pytest.raises(rb.Degenerate):
         rb.mgs(W, X[:, 3])
+
+
+# ---- adaptive basis size (Sec. 4.1, last paragraph) ----------------------------------
+def _adaptive_case(n_basis, dims=(15, 15), seed=3):
+    op = BlockDiffusion(dims, (2, 2))
+    W = random_orthonormal(seed, op.N, n_basis)
+    theta = np.array([0.3, 2.0, 5.0, 0.7])
+    return op, W, theta
+
+
+def test_adaptive_gamma_zero_is_fixed_size():
+    """gamma = 0: the size never grows, so the run equals RBCG with the leading n0
+    columns, iterate for iterate."""
+    op, W, theta = _adaptive_case(8)
+    a = rb.solve_rbcg_adaptive(op, theta, W, 0.0, 3, flexible=True, keep_iterates=True)
+    f = rb.solve_rbcg(op, theta, W[:, :3], flexible=True, keep_iterates=True)
+    assert a.iters == f.iters and set(a.n_history) == {3}
+    for xa, xf in zip(a.iterates, f.iterates):
+        assert np.array_equal(xa, xf)
+
+
+def test_adaptive_complete_basis_terminates():
+    """gamma huge: the size grows by one per iteration (capped at the basis size);
+    once the basis is complete (n = N) the preconditioner is A^-1 and CG stops at the
+    next step, so at most N - n0 + 2 iterations on a 5 x 5 grid."""
+    op = BlockDiffusion((5, 5), (2, 2))
+    W = random_orthonormal(4, op.N, op.N)
+    theta = np.array([0.3, 2.0, 5.0, 0.7])
+    n0 = 3
+    a = rb.solve_rbcg_adaptive(op, theta, W, 1e300, n0, flexible=True, rtol=1e-12)
+    assert a.converged and a.iters <= op.N - n0 + 2
+    assert a.n_history == [min(n0 + k, op.N) for k in range(len(a.n_history))]
+
+
+def test_adaptive_two_steps_by_hand():
+    """Two iterations built by hand from fixed-size preconditioners: gamma is set just
+    above the first step's reduction factor, so the second direction must come from the
+    preconditioner with one more vector (flexible beta)."""
+    op, W, theta = _adaptive_case(8)
+    A = op.assemble(theta)
+    b = op.rhs()
+    S = Smoother(A, op.colors(), RBGS)
+    AN, _ = rb.reduced_operators(op.A_q, [b], W)
+    ANt = rb.assemble_reduced(AN, theta)
+
+    def M(n):
+        return rb.RBPreconditioner(A, W[:, :n], rb.cholesky(ANt[:n, :n]), S)
+
+    n0 = 2
+    r0 = b.copy()
+    y0 = M(n0)(r0)
+    p0 = y0
+    a0 = (r0 @ y0) / (p0 @ (A @ p0))
+    x1 = a0 * p0
+    r1 = r0 - a0 * (A @ p0)
+    ratio = np.linalg.norm(r0) / np.linalg.norm(r1)
+    gamma = 1.5 * ratio                       # ratio < gamma: grow to n0 + 1
+    y1 = M(n0 + 1)(r1)
+    beta = (y1 @ (r1 - r0)) / (r0 @ y0)
+    p1 = y1 + beta * p0
+    a1 = (r1 @ y1) / (p1 @ (A @ p1))
+    x2 = x1 + a1 * p1
+    ad = rb.solve_rbcg_adaptive(op, theta, W, gamma, n0, flexible=True, fixed_iters=2)
+    assert ad.n_history[:2] == [n0, n0 + 1]
+    assert np.linalg.norm(ad.x - x2) <= 1e-13 * np.linalg.norm(x2)
+    # and with gamma below the reduction factor the size stays
+    ad2 = rb.solve_rbcg_adaptive(op, theta, W, 0.5 * ratio, n0, flexible=True, fixed_iters=2)
+    assert ad2.n_history[:2] == [n0, n0]
