@@ -71,6 +71,19 @@ def masked_argmax(values, excluded):
     return int(np.argmax(v))  # first (lowest) index among ties
 
 
+def _append(op, W, AN_q, fN, w):
+    """W_N = [W_{N-1}, w] and the reduced operators grown by one row/column (eq. 12c)."""
+    n = W.shape[1]
+    W = np.column_stack([W, w])
+    newAN = np.zeros((op.Q, n + 1, n + 1))
+    newAN[:, :n, :n] = AN_q
+    for q, Aq in enumerate(op.A_q):
+        col = W.T @ (Aq @ w)
+        newAN[q, :, n] = col
+        newAN[q, n, :] = col
+    return W, newAN, np.append(fN, w @ op.rhs())
+
+
 def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
                     snapshot_rtol=1e-10, snapshot_maxit=5000, keep_indicators=False,
                     snapshot_flexible=True):
@@ -101,17 +114,7 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
         picks.append(mu_next)
         excluded.add(mu_next)
         snap_iters.append(res.iters)
-        # grow the reduced operators by one row/column (eq. 12c)
-        n = W.shape[1]
-        W = np.column_stack([W, w])
-        newAN = np.zeros((op.Q, n + 1, n + 1))
-        newAN[:, :n, :n] = AN_q
-        for q, Aq in enumerate(op.A_q):
-            col = W.T @ (Aq @ w)
-            newAN[q, :, n] = col
-            newAN[q, n, :] = col
-        AN_q = newAN
-        fN = np.append(fN, w @ f)
+        W, AN_q, fN = _append(op, W, AN_q, fN, w)
         ind = indicator_values(op, W, AN_q, fN, thetas, indicator)      # step 5
         if keep_indicators:
             all_ind.append(ind.copy())
@@ -121,3 +124,38 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
         mu_next = masked_argmax(ind, excluded)                           # step 6
         maxind.append(float(ind[mu_next]))
     return GreedyResult(W, picks, maxind, AN_q, fN, snap_iters, all_ind)
+
+
+def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
+                          snapshot_flexible=True):
+    """Steps 3-4 of Alg. 4 for a given sequence of parameters: each snapshot is solved
+    by RBCG with the basis built so far and orthonormalised into it (degenerate
+    snapshots are skipped).  With the parameters picked by a greedy on a coarse grid
+    this is the multi-fidelity construction of Sec. 4.2 (last paragraph).  picks lists
+    the indices into thetas that entered the basis."""
+    W = np.zeros((op.N, 0))
+    AN_q = np.zeros((op.Q, 0, 0))
+    fN = np.zeros(0)
+    picks, snap_iters = [], []
+    for i, th in enumerate(thetas):
+        res = solve_rbcg(op, th, W, AN_q if W.shape[1] else None, rtol=snapshot_rtol,
+                         maxit=snapshot_maxit, flexible=snapshot_flexible)  # step 3
+        try:
+            w = mgs(W, res.x)                                               # step 4
+        except Degenerate:
+            continue
+        picks.append(i)
+        snap_iters.append(res.iters)
+        W, AN_q, fN = _append(op, W, AN_q, fN, w)
+    return GreedyResult(W, picks, [], AN_q, fN, snap_iters)
+
+
+def multi_fidelity(op_coarse, op_fine, thetas, n_max, indicator="residual", **kw):
+    """Greedy (Alg. 4) on the coarse problem, then the snapshots of its picks solved on
+    the fine problem (Sec. 4.2, last paragraph).  Both problems share the parameter
+    functions Theta_q (the same kappa blocks)."""
+    g = adaptive_greedy(op_coarse, thetas, n_max, indicator=indicator, **kw)
+    sel = [thetas[i] for i in g.picks]
+    fine = basis_from_parameters(op_fine, sel)
+    fine.picks = [g.picks[i] for i in fine.picks]
+    return g, fine

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import greedy, mlp
+from workloads import log_uniform_mu
 from oracle.operator import BlockDiffusion
 
 
@@ -121,3 +122,31 @@ def test_adam_first_step_is_signed_lr():
     opt = mlp.Adam(params, lr=0.1, eps=0.0)
     opt.step(params, g)
     assert np.allclose(params["w"], [0.9, -1.9, 2.9], rtol=0, atol=1e-15)
+
+
+# ---- multi-fidelity construction (Sec. 4.2, last paragraph) ----------------------------
+def test_basis_from_greedy_picks_reproduces_greedy_basis():
+    """Steps 3-4 replayed on the greedy's own picks give the greedy's basis exactly."""
+    op = BlockDiffusion((15, 15), (2, 2))
+    thetas = log_uniform_mu(11, 40, op.Q, 0.1, 10.0)
+    g = greedy.adaptive_greedy(op, thetas, 6, indicator="residual")
+    b = greedy.basis_from_parameters(op, [thetas[i] for i in g.picks])
+    assert b.picks == list(range(6))
+    assert np.array_equal(b.W, g.W) and np.array_equal(b.AN_q, g.AN_q)
+
+
+def test_multi_fidelity_basis_spans_fine_snapshots():
+    """Coarse picks, fine snapshots: W is orthonormal, every fine snapshot lies in its
+    span to the snapshot tolerance, and the reduced operators are W^T A_q W."""
+    from oracle import rb as orb
+    coarse, fine = BlockDiffusion((15, 15), (2, 2)), BlockDiffusion((31, 31), (2, 2))
+    thetas = log_uniform_mu(12, 40, coarse.Q, 0.1, 10.0)
+    g, mf = greedy.multi_fidelity(coarse, fine, thetas, 5)
+    W = mf.W
+    assert W.shape == (fine.N, 5) and mf.picks == g.picks
+    assert np.abs(W.T @ W - np.eye(5)).max() <= 1e-13
+    for i in g.picks:
+        x = orb.solve_cg(fine, thetas[i], rtol=1e-12).x
+        assert np.linalg.norm(x - W @ (W.T @ x)) <= 1e-8 * np.linalg.norm(x)
+    AN, _ = orb.reduced_operators(fine.A_q, [fine.rhs()], W)
+    assert np.abs(AN - mf.AN_q).max() <= 1e-12 * np.abs(AN).max()
