@@ -27,6 +27,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources of the dominant kernel: a traffic figure measured on other sources is stale
+KERNEL_SOURCES = ("paper_1804_06363_amd/csrc/stencil.hip", "paper_1804_06363_amd/csrc/common.h",
+                  "paper_1804_06363_amd/csrc/kernels.h")
+TRAFFIC_FILE = "profiles/k_pass_b_3d127_B256_fp32.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec, B):
+    """HBM bytes per launch of k_pass_b from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the calibration kernels), or None when the summary is for
+    another configuration or the kernel's sources changed since it was taken."""
+    import re
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if workload != "3d127" or prec != "fp32" or B != 256 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        m = re.search(r"^traffic_bytes_per_launch: (\d+) sources_sha256: ([0-9a-f]+)$", f.read(),
+                      re.M)
+    if not m or m.group(2) != kernel_source_hash():
+        return None
+    return int(m.group(1))
 
 
 def log(*a):
@@ -133,7 +162,7 @@ def main():
     achieved = bytes_b / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0
     roofline = {"kernel": "k_pass_b", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(args.workload, args.prec, B),
                 "bytes_per_launch": round(bytes_b / max(n_b, 1)),
                 "avg_launch_us": round(ms_b / max(n_b, 1) * 1e3, 1)}
 
@@ -219,19 +248,34 @@ def uneven_leg(rb, torch):
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda:0") for g, _, _ in qs]
     queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
-    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True)
+    # small bases on the 1023^2 grid need thousands of iterations
+    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True, maxit=50000)
     rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
     st = rb.solve_multi(ctx, probs, bases, queries, opts=opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= tol)).sum())
+    good = (st.status == rb.RB_OK) & (st.rel_res_true <= tol)
+    ok = int(good.sum())
+    gidx = np.array([g for g, _, _ in qs])
+    nidx = np.array([nu for _, nu, _ in qs])
+    groups = {}
+    for g, wk in enumerate(UNEVEN_GRIDS):
+        for nu in sorted(set(nidx.tolist())):
+            m = (gidx == g) & (nidx == nu)
+            if m.any():
+                groups[f"{wk.name}/n{nu}"] = {"queries": int(m.sum()), "converged": int(good[m].sum()),
+                                             "iters_mean": round(float(st.iters[m].mean()), 1),
+                                             "iters_max": int(st.iters[m].max())}
+                log(f"uneven {wk.name} n={nu}: {int(m.sum())} queries, {int(good[m].sum())} "
+                    f"converged, iters mean {st.iters[m].mean():.1f} max {st.iters[m].max()}, "
+                    f"status {np.bincount(st.status[m], minlength=6).tolist()}")
     log(f"uneven: {len(qs)} queries in {el:.3f}s -> {ok / el:.1f} mu-solves/s, "
         f"iters mean {st.iters.mean():.1f}, max rel res {st.rel_res_true.max():.2e}")
     return {"value": round(ok / el, 2), "unit": "mu-solves/s", "queries": len(qs),
             "converged": ok, "seconds": round(el, 4), "iters_mean": round(float(st.iters.mean()), 2),
-            "max_rel_res_over_rtol": float((st.rel_res_true / tol).max())}
+            "max_rel_res_over_rtol": float((st.rel_res_true / tol).max()), "groups": groups}
 
 
 def learned_leg(rb):

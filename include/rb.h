@@ -148,6 +148,15 @@ typedef struct {
                       (problem shape, batch, basis size, precision) is solved and keep
                       the fastest in the context (and in the JSON file named by
                       RB_AUTOTUNE_CACHE, if set); 0: cached choice or built-in default */
+  int stencil_kind; /* 3D passes A and B: 0 = autotuned / default, 1 = chunked over storage
+                       positions, 2 = marching along z with the plane in LDS (3D only; other
+                       grids use 1).  Changes speed and summation order only. */
+  double adapt_gamma; /* RBCG only.  > 0: adaptive basis size (Sec. 4.1, last
+                         paragraph): query b starts with n_use[b] vectors (1 if n_use is
+                         NULL) and uses one more (up to the basis size) for the next
+                         preconditioner application whenever its residual fell by less
+                         than this factor in an iteration; 0: fixed size.  Use with
+                         beta_flexible (the preconditioner changes between iterations). */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 
@@ -156,6 +165,7 @@ typedef struct {
   double rel_res_true;
   double rel_res_recursive;
   rb_status status;
+  int n_used; /* basis vectors used by the last preconditioner application */
 } rb_query_stats;
 
 /* B queries on one problem and basis.  theta [B][Q] host; phi [B][R] host or NULL
@@ -250,6 +260,18 @@ typedef struct {
 rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob, const rb_greedy_opts* opts,
                            int64_t M, int P, const double* mu, const double* theta,
                            const double* phi, rb_basis** out, rb_greedy_report* rep);
+
+/* Steps 3-4 of Alg. 4 for a given sequence of K <= 80 parameters: each snapshot
+ * x(theta_k) = RBCG(A(theta_k), f, W_{k-1}) (snapshot_rtol, snapshot_maxit,
+ * snapshot_flexible of opts; the other fields are ignored) is orthonormalised into the
+ * basis; a degenerate snapshot (already in the span) is skipped.  With the picks of a
+ * greedy on a coarse grid (rb_greedy_report.picks) this is the multi-fidelity offline
+ * build of Sec. 4.2 (last paragraph).  theta [K][Q], phi [K][R] or NULL, host.
+ * rep (nullable): n_built, picks = indices k that entered the basis, snapshot_iters,
+ * seconds.  A failed snapshot solve returns its status and no basis. */
+rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* prob,
+                                   const rb_greedy_opts* opts, int K, const double* theta,
+                                   const double* phi, rb_basis** out, rb_greedy_report* rep);
 
 /* ---- MLP surrogate of the greedy indicator (not in the paper) ----------------
  * Diagnostics of the network rb_offline_build trains when use_surrogate is set.

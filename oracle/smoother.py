@@ -20,34 +20,37 @@ RBGS, RBGS_SYM, JACOBI, NONE = "rbgs", "rbgs_sym", "jacobi", "none"
 
 
 class Smoother:
+    """colors: colour class of every unknown (0 .. C-1) such that no two unknowns of one
+    class are coupled; one forward sweep updates the classes in increasing order, each
+    class from the latest values of all the others (Gauss-Seidel in the class-major
+    ordering).  The stencil problems use the red-black colouring (C = 2); general
+    sparse problems a greedy colouring."""
+
     def __init__(self, A, colors, kind=RBGS, omega=2.0 / 3.0):
         self.kind = kind
         self.A = sp.csr_matrix(A)
         self.D = self.A.diagonal()
-        self.red = np.flatnonzero(colors == 0)
-        self.black = np.flatnonzero(colors == 1)
-        self.A_RB = self.A[self.red][:, self.black]
-        self.A_BR = self.A[self.black][:, self.red]
+        colors = np.asarray(colors)
+        ncol = int(colors.max()) + 1 if colors.size else 0
+        self.sets = [np.flatnonzero(colors == c) for c in range(ncol)]
+        self.rest = [np.flatnonzero(colors != c) for c in range(ncol)]
+        self.blocks = [self.A[S][:, O] for S, O in zip(self.sets, self.rest)]
         self.omega = omega
 
-    def _red(self, b, y):
-        # y_R <- D_R^-1 (b_R - A_RB y_B)
-        y[self.red] = (b[self.red] - self.A_RB @ y[self.black]) / self.D[self.red]
-
-    def _black(self, b, y):
-        # y_B <- D_B^-1 (b_B - A_BR y_R)
-        y[self.black] = (b[self.black] - self.A_BR @ y[self.red]) / self.D[self.black]
+    def _sweep(self, c, b, y):
+        # y_c <- D_c^-1 (b_c - A_{c,rest} y_rest)
+        S = self.sets[c]
+        y[S] = (b[S] - self.blocks[c] @ y[self.rest[c]]) / self.D[S]
 
     def __call__(self, b, y0):
         y = np.array(y0, dtype=np.float64, copy=True)
+        C = len(self.sets)
         if self.kind == RBGS:
-            self._red(b, y)
-            self._black(b, y)
+            for c in range(C):
+                self._sweep(c, b, y)
         elif self.kind == RBGS_SYM:
-            self._red(b, y)
-            self._black(b, y)
-            self._black(b, y)
-            self._red(b, y)
+            for c in list(range(C)) + list(range(C - 1, -1, -1)):
+                self._sweep(c, b, y)
         elif self.kind == JACOBI:
             y = y + self.omega * (b - self.A @ y) / self.D
         elif self.kind == NONE:

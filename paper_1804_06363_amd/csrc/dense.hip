@@ -827,6 +827,10 @@ __global__ __launch_bounds__(256) void k_fin_rr(const double* __restrict__ part,
     q.iters[b] = it;
     const double rel = sqrt(rr / q.fnorm2[b]);
     q.rel_rec[b] = rel;
+    if (q.gamma2 > 0.0) {  // adaptive basis size (Sec. 4.1)
+      if (q.rr_in[b] < q.gamma2 * rr) q.nuse[b] = min(q.nuse[b] + 1, q.nmax);
+      q.rr_in[b] = rr;
+    }
     if (fixed) return;
     if (rel <= rtol) {
       q.flag[b] = 1;
@@ -859,6 +863,7 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
       q.status[b] = RB_ENOCONV;
     } else {
       q.restart[b] = 1;
+      if (q.gamma2 > 0.0) q.rr_in[b] = rr;  // the replaced residual is preconditioned next
     }
   }
 }

@@ -106,6 +106,7 @@ struct Buf {
 struct TuneConfig {
   int qpb_a = 0, qpb_b = 0, qpb_gs = 0;  // queries per block of pass A / pass B / sweeps
   int proj_target = 0;                   // projection: target number of blocks
+  int kind_a = 0, kind_b = 0;            // pass A / B: 0 default, 1 chunked, 2 z-marching
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

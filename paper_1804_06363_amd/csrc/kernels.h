@@ -23,6 +23,13 @@ struct QState {
   int* iters;
   int* flag;     // true-residual check pending
   int* restart;  // next beta = 0 (p = y)
+  // adaptive basis size (gamma2 > 0): nuse[b] grows by one, up to nmax, when
+  // ||r_in||^2 < gamma2 ||r_new||^2, with rr_in the squared norm of the residual the
+  // current direction was preconditioned from
+  int* nuse = nullptr;
+  double* rr_in = nullptr;
+  double gamma2 = 0.0;
+  int nmax = 0;
 };
 
 struct ProjPlan {
@@ -49,13 +56,15 @@ int stencil_chunks_all(int N);
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                   const int* flag, double* part, hipStream_t s);
+// passes A and B return the number of partial sums per query they wrote (at most
+// stencil_chunks_all(N); row stride stays stencil_chunks_all(N) in the solver's arrays)
 template <typename TY>
-void launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
-                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
-                   const int* active, double* part, hipStream_t s);
-void launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
-                   double* x, const double* r_in, double* r_out, const double* alpha,
-                   const int* active, double* part, hipStream_t s);
+int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
+                  int64_t y_ld, const double* p_old, double* p_new, const double* beta,
+                  const int* active, double* part, hipStream_t s);
+int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
+                  double* x, const double* r_in, double* r_out, const double* alpha,
+                  const int* active, double* part, hipStream_t s);
 template <typename TY>
 void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
                      int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,

@@ -344,3 +344,60 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
     return RB_EINVAL;
   }
 }
+
+// Steps 3-4 of Alg. 4 for a given parameter sequence (the multi-fidelity construction of
+// Sec. 4.2: the parameters are the picks of a greedy on a coarse grid).
+extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* prob,
+                                              const rb_greedy_opts* opts, int K,
+                                              const double* theta, const double* phi,
+                                              rb_basis** out, rb_greedy_report* rep) {
+  try {
+    RB_REQUIRE(ctx && prob && opts && theta && out, RB_EINVAL, "null argument");
+    RB_REQUIRE(opts->struct_size == sizeof(rb_greedy_opts), RB_EINVAL,
+               "rb_greedy_opts.struct_size mismatch");
+    RB_REQUIRE(K >= 1 && K <= 80, RB_EINVAL, "K must be 1..80");
+    for (int64_t i = 0; i < (int64_t)K * prob->g.Q; ++i)
+      RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");
+    const auto t0 = std::chrono::steady_clock::now();
+    int dev_old = 0;
+    (void)hipGetDevice(&dev_old);
+    RB_HIP(hipSetDevice(ctx->device));
+    rb_greedy_opts o = *opts;
+    o.n_max = K;
+    o.use_surrogate = 0;
+    GreedyState gs(ctx, prob, o, K, theta, phi);
+    std::vector<int64_t> used;
+    std::vector<int> snap_it;
+    for (int i = 0; i < K; ++i) {
+      const int it = gs.snapshot(i);            // step 3
+      if (!gs.orthonormalize_append()) continue;  // step 4; degenerate: skipped
+      used.push_back(i);
+      snap_it.push_back(it);
+      gs.bs->picks.push_back(i);
+    }
+    RB_REQUIRE(gs.bs->n > 0, RB_EDEGENERATE, "every snapshot was degenerate");
+    (void)hipSetDevice(dev_old);
+    if (rep) {
+      rep->n_built = gs.bs->n;
+      for (size_t i = 0; i < used.size(); ++i) {
+        if (rep->picks) rep->picks[i] = used[i];
+        if (rep->max_indicator) rep->max_indicator[i] = 0.0;
+        if (rep->snapshot_iters) rep->snapshot_iters[i] = snap_it[i];
+      }
+      rep->true_evals = 0;
+      rep->full_sweeps = 0;
+      rep->seconds =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      rep->mlp_loss = 0.0;
+      rep->surrogate_fallbacks = 0;
+    }
+    *out = gs.bs.release();
+    return RB_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RB_EINVAL;
+  }
+}

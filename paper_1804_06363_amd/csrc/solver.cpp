@@ -25,6 +25,8 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   }
   n = basis ? basis->n : 0;
   std::vector<int> nu(B, n);
+  adaptive = opt.adapt_gamma > 0.0 && opt.solver == RB_SOLVER_RBCG && n > 0;
+  if (adaptive && !n_use) std::fill(nu.begin(), nu.end(), 1);
   if (n_use && basis)
     for (int i = 0; i < B; ++i) {
       RB_REQUIRE(n_use[i] >= 0, RB_EINVAL, "n_use must be >= 0");
@@ -89,6 +91,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
                std::to_string((int)opt.precond_prec) + "|s" + std::to_string((int)opt.smoother);
     ctx->tuner.load();
     if (const TuneConfig* c = ctx->tuner.find(tune_key)) tc = *c;
+    if (opt.stencil_kind) tc.kind_a = tc.kind_b = opt.stencil_kind;
   }
   // projection plan first: for batches it reads residual rows in whole query tiles
   if (n > 0) {
@@ -134,14 +137,19 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   }
 
   // per-query scalars
-  qbuf = get_ws(WS_Q, (sizeof(double) * 7 + sizeof(int) * 5) * (size_t)B);
+  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 5) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
   takeD(q.fnorm2); takeD(q.rho); takeD(q.alpha); takeD(q.beta); takeD(q.rel_rec);
-  takeD(q.rel_true); takeD(q.scalar);
+  takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in);
   takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
-  launch_fill<double>(q.fnorm2, 0, 7 * (int64_t)B, 1, 0.0, st);
+  launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
+  if (adaptive) {
+    q.nuse = nuse_d.as<int>();
+    q.gamma2 = opt.adapt_gamma * opt.adapt_gamma;
+    q.nmax = n;
+  }
   launch_fill<int>(q.status, 0, (int64_t)B, 1, (int)RB_OK, st);
   launch_fill<int>(q.active, 0, (int64_t)B, 1, 1, st);
   launch_fill<int>(q.iters, 0, 3 * (int64_t)B, 1, 0, st);  // iters, flag, restart
@@ -155,8 +163,10 @@ BatchSolver::~BatchSolver() {
 // reduced matrix is not SPD is retired with RB_ENOTSPD.
 void BatchSolver::factor() {
   if (n == 0) return;
+  // adaptive size: factor the whole reduced matrix; the leading n x n block of the
+  // factor is the factor of the leading block, so one factorization serves every size
   launch_cholesky(basis->AN.as<double>(), n, prob->g.Q, B, theta_d.as<double>(),
-                  nuse_d.as<int>(), L.as<double>(), q.status, s());
+                  adaptive ? nullptr : nuse_d.as<int>(), L.as<double>(), q.status, s());
   // status != OK -> inactive
   std::vector<int> st(B);
   RB_HIP(hipMemcpyAsync(st.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost, s()));
@@ -260,6 +270,8 @@ void BatchSolver::init_cg() {
   const int ci = launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_,
                                  B, part_m.as<double>(), pt, st);
   launch_fin_sum(part_m.as<double>(), ci, ci, q.fnorm2, nullptr, B, st);
+  if (adaptive)  // r_0 = f is preconditioned first
+    RB_HIP(hipMemcpyAsync(q.rr_in, q.fnorm2, sizeof(double) * B, hipMemcpyDeviceToDevice, st));
   factor();
   launch_fill<int>(q.restart, 0, B, 1, 1, st);
   precondition(r0.as<double>(), nullptr);
@@ -279,25 +291,26 @@ void BatchSolver::iterate_cg(int k) {
   double* rin = (flex && (k & 1)) ? r1.as<double>() : r0.as<double>();
   double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
   // step 11 of the previous iteration fused with step 5's product: p = y + beta p; A p
+  int ca, cb;
   {
-  ProfScope ps(ctx, "pass_a", st);
-  if (y32)
-    launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
-                         q.beta, q.active, part_m.as<double>(), st);
-  else
-    launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, pold, pnew,
-                          q.beta, q.active, part_m.as<double>(), st);
+    ProfScope ps(ctx, "pass_a", st);
+    if (y32)
+      ca = launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, pold, pnew,
+                                q.beta, q.active, part_m.as<double>(), st);
+    else
+      ca = launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, pold, pnew,
+                                 q.beta, q.active, part_m.as<double>(), st);
   }
-  launch_fin_alpha(part_m.as<double>(), cN, cN, q, B, st);
+  launch_fin_alpha(part_m.as<double>(), cN, ca, q, B, st);
   // steps 6-7: x += alpha p, r -= alpha A p
   {
     ProfScope ps(ctx, "pass_b", st);
-    launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha, q.active,
-                  part_m.as<double>(), st);
+    cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha,
+                       q.active, part_m.as<double>(), st);
   }
   // step 8
   const bool fixed = opt.fixed_iters > 0;
-  launch_fin_rr(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, fixed, st);
+  launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
     ProfScope ps(ctx, "true_residual", st);
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
@@ -415,10 +428,14 @@ void BatchSolver::final_true_residual() {
 }
 
 // Times candidate tiles on this solve's own (not yet initialised) buffers and keeps the
-// fastest: queries per block of pass A, pass B and the colour sweeps, and the number of
-// projection blocks.  Runs before init, so the values it computes are overwritten.
+// fastest: kind (chunked or z-marching) and queries per block of pass A and pass B,
+// queries per block of the colour sweeps, and the number of projection blocks (timed
+// with the reduction of their partials).  Runs before init, so the values it computes
+// are overwritten.
 void BatchSolver::autotune() {
-  if (!opt.autotune || ctx->tuner.find(tune_key) || opt.solver == RB_SOLVER_RBI) return;
+  if (!opt.autotune || ctx->tuner.find(tune_key) || opt.solver == RB_SOLVER_RBI ||
+      opt.stencil_kind)
+    return;
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
@@ -442,28 +459,38 @@ void BatchSolver::autotune() {
   const int caps[4] = {1, 2, 4, 8};
   TuneConfig best = tc, cur = tc;
   float ta = 1e30f, tb = 1e30f, tg = 1e30f;
+  for (int kind : {1, 2}) {  // chunked, z-marching (3D only)
+    if (kind == 2 && g.dim != 3) break;
+    for (int c : caps) {
+      if (c > B || (kind == 2 && c > 4)) break;
+      cur = best;
+      cur.qpb_a = c;
+      cur.kind_a = kind;
+      set_stencil_tiles(cur);
+      const float t1 = timed([&] {
+        if (y32)
+          launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, p0.as<double>(),
+                               p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
+        else
+          launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_,
+                                p0.as<double>(), p1.as<double>(), q.beta, q.active,
+                                part_m.as<double>(), st);
+      });
+      if (t1 < ta) { ta = t1; best.qpb_a = c; best.kind_a = kind; }
+      cur = best;
+      cur.qpb_b = c;
+      cur.kind_b = kind;
+      set_stencil_tiles(cur);
+      const float t2 = timed([&] {
+        launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
+                      r0.as<double>(), r0.as<double>(), q.alpha, q.active, part_m.as<double>(),
+                      st);
+      });
+      if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; }
+    }
+  }
   for (int c : caps) {
     if (c > B) break;
-    cur = best;
-    cur.qpb_a = c;
-    set_stencil_tiles(cur);
-    const float t1 = timed([&] {
-      if (y32)
-        launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, p0.as<double>(),
-                             p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
-      else
-        launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_, p0.as<double>(),
-                              p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
-    });
-    if (t1 < ta) { ta = t1; best.qpb_a = c; }
-    cur = best;
-    cur.qpb_b = c;
-    set_stencil_tiles(cur);
-    const float t2 = timed([&] {
-      launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(), r0.as<double>(),
-                    r0.as<double>(), q.alpha, q.active, part_m.as<double>(), st);
-    });
-    if (t2 < tb) { tb = t2; best.qpb_b = c; }
     cur = best;
     cur.qpb_gs = c;
     set_stencil_tiles(cur);
@@ -487,6 +514,10 @@ void BatchSolver::autotune() {
       const float t = timed([&] {
         launch_projection(pl, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
                           projpart.p, st);
+        // the reduction of the chunk partials grows with the number of chunks
+        launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, pl.chunks, B, pl.nj,
+                            n, nuse_d.as<int>(), L.as<double>(), q.active, nullptr, nullptr,
+                            nullptr, e_ld, false, st);
       });
       if (t < tp) { tp = t; best.proj_target = target; }
     }
@@ -595,8 +626,10 @@ void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_s
   hipStream_t st = s();
   final_true_residual();
   if (x_user) launch_from_storage(*prob, B, x.as<double>(), ld(), x_user, user_ld, st);
-  std::vector<int> it(B), stt(B);
+  std::vector<int> it(B), stt(B), nu(B, n);
   std::vector<double> rr(B), rec(B), fn(B);
+  if (n > 0)
+    RB_HIP(hipMemcpyAsync(nu.data(), nuse_d.p, sizeof(int) * B, hipMemcpyDeviceToHost, st));
   RB_HIP(hipMemcpyAsync(it.data(), q.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
   RB_HIP(hipMemcpyAsync(stt.data(), q.status, sizeof(int) * B, hipMemcpyDeviceToHost, st));
   RB_HIP(hipMemcpyAsync(rr.data(), q.scalar, sizeof(double) * B, hipMemcpyDeviceToHost, st));
@@ -609,6 +642,7 @@ void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_s
     stats[i].status = (rb_status)stt[i];
     stats[i].rel_res_true = std::sqrt(rr[i] / fn[i]);
     stats[i].rel_res_recursive = rec[i];
+    stats[i].n_used = n > 0 ? nu[i] : 0;
   }
 }
 

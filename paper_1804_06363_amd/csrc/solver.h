@@ -24,6 +24,7 @@ struct BatchSolver {
   int cN = 1, cR = 1, cB = 1;  // partial-sum chunks for all / red / black nodes
   int pstride = 1;             // per-query stride of the partial-sum arrays
   bool y32 = false;            // y stored in FP32
+  bool adaptive = false;       // adaptive basis size (opt.adapt_gamma > 0)
   int rrows = 0;               // rows allocated for r (padded for the projection)
   ProjPlan plan;
   const void* Wsh = nullptr;   // basis in the preconditioner's precision

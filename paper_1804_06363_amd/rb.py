@@ -48,12 +48,13 @@ class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("solver", C.c_int), ("precond_prec", C.c_int),
                 ("smoother", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
                 ("beta_flexible", C.c_int), ("use_graph", C.c_int), ("fixed_iters", C.c_int),
-                ("check_every", C.c_int), ("autotune", C.c_int)]
+                ("check_every", C.c_int), ("autotune", C.c_int), ("stencil_kind", C.c_int),
+                ("adapt_gamma", C.c_double)]
 
 
 class QueryStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("rel_res_true", C.c_double),
-                ("rel_res_recursive", C.c_double), ("status", C.c_int)]
+                ("rel_res_recursive", C.c_double), ("status", C.c_int), ("n_used", C.c_int)]
 
 
 class Query(C.Structure):
@@ -123,6 +124,8 @@ _sig("rb_topk", [_P, C.c_int, C.c_int, _F, _I, _I, _I])
 _sig("rb_greedy_opts_default", [C.POINTER(GreedyOpts)], None)
 _sig("rb_offline_build", [_P, _P, C.POINTER(GreedyOpts), C.c_int64, C.c_int, _D, _D, _D,
                           C.POINTER(_P), C.POINTER(GreedyReport)])
+_sig("rb_basis_from_parameters", [_P, _P, C.POINTER(GreedyOpts), C.c_int, _D, _D,
+                                  C.POINTER(_P), C.POINTER(GreedyReport)])
 
 EXPORTED = [
     "rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_version",
@@ -131,7 +134,7 @@ EXPORTED = [
     "rb_basis_from_host", "rb_basis_info", "rb_basis_save", "rb_basis_load", "rb_basis_destroy",
     "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi", "rb_apply_batch",
     "rb_precond_batch", "rb_project_batch", "rb_reduced_factor_batch",
-    "rb_greedy_opts_default", "rb_offline_build",
+    "rb_greedy_opts_default", "rb_offline_build", "rb_basis_from_parameters",
     "rb_mlp_forward", "rb_mlp_loss_grad", "rb_mlp_train", "rb_topk",
 ]
 
@@ -272,8 +275,12 @@ class Basis:
             pass
 
 
+STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2}
+
+
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,
-               flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False):
+               flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False,
+               stencil="auto", adapt_gamma=0.0):
     o = SolveOpts()
     _lib.rb_solve_opts_default(C.byref(o))
     o.solver = SOLVER[solver]
@@ -286,6 +293,8 @@ def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=20
     o.fixed_iters = fixed_iters
     o.check_every = check_every
     o.autotune = int(autotune)
+    o.stencil_kind = STENCIL_KIND[stencil]
+    o.adapt_gamma = adapt_gamma
     return o
 
 
@@ -295,13 +304,15 @@ class Stats:
     rel_res_true: np.ndarray
     rel_res_recursive: np.ndarray
     status: np.ndarray
+    n_used: np.ndarray
 
 
 def _stats(arr, B):
     return Stats(np.array([arr[i].iters for i in range(B)]),
                  np.array([arr[i].rel_res_true for i in range(B)]),
                  np.array([arr[i].rel_res_recursive for i in range(B)]),
-                 np.array([arr[i].status for i in range(B)]))
+                 np.array([arr[i].status for i in range(B)]),
+                 np.array([arr[i].n_used for i in range(B)]))
 
 
 def solve_batch(ctx, prob, basis, theta, x=None, phi=None, n_use=None, **kw):
@@ -417,6 +428,25 @@ def offline_build(ctx, prob, theta, mu=None, phi=None, **kw):
               "snapshot_iters": sit[:nb].tolist(), "true_evals": rep.true_evals,
               "full_sweeps": rep.full_sweeps, "seconds": rep.seconds, "mlp_loss": rep.mlp_loss,
               "surrogate_fallbacks": rep.surrogate_fallbacks}
+    return Basis(ctx, prob, h), report
+
+
+def basis_from_parameters(ctx, prob, theta, phi=None, **kw):
+    """Steps 3-4 of Alg. 4 for the given parameters (multi-fidelity build, Sec. 4.2)."""
+    theta = _f64(np.atleast_2d(theta))
+    K = theta.shape[0]
+    opts = greedy_opts(**kw)
+    picks = np.zeros(K, dtype=np.int64)
+    sit = np.zeros(K, dtype=np.int32)
+    rep = GreedyReport()
+    rep.picks = picks.ctypes.data_as(C.POINTER(C.c_int64))
+    rep.snapshot_iters = sit.ctypes.data_as(_I)
+    h = _P()
+    _check(_lib.rb_basis_from_parameters(ctx.h, prob.h, C.byref(opts), K, _dptr(theta),
+                                         _dptr(_f64(phi)), C.byref(h), C.byref(rep)))
+    nb = rep.n_built
+    report = {"n_built": nb, "picks": picks[:nb].tolist(), "snapshot_iters": sit[:nb].tolist(),
+              "seconds": rep.seconds}
     return Basis(ctx, prob, h), report
 
 

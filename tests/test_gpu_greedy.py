@@ -69,3 +69,30 @@ def test_basis_save_load_roundtrip(lib, ctx, tmp_path):
     x1, s1 = lib.solve_batch(ctx, prob, basis, theta)
     x2, s2 = lib.solve_batch(ctx, prob, b2, theta)
     assert np.array_equal(s1.iters, s2.iters)
+
+
+@pytest.mark.parametrize("coarse,fine,blocks", [((15, 15), (31, 31), (2, 2)),
+                                                ((7, 7, 7), (15, 15, 15), (2, 2, 2))])
+def test_multi_fidelity_matches_oracle(lib, ctx, coarse, fine, blocks):
+    """Multi-fidelity build (Sec. 4.2): greedy on the coarse grid, snapshots of its picks
+    on the fine grid; the fine basis matches the oracle's column by column and the
+    parameters that were given twice are skipped as degenerate."""
+    opc, opf = BlockDiffusion(coarse, blocks), BlockDiffusion(fine, blocks)
+    mus = log_uniform_mu(83, 30, opc.Q, 0.1, 10.0)
+    n_max = 5
+    g_ref, f_ref = og.multi_fidelity(opc, opf, mus, n_max, snapshot_rtol=1e-12)
+    pc = lib.Problem(ctx, coarse, blocks)
+    _, rep = lib.offline_build(ctx, pc, mus, n_max=n_max, indicator="residual",
+                               snapshot_rtol=1e-12)
+    assert rep["picks"] == g_ref.picks
+    pf = lib.Problem(ctx, fine, blocks)
+    sel = mus[rep["picks"]]
+    sel = np.vstack([sel[:2], sel[1:2], sel[2:]])     # one parameter repeated
+    fb, frep = lib.basis_from_parameters(ctx, pf, sel, snapshot_rtol=1e-12)
+    assert frep["n_built"] == n_max and frep["picks"] == [0, 1, 3, 4, 5]
+    W, AN, fN = fb.info()
+    assert np.abs(W @ W.T - np.eye(n_max)).max() <= 1e-13
+    ref_sel = og.basis_from_parameters(opf, [mus[i] for i in g_ref.picks], snapshot_rtol=1e-12)
+    for j in range(n_max):
+        assert np.linalg.norm(W[j] - ref_sel.W[:, j]) <= 1e-7
+    assert np.abs(AN - ref_sel.AN_q).max() <= 1e-7 * np.abs(ref_sel.AN_q).max()

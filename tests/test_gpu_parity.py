@@ -187,6 +187,101 @@ def test_rbcg_converged(lib, ctx, dims, blocks, n, graph):
             assert _rel(x[b], ref.x) <= 1e-9
 
 
+# 3D grids for the z-marching passes: one tile; several slabs; two column tiles
+# (nx > 128); several row tiles with halo rows
+ZGRIDS = [((7, 9, 5), (2, 2, 3)), ((31, 31, 31), (2, 2, 2)), ((129, 5, 9), (2, 2, 2)),
+          ((63, 63, 63), (2, 2, 2))]
+
+
+@pytest.mark.parametrize("dims,blocks", ZGRIDS)
+@pytest.mark.parametrize("B", [1, 5])
+def test_zmarch_fixed_iterations(lib, ctx, dims, blocks, B):
+    """Passes A and B marching along z against the oracle's iterates (1e-10) and against
+    the chunked passes (summation order of the dots only: 1e-12)."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 4, seed=60)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(61, B, op.Q, 0.1, 10.0)
+    k = 7
+    xz, sz = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="zmarch")
+    xc, sc = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="chunked")
+    xz, xc = xz.cpu().numpy(), xc.cpu().numpy()
+    for b in range(B):
+        ref = orb.solve_rbcg(op, theta[b], W, AN, fixed_iters=k)
+        assert sz.iters[b] == k
+        assert _rel(xz[b], ref.x) <= 1e-10, (b, _rel(xz[b], ref.x))
+        assert _rel(xz[b], xc[b]) <= 1e-12, (b, _rel(xz[b], xc[b]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zmarch_converged(lib, ctx, prec):
+    """Converged solves with the z-marching passes: queries retire at different
+    iterations (masked lanes in a block), FP64 and FP32 preconditioners."""
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 6, seed=30)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(62, 9, op.Q, 0.01, 100.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, prec=prec, flexible=True, stencil="zmarch")
+    x = x.cpu().numpy()
+    assert len(set(st.iters.tolist())) > 1
+    h = 1.0 / (dims[0] + 1)
+    for b in range(len(theta)):
+        ref = orb.solve_rbcg(op, theta[b], W, AN, flexible=True)
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        if prec == "fp64":
+            assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
+        kappa = (theta[b].max() * 12.0 / h**2) / (
+            theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
+        assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
+
+
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3)),
+                                         ((31, 31, 31), (2, 2, 2))])
+def test_adaptive_basis_size_fixed_iterations(lib, ctx, dims, blocks):
+    """Adaptive basis size (Sec. 4.1): iterates and the size reached after k steps
+    match the oracle (random basis, so the size grows at most steps)."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 8, seed=70)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(71, 3, op.Q, 0.1, 10.0)
+    start = np.array([1, 2, 5], dtype=np.int32)
+    k = 6
+    x, st = lib.solve_batch(ctx, prob, basis, theta, n_use=start, fixed_iters=k, flexible=True,
+                            adapt_gamma=10.0)
+    x = x.cpu().numpy()
+    for b in range(3):
+        ref = orb.solve_rbcg_adaptive(op, theta[b], W, 10.0, int(start[b]), AN, fixed_iters=k,
+                                      flexible=True)
+        assert st.n_used[b] == ref.n_history[-1], (b, st.n_used[b], ref.n_history)
+        assert _rel(x[b], ref.x) <= 1e-10, (b, _rel(x[b], ref.x))
+
+
+def test_adaptive_basis_size_converged(lib, ctx):
+    """Converged adaptive solves against the oracle: same final size (within one, the
+    growth test is a threshold on rounded norms), iterations within two, solutions
+    within 2 kappa 1e-10; gamma = 0 keeps the start size."""
+    dims, blocks = (31, 31), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 10, seed=72)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(73, 5, op.Q, 0.1, 10.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, flexible=True, adapt_gamma=10.0)
+    x = x.cpu().numpy()
+    for b in range(5):
+        ref = orb.solve_rbcg_adaptive(op, theta[b], W, 10.0, 1, AN, flexible=True)
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        assert abs(st.n_used[b] - ref.n_history[-1]) <= 1, (st.n_used[b], ref.n_history[-1])
+        assert abs(st.iters[b] - ref.iters) <= 2, (st.iters[b], ref.iters)
+        kappa = _cond(op.assemble(theta[b]))
+        assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
+    _, s0 = lib.solve_batch(ctx, prob, basis, theta, n_use=np.full(5, 3, np.int32),
+                            flexible=True, adapt_gamma=0.0)
+    assert (s0.n_used == 3).all()
+
+
 def test_graph_replay_is_bitwise_equal_to_eager(lib, ctx):
     dims, blocks = (63, 63), (2, 2)
     op = BlockDiffusion(dims, blocks)
