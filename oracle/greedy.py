@@ -48,15 +48,27 @@ def reduced_coefficients(AN_q, fN, theta):
     return chol_solve(cholesky(AN), fN)
 
 
-def indicator_values(op, W, AN_q, fN, thetas, kind):
+def _rhs_terms(op):
+    """The right-hand-side terms f_r (R x N) of eq. 12."""
+    return op.f_r if hasattr(op, "f_r") else op.rhs()[None, :]
+
+
+def indicator_values(op, W, AN_q, fN, thetas, kind, phis=None):
+    """fN: R x n reduced right-hand-side terms (or a vector when R = 1); f_N(mu) =
+    sum_r Phi_r(mu) f_{N,r}."""
+    fN = np.atleast_2d(fN)
     f = op.rhs()
     nf = np.linalg.norm(f)
     out = np.empty(len(thetas))
     for i, th in enumerate(thetas):
-        a = reduced_coefficients(AN_q, fN, th)
+        fn = fN[0] if phis is None else phis[i] @ fN
+        a = reduced_coefficients(AN_q, fn, th)
         if kind == "l1":
             out[i] = np.abs(a).sum()
         elif kind == "residual":
+            if phis is not None:
+                f = op.rhs(phis[i])
+                nf = np.linalg.norm(f)
             out[i] = np.linalg.norm(f - op.assemble(th) @ (W @ a)) / nf
         else:
             raise ValueError(kind)
@@ -81,17 +93,18 @@ def _append(op, W, AN_q, fN, w):
         col = W.T @ (Aq @ w)
         newAN[q, :, n] = col
         newAN[q, n, :] = col
-    return W, newAN, np.append(fN, w @ op.rhs())
+    fr = _rhs_terms(op)
+    return W, newAN, np.column_stack([np.atleast_2d(fN).reshape(len(fr), n), fr @ w])
 
 
 def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
                     snapshot_rtol=1e-10, snapshot_maxit=5000, keep_indicators=False,
-                    snapshot_flexible=True):
+                    snapshot_flexible=True, phis=None):
+    """phis (M x R, optional): Phi_r of every training parameter (eq. 12)."""
     N = op.N
-    f = op.rhs()
     W = np.zeros((N, 0))
     AN_q = np.zeros((op.Q, 0, 0))
-    fN = np.zeros(0)
+    fN = np.zeros((len(_rhs_terms(op)), 0))
     picks = []
     excluded = set()
     maxind = []
@@ -102,7 +115,8 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
     while W.shape[1] < n_max:
         res = solve_rbcg(op, thetas[mu_next], W, AN_q if W.shape[1] else None,
                          rtol=snapshot_rtol, maxit=snapshot_maxit,
-                         flexible=snapshot_flexible)                     # step 3
+                         flexible=snapshot_flexible,
+                         phi=None if phis is None else phis[mu_next])   # step 3
         try:
             w = mgs(W, res.x)                                            # step 4
         except Degenerate:
@@ -115,7 +129,7 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
         excluded.add(mu_next)
         snap_iters.append(res.iters)
         W, AN_q, fN = _append(op, W, AN_q, fN, w)
-        ind = indicator_values(op, W, AN_q, fN, thetas, indicator)      # step 5
+        ind = indicator_values(op, W, AN_q, fN, thetas, indicator, phis)  # step 5
         if keep_indicators:
             all_ind.append(ind.copy())
         if len(excluded) >= len(thetas):
@@ -123,11 +137,12 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
             break
         mu_next = masked_argmax(ind, excluded)                           # step 6
         maxind.append(float(ind[mu_next]))
-    return GreedyResult(W, picks, maxind, AN_q, fN, snap_iters, all_ind)
+    return GreedyResult(W, picks, maxind, AN_q, fN[0] if len(fN) == 1 else fN, snap_iters,
+                        all_ind)
 
 
 def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
-                          snapshot_flexible=True):
+                          snapshot_flexible=True, phis=None):
     """Steps 3-4 of Alg. 4 for a given sequence of parameters: each snapshot is solved
     by RBCG with the basis built so far and orthonormalised into it (degenerate
     snapshots are skipped).  With the parameters picked by a greedy on a coarse grid
@@ -135,11 +150,12 @@ def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
     the indices into thetas that entered the basis."""
     W = np.zeros((op.N, 0))
     AN_q = np.zeros((op.Q, 0, 0))
-    fN = np.zeros(0)
+    fN = np.zeros((len(_rhs_terms(op)), 0))
     picks, snap_iters = [], []
     for i, th in enumerate(thetas):
         res = solve_rbcg(op, th, W, AN_q if W.shape[1] else None, rtol=snapshot_rtol,
-                         maxit=snapshot_maxit, flexible=snapshot_flexible)  # step 3
+                         maxit=snapshot_maxit, flexible=snapshot_flexible,
+                         phi=None if phis is None else phis[i])           # step 3
         try:
             w = mgs(W, res.x)                                               # step 4
         except Degenerate:
@@ -147,7 +163,7 @@ def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
         picks.append(i)
         snap_iters.append(res.iters)
         W, AN_q, fN = _append(op, W, AN_q, fN, w)
-    return GreedyResult(W, picks, [], AN_q, fN, snap_iters)
+    return GreedyResult(W, picks, [], AN_q, fN[0] if len(fN) == 1 else fN, snap_iters)
 
 
 def multi_fidelity(op_coarse, op_fine, thetas, n_max, indicator="residual", **kw):

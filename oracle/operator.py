@@ -121,3 +121,52 @@ class BlockDiffusion:
         """Red-black colour (i + j + k) mod 2 of every node, 0-based indices, lex order."""
         idx = np.indices(self.dims[::-1]).reshape(self.dim, -1)
         return (idx.sum(axis=0) % 2).astype(np.int8)
+
+
+class SparseAffine:
+    """A general affine sparse problem (eq. 12, Sec. 2.3) given by its terms: the CSR
+    arrays of the union pattern (rowptr [N+1], col [nnz]) and the values of every term
+    on it (vals [Q][nnz]); right-hand-side terms f_r (R x N, default one term f = 1).
+
+    Gauss-Seidel colouring (the smoother reading for sparse input): greedy first fit in
+    natural row order on the symmetrised pattern without the diagonal, i.e. unknown i
+    gets the smallest colour not taken by a neighbour j < i.  On the 5/7-point grids this
+    is exactly the red-black colouring.
+    """
+
+    def __init__(self, rowptr, col, vals, f_r=None):
+        rowptr = np.asarray(rowptr, dtype=np.int64)
+        col = np.asarray(col, dtype=np.int64)
+        vals = np.atleast_2d(np.asarray(vals, dtype=np.float64))
+        self.N = len(rowptr) - 1
+        self.Q = vals.shape[0]
+        self.A_q = [sp.csr_matrix((vals[q], col, rowptr), shape=(self.N, self.N))
+                    for q in range(self.Q)]
+        self.f_r = (np.ones((1, self.N)) if f_r is None
+                    else np.atleast_2d(np.asarray(f_r, dtype=np.float64)))
+        self.R = self.f_r.shape[0]
+        self._pattern = sp.csr_matrix((np.ones(len(col)), col, rowptr), shape=(self.N, self.N))
+
+    def assemble(self, theta):
+        theta = np.asarray(theta, dtype=np.float64)
+        A = theta[0] * self.A_q[0]
+        for q in range(1, self.Q):
+            A = A + theta[q] * self.A_q[q]
+        return A.tocsr()
+
+    def rhs(self, phi=None):
+        """f = sum_r phi_r f_r (phi = 1 for every term if not given)."""
+        phi = np.ones(self.R) if phi is None else np.asarray(phi, dtype=np.float64)
+        return phi @ self.f_r
+
+    def colors(self):
+        S = (self._pattern + self._pattern.T).tocsr()
+        color = np.full(self.N, -1, dtype=np.int64)
+        for i in range(self.N):
+            nb = S.indices[S.indptr[i]:S.indptr[i + 1]]
+            used = {int(color[j]) for j in nb if j < i}
+            c = 0
+            while c in used:
+                c += 1
+            color[i] = c
+        return color

@@ -252,9 +252,15 @@ def make_preconditioner(op, theta, W, AN_q=None, smoother_kind=RBGS):
     return A, RBPreconditioner(A, W, L, S)
 
 
-def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, **kw):
+def _rhs(op, phi):
+    """f(mu) = sum_r Phi_r f_r (eq. 12); the problem's single right-hand side if phi is
+    not given."""
+    return op.rhs() if phi is None else op.rhs(phi)
+
+
+def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, phi=None, **kw):
     A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
-    return rbcg(A, op.rhs(), M, **kw)
+    return rbcg(A, _rhs(op, phi), M, **kw)
 
 
 class NestedRBPreconditioner:
@@ -274,7 +280,8 @@ class NestedRBPreconditioner:
         return self.cache[n](r)
 
 
-def solve_rbcg_adaptive(op, theta, W, gamma, n0, AN_q=None, smoother_kind=RBGS, **kw):
+def solve_rbcg_adaptive(op, theta, W, gamma, n0, AN_q=None, smoother_kind=RBGS, phi=None,
+                        **kw):
     """RBCG with the adaptive basis size (Sec. 4.1): starts with the leading n0 vectors
     of W and grows by one whenever the residual falls by less than gamma per step."""
     A = op.assemble(theta)
@@ -282,16 +289,16 @@ def solve_rbcg_adaptive(op, theta, W, gamma, n0, AN_q=None, smoother_kind=RBGS, 
     if AN_q is None:
         AN_q, _ = reduced_operators(op.A_q, [op.rhs()], W)
     M = NestedRBPreconditioner(A, W, assemble_reduced(AN_q, theta), S)
-    return rbcg(A, op.rhs(), M, adapt=(gamma, n0, W.shape[1]), **kw)
+    return rbcg(A, _rhs(op, phi), M, adapt=(gamma, n0, W.shape[1]), **kw)
 
 
-def solve_cg(op, theta, **kw):
+def solve_cg(op, theta, phi=None, **kw):
     """Plain CG (Hestenes-Stiefel): the identity preconditioner."""
     A = op.assemble(theta)
-    return rbcg(A, op.rhs(), lambda r: r.copy(), **kw)
+    return rbcg(A, _rhs(op, phi), lambda r: r.copy(), **kw)
 
 
-def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS):
+def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS, phi=None):
     A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
-    x, k, hist = rbi(A, op.rhs(), W, M.L, M.S, m, rtol)
+    x, k, hist = rbi(A, _rhs(op, phi), W, M.L, M.S, m, rtol)
     return x, k, hist
