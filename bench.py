@@ -81,6 +81,8 @@ def main():
                     help="also compare the surrogate-ranked greedy with the plain greedy")
     ap.add_argument("--basis", default="",
                     help="load the basis from this file if it exists, else build and save it")
+    ap.add_argument("--fem", type=int, default=0,
+                    help="also run the paper's two P1 cases (Table 1) through the sparse path")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also fill and sum a buffer of this many MiB (profiler calibration)")
     args = ap.parse_args()
@@ -192,7 +194,8 @@ def main():
 
     extra = {}
     for flag, name, fn in ((args.uneven, "uneven_batch", lambda: uneven_leg(rb, torch)),
-                           (args.learned, "learned_greedy", lambda: learned_leg(rb))):
+                           (args.learned, "learned_greedy", lambda: learned_leg(rb)),
+                           (args.fem, "fem_cases", lambda: fem_leg(rb, torch))):
         if flag:
             try:
                 extra[name] = fn()
@@ -248,8 +251,9 @@ def uneven_leg(rb, torch):
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda:0") for g, _, _ in qs]
     queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
-    # small bases on the 1023^2 grid need thousands of iterations
-    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True, maxit=50000)
+    # small bases on the 1023^2 grid need up to ~7500 iterations; a query whose FP64
+    # residual floor lies above its tolerance stops at maxit
+    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000)
     rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -306,6 +310,52 @@ def learned_leg(rb):
         log(f"learned greedy [{name}]: {rep['seconds']:.2f}s, {rep['true_evals']} true "
             f"evaluations, held-out max eta {worst:.3e}")
     return res
+
+
+def fem_leg(rb, torch, n=63):
+    """The paper's P1 cases on the unit cube (n^3 interior nodes): 100 random parameters
+    solved by RBCG with greedy bases of the sizes of its Sec. 5.1 (1 and 5 for case 1,
+    2 and 20 for case 2) and by plain CG, all to relative residual 1e-10 in one batch."""
+    from workloads import fem
+    ctx = rb.Context(0)
+    out = {}
+    for case, sizes in ((1, (1, 5)), (2, (2, 20))):
+        s = fem.build(case, n, 3)
+        rp, c, v = fem.csr_arrays(s)
+        prob = rb.Problem.from_csr(ctx, rp, c, v)
+        prob.set_rhs(s.b_r)
+        train = s.draw_mu(1000 + case, 256)
+        t0 = time.time()
+        basis, rep = rb.offline_build(ctx, prob, s.theta(train), phi=s.phi(train),
+                                      n_max=max(sizes), indicator="l1")
+        tg = time.time() - t0
+        test = s.draw_mu(2000 + case, 100)
+        th, ph = s.theta(test), s.phi(test)
+        res = {"N": s.N, "greedy_seconds": round(tg, 2)}
+        for nb in sizes:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, st = rb.solve_batch(ctx, prob, basis, th, phi=ph, n_use=np.full(100, nb, np.int32),
+                                   flexible=True, maxit=20000)
+            el = time.perf_counter() - t
+            ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+            res[f"rbcg_n{nb}"] = {"iters_min": int(st.iters.min()), "iters_max": int(st.iters.max()),
+                                  "iters_mean": round(float(st.iters.mean()), 1),
+                                  "converged": ok, "mu_solves_per_s": round(ok / el, 1)}
+            log(f"fem case {case} N={s.N} RBCG n={nb}: iters {st.iters.min()}..{st.iters.max()} "
+                f"(mean {st.iters.mean():.1f}), {ok}/100 converged, {ok / el:.1f} mu-solves/s")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = rb.solve_batch(ctx, prob, None, th, phi=ph, solver="cg", maxit=20000)
+        el = time.perf_counter() - t
+        ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+        res["cg"] = {"iters_min": int(st.iters.min()), "iters_max": int(st.iters.max()),
+                     "iters_mean": round(float(st.iters.mean()), 1), "converged": ok,
+                     "mu_solves_per_s": round(ok / el, 1)}
+        log(f"fem case {case} plain CG: iters {st.iters.min()}..{st.iters.max()}, {ok}/100 "
+            f"converged, {ok / el:.1f} mu-solves/s")
+        out[f"case{case}"] = res
+    return out
 
 
 def held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch):

@@ -102,6 +102,20 @@ typedef struct {
   int blocks[3];
 } rb_stencil_desc;
 rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* desc, rb_problem** out);
+
+/* General sparse affine problem A(theta) = sum_q theta_q A_q (eq. 12, Sec. 2.3) with all Q
+ * terms on one pattern: rowptr [N+1] (int64), col [nnz] (int32, strictly increasing within
+ * a row, every row holding its diagonal), vals [Q][nnz] (term q's values on the pattern,
+ * zeros allowed); host arrays, copied.  The caller guarantees A(theta) SPD for the thetas
+ * it solves with (a symmetric pattern and symmetric terms).  The Gauss-Seidel smoother
+ * colours the unknowns greedily (first fit in natural order on the symmetrised pattern)
+ * and sweeps the colour classes in increasing order; at most 32 classes.  N < 2^30,
+ * nnz < 2^31, Q <= 64.  Default right-hand side R = 1, f = 1.  Errors: RB_EINVAL for
+ * malformed arrays or non-finite values, RB_EUNSUPPORTED beyond the limits. */
+rb_status rb_problem_create_csr(rb_ctx* ctx, int64_t N, int Q, const int64_t* rowptr,
+                                const int32_t* col, const double* vals, rb_problem** out);
+/* Colour class of every unknown (natural order, [N] host) and the number of classes. */
+rb_status rb_problem_colors(const rb_problem* prob, int32_t* color, int* ncolors);
 /* Replace the right-hand-side terms f_r: f is [R][N] host, natural ordering. */
 rb_status rb_problem_set_rhs(rb_problem* prob, int R, const double* f);
 /* Query sizes: any output pointer may be NULL. */
@@ -157,6 +171,14 @@ typedef struct {
                          preconditioner application whenever its residual fell by less
                          than this factor in an iteration; 0: fixed size.  Use with
                          beta_flexible (the preconditioner changes between iterations). */
+  double floor_factor; /* > 0: the true-residual test also accepts ||f - A x|| <= floor_factor
+                          * eps * || |A| |x| || (eps = 2^-52), the rounding level of an FP64
+                          * residual of x; such queries end RB_OK with at_floor = 1.  0: off.
+                          * For problems whose 1e-10 lies below that level (strong kappa
+                          * contrasts on fine grids). */
+  int smooth_sweeps;  /* Gauss-Seidel sweeps per smoother application (RBGS: forward sweeps,
+                         RBGS_SYM: forward + backward pairs); 0 or 1 = one.  Jacobi and
+                         none take one only (RB_EUNSUPPORTED otherwise). */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 
@@ -166,6 +188,7 @@ typedef struct {
   double rel_res_recursive;
   rb_status status;
   int n_used; /* basis vectors used by the last preconditioner application */
+  int at_floor; /* 1: accepted at the rounding level (floor_factor), not at rtol */
 } rb_query_stats;
 
 /* B queries on one problem and basis.  theta [B][Q] host; phi [B][R] host or NULL

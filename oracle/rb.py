@@ -240,10 +240,10 @@ def mgs(W, x, reorth_ratio=0.5, degenerate_tol=1e-12):
     return w / after
 
 
-def make_preconditioner(op, theta, W, AN_q=None, smoother_kind=RBGS):
+def make_preconditioner(op, theta, W, AN_q=None, smoother_kind=RBGS, sweeps=1):
     """Build (A(theta), RBI preconditioner) for one parameter vector."""
     A = op.assemble(theta)
-    S = Smoother(A, op.colors(), smoother_kind)
+    S = Smoother(A, op.colors(), smoother_kind, sweeps=sweeps)
     if W.shape[1] == 0:
         return A, RBPreconditioner(A, W, None, S)
     if AN_q is None:
@@ -258,8 +258,8 @@ def _rhs(op, phi):
     return op.rhs() if phi is None else op.rhs(phi)
 
 
-def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, phi=None, **kw):
-    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
+def solve_rbcg(op, theta, W, AN_q=None, smoother_kind=RBGS, phi=None, sweeps=1, **kw):
+    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind, sweeps)
     return rbcg(A, _rhs(op, phi), M, **kw)
 
 
@@ -298,7 +298,8 @@ def solve_cg(op, theta, phi=None, **kw):
     return rbcg(A, _rhs(op, phi), lambda r: r.copy(), **kw)
 
 
-def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS, phi=None):
-    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind)
+def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS, phi=None,
+              sweeps=1):
+    A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind, sweeps)
     x, k, hist = rbi(A, _rhs(op, phi), W, M.L, M.S, m, rtol)
     return x, k, hist

@@ -26,8 +26,11 @@ class Smoother:
     ordering).  The stencil problems use the red-black colouring (C = 2); general
     sparse problems a greedy colouring."""
 
-    def __init__(self, A, colors, kind=RBGS, omega=2.0 / 3.0):
+    def __init__(self, A, colors, kind=RBGS, omega=2.0 / 3.0, sweeps=1):
+        """sweeps: how many times the sweep (forward, or forward then backward for the
+        symmetric kind) is applied per smoother application."""
         self.kind = kind
+        self.sweeps = int(sweeps)
         self.A = sp.csr_matrix(A)
         self.D = self.A.diagonal()
         colors = np.asarray(colors)
@@ -46,11 +49,13 @@ class Smoother:
         y = np.array(y0, dtype=np.float64, copy=True)
         C = len(self.sets)
         if self.kind == RBGS:
-            for c in range(C):
-                self._sweep(c, b, y)
+            for _ in range(self.sweeps):
+                for c in range(C):
+                    self._sweep(c, b, y)
         elif self.kind == RBGS_SYM:
-            for c in list(range(C)) + list(range(C - 1, -1, -1)):
-                self._sweep(c, b, y)
+            for _ in range(self.sweeps):
+                for c in list(range(C)) + list(range(C - 1, -1, -1)):
+                    self._sweep(c, b, y)
         elif self.kind == JACOBI:
             y = y + self.omega * (b - self.A @ y) / self.D
         elif self.kind == NONE:

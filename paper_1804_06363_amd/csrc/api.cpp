@@ -119,11 +119,6 @@ using namespace rb;
 
 static int64_t align_ld(int64_t N) { return (N + 63) / 64 * 64; }
 
-// Red-black storage position -> lexicographic index.
-static inline int lex_of(const StencilGeom& g, int pos) {
-  return pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
-}
-
 const void* rb_basis::shadow(rb_prec prec) {
   if (prec == RB_PREC_FP64) return W64.p;
   DevBuf& dst = prec == RB_PREC_FP32 ? W32 : W16;
@@ -250,6 +245,10 @@ rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* d, rb_pr
     g.Q = Q;
     g.N = (int)N;
     g.NR = (int)((N + 1) / 2);
+    g.C = 2;  // red-black
+    g.coff[0] = 0;
+    g.coff[1] = g.NR;
+    g.coff[2] = g.N;
     g.nxy = n[0] * n[1];
     g.div_nx = rbk::make_fastdiv((uint32_t)n[0]);
     g.div_nxy = rbk::make_fastdiv((uint32_t)(n[0] * n[1]));
@@ -289,6 +288,165 @@ rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* d, rb_pr
     launch_fill<double>(p->f.as<double>(), 0, N, 1, 1.0, ctx->stream);
     RB_HIP(hipStreamSynchronize(ctx->stream));
     *out = p.release();
+  });
+}
+
+rb_status rb_problem_create_csr(rb_ctx* ctx, int64_t N, int Q, const int64_t* rowptr,
+                                const int32_t* col, const double* vals, rb_problem** out) {
+  return guarded([&] {
+    RB_REQUIRE(ctx && rowptr && col && vals && out, RB_EINVAL, "null argument");
+    RB_REQUIRE(N >= 1 && Q >= 1, RB_EINVAL, "N and Q must be positive");
+    RB_REQUIRE(N < (1ll << 30), RB_EUNSUPPORTED, "N >= 2^30");
+    RB_REQUIRE(Q <= 64, RB_EUNSUPPORTED, "at most 64 affine terms");
+    RB_REQUIRE(rowptr[0] == 0, RB_EINVAL, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < N; ++i)
+      RB_REQUIRE(rowptr[i + 1] >= rowptr[i], RB_EINVAL, "rowptr must be non-decreasing");
+    const int64_t nnz = rowptr[N];
+    RB_REQUIRE(nnz < (1ll << 31), RB_EUNSUPPORTED, "nnz >= 2^31");
+    std::vector<int64_t> dpos(N, -1);
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        RB_REQUIRE(col[e] >= 0 && col[e] < N, RB_EINVAL, "column index out of range");
+        RB_REQUIRE(e == rowptr[i] || col[e] > col[e - 1], RB_EINVAL,
+                   "columns must be strictly increasing within a row");
+        if (col[e] == i) dpos[i] = e;
+      }
+    for (int64_t i = 0; i < N; ++i)
+      RB_REQUIRE(dpos[i] >= 0, RB_EINVAL, "every row must hold its diagonal");
+    check_finite(vals, (size_t)Q * nnz, "vals");
+    const int n = (int)N;
+    // symmetrised adjacency without the diagonal
+    std::vector<int64_t> deg(n + 1, 0);
+    for (int i = 0; i < n; ++i)
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        if (col[e] != i) {
+          deg[i + 1]++;
+          deg[col[e] + 1]++;
+        }
+    for (int i = 0; i < n; ++i) deg[i + 1] += deg[i];
+    std::vector<int> adj(deg[n]);
+    {
+      std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+      for (int i = 0; i < n; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+          if (col[e] != i) {
+            adj[fill[i]++] = col[e];
+            adj[fill[col[e]]++] = i;
+          }
+    }
+    // first-fit colouring in natural order
+    std::vector<int> color(n, -1), stamp(kMaxColors + 1, -1);
+    int C = 0;
+    for (int i = 0; i < n; ++i) {
+      for (int64_t e = deg[i]; e < deg[i + 1]; ++e) {
+        const int j = adj[e];
+        if (j < i && color[j] <= kMaxColors) stamp[color[j]] = i;
+      }
+      int c = 0;
+      while (c <= kMaxColors && stamp[c] == i) ++c;
+      RB_REQUIRE(c < kMaxColors, RB_EUNSUPPORTED, "the colouring needs more than 32 classes");
+      color[i] = c;
+      C = std::max(C, c + 1);
+    }
+    DeviceGuard dg(ctx->device);
+    auto p = std::make_unique<rb_problem>();
+    p->ctx = ctx;
+    p->N = N;
+    p->ld = align_ld(N);
+    StencilGeom& g = p->g;
+    g.csr = 1;
+    g.dim = 0;
+    g.Q = Q;
+    g.N = n;
+    g.C = C;
+    // storage order: colour-major, natural order within a class
+    std::vector<int> cnt(C + 1, 0);
+    for (int i = 0; i < n; ++i) cnt[color[i] + 1]++;
+    for (int c = 0; c < C; ++c) cnt[c + 1] += cnt[c];
+    for (int c = 0; c <= C; ++c) g.coff[c] = cnt[c];
+    g.NR = g.coff[1];
+    p->perm_h.resize(n);
+    std::vector<int> inv(n);
+    {
+      std::vector<int> next(cnt.begin(), cnt.end() - 1);
+      for (int i = 0; i < n; ++i) {
+        const int pos = next[color[i]]++;
+        p->perm_h[pos] = i;
+        inv[i] = pos;
+      }
+    }
+    p->color_h = color;
+    // sliced ELL: slices of 64 storage rows, width = longest off-diagonal row of the slice
+    const int ns = (n + 63) / 64;
+    std::vector<int64_t> sptr(ns + 1, 0);
+    for (int s = 0; s < ns; ++s) {
+      int w = 0;
+      for (int pos = 64 * s; pos < std::min(n, 64 * s + 64); ++pos) {
+        const int i = p->perm_h[pos];
+        w = std::max(w, (int)(rowptr[i + 1] - rowptr[i] - 1));
+      }
+      sptr[s + 1] = sptr[s] + 64 * (int64_t)w;
+    }
+    const int64_t total = std::max<int64_t>(sptr[ns], 64);
+    std::vector<int> scol(total);
+    std::vector<double> sval((size_t)Q * total, 0.0), dg_((size_t)Q * n);
+    for (int s = 0; s < ns; ++s) {
+      const int w = (int)((sptr[s + 1] - sptr[s]) / 64);
+      for (int l = 0; l < 64; ++l) {
+        const int pos = 64 * s + l;
+        const int i = pos < n ? p->perm_h[pos] : 0;
+        int k = 0;
+        if (pos < n)
+          for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (col[e] == i) {
+              for (int q = 0; q < Q; ++q) dg_[(size_t)q * n + pos] = vals[(size_t)q * nnz + e];
+              continue;
+            }
+            const int64_t at = sptr[s] + 64 * (int64_t)k + l;
+            scol[at] = inv[col[e]];
+            for (int q = 0; q < Q; ++q) sval[(size_t)q * total + at] = vals[(size_t)q * nnz + e];
+            ++k;
+          }
+        for (; k < w; ++k) scol[sptr[s] + 64 * (int64_t)k + l] = pos < n ? pos : 0;
+      }
+    }
+    p->sptr.alloc(sizeof(int64_t) * (ns + 1));
+    p->scol.alloc(sizeof(int) * total);
+    p->sval.alloc(sizeof(double) * (size_t)Q * total);
+    p->diag.alloc(sizeof(double) * (size_t)Q * n);
+    p->perm.alloc(sizeof(int) * n);
+    RB_HIP(hipMemcpy(p->sptr.p, sptr.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(p->scol.p, scol.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(p->sval.p, sval.data(), sizeof(double) * (size_t)Q * total,
+                     hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(p->diag.p, dg_.data(), sizeof(double) * (size_t)Q * n,
+                     hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(p->perm.p, p->perm_h.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    g.sptr = p->sptr.as<int64_t>();
+    g.scol = p->scol.as<int>();
+    g.sval = p->sval.as<double>();
+    g.sval_ld = total;
+    g.diag = p->diag.as<double>();
+    g.ct_size = (Q + 7) / 8 * 8;
+    p->R = 1;
+    p->f_host.assign((size_t)N, 1.0);
+    p->f.alloc(sizeof(double) * p->ld);
+    launch_fill<double>(p->f.as<double>(), 0, N, 1, 1.0, ctx->stream);
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    *out = p.release();
+  });
+}
+
+rb_status rb_problem_colors(const rb_problem* p, int32_t* color, int* ncolors) {
+  return guarded([&] {
+    RB_REQUIRE(p, RB_EINVAL, "null problem");
+    if (ncolors) *ncolors = p->g.C;
+    if (color)
+      for (int pos = 0; pos < p->g.N; ++pos) {  // class of the storage position's unknown
+        int c = 0;
+        while (pos >= p->g.coff[c + 1]) ++c;
+        color[p->nat_index(pos)] = c;
+      }
   });
 }
 
@@ -528,6 +686,12 @@ static void check_opts(const rb_solve_opts* o) {
              "bad adapt_gamma");
   RB_REQUIRE(o->adapt_gamma == 0.0 || o->solver == RB_SOLVER_RBCG, RB_EINVAL,
              "the adaptive basis size applies to RBCG only");
+  RB_REQUIRE(o->smooth_sweeps >= 0 && o->smooth_sweeps <= 64, RB_EINVAL, "bad smooth_sweeps");
+  RB_REQUIRE(std::isfinite(o->floor_factor) && o->floor_factor >= 0.0, RB_EINVAL,
+             "bad floor_factor");
+  RB_REQUIRE(o->smooth_sweeps <= 1 || o->smoother == RB_SMOOTH_RBGS ||
+                 o->smoother == RB_SMOOTH_RBGS_SYM,
+             RB_EUNSUPPORTED, "several sweeps need a Gauss-Seidel smoother");
 }
 
 rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,

@@ -846,18 +846,24 @@ __global__ __launch_bounds__(256) void k_fin_rr(const double* __restrict__ part,
 
 // true residual (eq. relerr): retire on success, else restart with the replaced residual
 __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ part, int stride,
-                                                  int cnt, QState q, double rtol, int maxit) {
+                                                  int cnt, QState q, double rtol, int maxit,
+                                                  const double* __restrict__ part2,
+                                                  double floor_factor) {
   __shared__ double sh[4];
   const int b = blockIdx.x;
   if (!q.active[b] || !q.flag[b]) return;
   const double rr = sum_parts(part + (size_t)b * stride, cnt, sh);
+  // rounding level of the FP64 residual of x: eps || |A| |x| || (relative to ||f||)
+  const double aa = part2 ? sum_parts(part2 + (size_t)b * stride, cnt, sh) : 0.0;
   if (threadIdx.x == 0) {
     const double rel = sqrt(rr / q.fnorm2[b]);
+    const double lvl = floor_factor * 0x1p-52 * sqrt(aa / q.fnorm2[b]);
     q.rel_true[b] = rel;
     q.flag[b] = 0;
-    if (rel <= rtol) {
+    if (rel <= rtol || (part2 && rel <= lvl)) {
       q.active[b] = 0;
       q.status[b] = RB_OK;
+      if (q.at_floor && rel > rtol) q.at_floor[b] = 1;
     } else if (q.iters[b] >= maxit) {
       q.active[b] = 0;
       q.status[b] = RB_ENOCONV;
@@ -869,30 +875,26 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
 }
 
 // steps 9-10: rho_new = y^T r (red + black partials); beta (literal or flexible)
-__global__ __launch_bounds__(256) void k_fin_beta(const double* __restrict__ pr, int cr,
-                                                  const double* __restrict__ pb, int cb,
-                                                  const double* __restrict__ fr,
-                                                  const double* __restrict__ fb, QState q,
-                                                  int flexible) {
+__global__ __launch_bounds__(256) void k_fin_beta(const double* __restrict__ pr,
+                                                  const double* __restrict__ fr, Segs sg,
+                                                  QState q, int flexible) {
   __shared__ double sh[4];
   const int b = blockIdx.x;
   if (!q.active[b]) return;
-  const double s0 = sum_parts(pr + (size_t)b * cr, cr, sh);
-  const double s1 = pb ? sum_parts(pb + (size_t)b * cb, cb, sh) : 0.0;
-  double x0 = 0.0, x1 = 0.0;
-  if (flexible && fr) {
-    x0 = sum_parts(fr + (size_t)b * cr, cr, sh);
-    x1 = fb ? sum_parts(fb + (size_t)b * cb, cb, sh) : 0.0;
+  // one segment per colour sweep (or one for a whole-vector smoother), in sweep order
+  double rho_new = 0.0, x = 0.0;
+  for (int c = 0; c < sg.n; ++c) {
+    rho_new += sum_parts(pr + sg.off[c] + (size_t)b * sg.cnt[c], sg.cnt[c], sh);
+    if (flexible && fr) x += sum_parts(fr + sg.off[c] + (size_t)b * sg.cnt[c], sg.cnt[c], sh);
   }
   if (threadIdx.x == 0) {
-    const double rho_new = s0 + s1;
     const double rho_old = q.rho[b];
     double beta;
     if (q.restart[b]) {
       beta = 0.0;
       q.restart[b] = 0;
     } else if (flexible) {
-      beta = (rho_new - (x0 + x1)) / rho_old;
+      beta = (rho_new - x) / rho_old;
     } else {
       beta = rho_new / rho_old;
     }
@@ -922,13 +924,13 @@ void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int
                      fixed ? 1 : 0);
 }
 void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
-                     int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_true, dim3(B), dim3(256), 0, s, part, stride, cnt, q, rtol, maxit);
+                     int maxit, hipStream_t s, const double* part2, double floor_factor) {
+  hipLaunchKernelGGL(k_fin_true, dim3(B), dim3(256), 0, s, part, stride, cnt, q, rtol, maxit,
+                     part2, floor_factor);
 }
-void launch_fin_beta(const double* pr, int cr, const double* pb, int cb, const double* fr,
-                     const double* fb, const QState& q, int B, bool flexible, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_beta, dim3(B), dim3(256), 0, s, pr, cr, pb, cb, fr, fb, q,
-                     flexible ? 1 : 0);
+void launch_fin_beta(const double* pr, const double* fr, const Segs& sg, const QState& q, int B,
+                     bool flexible, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(B), dim3(256), 0, s, pr, fr, sg, q, flexible ? 1 : 0);
 }
 void launch_fin_sum(const double* part, int stride, int cnt, double* out, const int* active,
                     int B, hipStream_t s) {

@@ -55,6 +55,8 @@ struct DevBuf {
 // the red node with lexicographic index L = 2g, position g >= NR the black node
 // L = 2(g - NR) + 1.  With n_x (and n_y in 3D) odd, the parity of L equals the
 // colour (i + j + k) mod 2.
+constexpr int kMaxColors = 32;  // colour classes of the Gauss-Seidel smoother
+
 struct StencilGeom {
   int dim;
   int nx, ny, nz;
@@ -71,6 +73,21 @@ struct StencilGeom {
   int ct_s1[3];   // size of the first tangential state dimension (or 1)
   int ct_s2[3];   // size of the second tangential state dimension (or 1)
   int ct_size;    // doubles per query (padded)
+  // colour classes of the Gauss-Seidel smoother in storage order: class c holds the
+  // positions [coff[c], coff[c+1]); the grids use red-black (C = 2, coff[1] = NR)
+  int C;
+  int coff[kMaxColors + 1];
+  // general sparse problems (csr != 0): terms on a shared pattern in sliced ELL form,
+  // rows in storage (colour-major) order.  Slice s holds rows [64 s, 64 s + 64);
+  // entry k of its lane l is at sptr[s] + 64 k + l (column in scol, storage index; the
+  // value of term q in sval[q * sval_ld + ...]); the diagonal is kept apart in diag[q * N
+  // + row] and padding entries point at their own row with value 0.
+  int csr;
+  const int64_t* sptr;
+  const int* scol;
+  const double* sval;
+  int64_t sval_ld;
+  const double* diag;
 };
 
 namespace rb {
@@ -124,7 +141,7 @@ TuneConfig stencil_tiles();
 
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
-  WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PR0, WS_PR1, WS_PB0, WS_PB1, WS_Q, WS_COUNT
+  WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_COUNT
 };
 }  // namespace rb
 
@@ -188,7 +205,15 @@ struct rb_problem {
   int64_t ld = 0;  // padded per-vector stride (elements)
   int R = 1;
   rb::DevBuf tabs;       // per-axis node tables
-  rb::DevBuf perm;       // int32 [N]: storage position -> lexicographic index
+  rb::DevBuf perm;       // int32 [N]: storage position -> natural index (sparse problems)
+  std::vector<int> perm_h;  // the same on the host (sparse problems)
+  std::vector<int> color_h; // colour class of every unknown, natural order (sparse problems)
+  rb::DevBuf sptr, scol, sval, diag;  // sliced ELL terms (sparse problems)
+  // natural index of storage position pos
+  int nat_index(int pos) const {
+    if (g.csr) return perm_h[pos];
+    return pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
+  }
   rb::DevBuf f;          // double [R][ld], storage (red-black) order
   std::vector<double> f_host;  // [R][N] natural order
 };

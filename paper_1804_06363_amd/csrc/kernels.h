@@ -30,6 +30,14 @@ struct QState {
   double* rr_in = nullptr;
   double gamma2 = 0.0;
   int nmax = 0;
+  int* at_floor = nullptr;  // accepted at the rounding level (floor test on)
+};
+
+// Segments of a partial-sum buffer written by successive colour sweeps.
+struct Segs {
+  int n = 0;
+  int cnt[kMaxColors];
+  int64_t off[kMaxColors];
 };
 
 struct ProjPlan {
@@ -53,9 +61,10 @@ inline int padded_queries(int B) { return (B + 255) / 256 * 256; }
 int stencil_chunks(int count);
 // partial-sum chunks of an all-node stencil pass (apply, pass A/B, Jacobi)
 int stencil_chunks_all(int N);
+// mode 1 with part2: partial sums of (|A| |u|)^2 as well (rounding level of the residual)
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, hipStream_t s);
+                  const int* flag, double* part, hipStream_t s, double* part2 = nullptr);
 // passes A and B return the number of partial sums per query they wrote (at most
 // stencil_chunks_all(N); row stride stays stencil_chunks_all(N) in the solver's arrays)
 template <typename TY>
@@ -76,6 +85,36 @@ void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z,
                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                    double* part1, hipStream_t s);
 
+// csr.hip: the same passes for general sparse problems (the stencil launchers above
+// forward to these when g.csr is set)
+int csr_chunks(int rows);
+void csr_coef_tables(const StencilGeom& g, int B, const double* theta, const int* qidx,
+                     double* coef, hipStream_t s);
+void csr_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
+               double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+               const int* flag, double* part, hipStream_t s, double* part2 = nullptr);
+template <typename TY>
+int csr_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
+               int64_t y_ld, const double* p_old, double* p_new, const double* beta,
+               const int* active, double* part, hipStream_t s);
+int csr_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
+               double* x, const double* r_in, double* r_out, const double* alpha,
+               const int* active, double* part, hipStream_t s);
+template <typename TY>
+void csr_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
+                  int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                  const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                  double* part1, hipStream_t s);
+template <typename TY>
+void csr_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
+                int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
+                const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                double* part1, hipStream_t s);
+void csr_to_storage(int N, const int* perm, int B, const double* nat, int64_t nat_ld,
+                    double* sto, int64_t sto_ld, hipStream_t s);
+void csr_from_storage(int N, const int* perm, int B, const double* sto, int64_t sto_ld,
+                      double* nat, int64_t nat_ld, hipStream_t s);
+
 // dense.hip
 ProjPlan plan_projection(int N, int B, int n, int target_blocks);
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
@@ -95,11 +134,15 @@ void launch_fin_alpha(const double* part, int stride, int cnt, const QState& q, 
                       hipStream_t s);
 void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
                    int maxit, bool fixed, hipStream_t s);
+// part2 (nullable): partial sums of (|A||x|)^2; floor_factor > 0 also accepts residuals
+// within floor_factor * eps * || |A||x| || (at_floor)
 void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
-                     int maxit, hipStream_t s);
-// Partial-sum arrays are [B][count] (the stride of each array equals its count).
-void launch_fin_beta(const double* pr, int cr, const double* pb, int cb, const double* fr,
-                     const double* fb, const QState& q, int B, bool flexible, hipStream_t s);
+                     int maxit, hipStream_t s, const double* part2 = nullptr,
+                     double floor_factor = 0.0);
+// Partial sums of y^T r (pr) and y^T r_old (fr): segment c is [B][cnt[c]] starting at
+// element off[c]; the segments are summed in order.
+void launch_fin_beta(const double* pr, const double* fr, const Segs& sg, const QState& q, int B,
+                     bool flexible, hipStream_t s);
 void launch_fin_sum(const double* part, int stride, int cnt, double* out, const int* active,
                     int B, hipStream_t s);
 template <typename T>

@@ -35,9 +35,19 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   e_ld = std::max(16, (n + 15) / 16 * 16);
   y32 = opt.precond_prec != RB_PREC_FP64 && opt.solver != RB_SOLVER_RBI;
   cN = stencil_chunks_all(g.N);
-  cR = stencil_chunks(g.NR);
-  cB = stencil_chunks(g.N - g.NR);
-  pstride = std::max(cN, std::max(cR, (g.N + 1023) / 1024));
+  pstride = std::max(cN, (g.N + 1023) / 1024);
+  // partial sums of the colour sweeps: one segment per colour class, in sweep order
+  gsegs.n = g.C;
+  int64_t acc = 0;
+  for (int c = 0; c < g.C; ++c) {
+    gsegs.cnt[c] = stencil_chunks(g.coff[c + 1] - g.coff[c]);
+    gsegs.off[c] = acc;
+    acc += (int64_t)B * gsegs.cnt[c];
+  }
+  jsegs.n = 1;
+  jsegs.cnt[0] = cN;
+  jsegs.off[0] = 0;
+  const int64_t dot_elems = std::max<int64_t>(acc, (int64_t)B * pstride);
   const int64_t L_ = ld();
   hipStream_t st = s();
 
@@ -63,7 +73,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     std::vector<double> sto((size_t)g.N);
     for (int i = 0; i < B; ++i) {
       for (int pos = 0; pos < g.N; ++pos) {
-        const int Lx = pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
+        const int Lx = prob->nat_index(pos);
         double v = 0.0;
         for (int r = 0; r < R; ++r)
           v += (phi ? phi[(size_t)i * R + r] : 1.0) * prob->f_host[(size_t)r * g.N + Lx];
@@ -115,10 +125,9 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
       z = get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
   }
   part_m = get_ws(WS_PM, sizeof(double) * (size_t)B * pstride);
-  part_r0 = get_ws(WS_PR0, sizeof(double) * (size_t)B * pstride);
-  part_r1 = get_ws(WS_PR1, sizeof(double) * (size_t)B * pstride);
-  part_b0 = get_ws(WS_PB0, sizeof(double) * (size_t)B * pstride);
-  part_b1 = get_ws(WS_PB1, sizeof(double) * (size_t)B * pstride);
+  if (opt.floor_factor > 0.0) part_m2 = get_ws(WS_PM2, sizeof(double) * (size_t)B * pstride);
+  part_r0 = get_ws(WS_PR0, sizeof(double) * (size_t)dot_elems);
+  part_r1 = get_ws(WS_PR1, sizeof(double) * (size_t)dot_elems);
 
   // reduced basis data
   if (n > 0) {
@@ -137,14 +146,16 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   }
 
   // per-query scalars
-  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 5) * (size_t)B);
+  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 6) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
   takeD(q.fnorm2); takeD(q.rho); takeD(q.alpha); takeD(q.beta); takeD(q.rel_rec);
   takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in);
   takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
+  takeI(q.at_floor);
   launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
+  launch_fill<int>(q.at_floor, 0, (int64_t)B, 1, 0, st);
   if (adaptive) {
     q.nuse = nuse_d.as<int>();
     q.gamma2 = opt.adapt_gamma * opt.adapt_gamma;
@@ -206,39 +217,42 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     }
     ProfScope ps(ctx, "prolong", st);
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
-                   q.active, zdst, !y32, L_, full ? 0 : g.NR, g.N, false, st);
+                   q.active, zdst, !y32, L_, full ? 0 : g.coff[1], g.N, false, st);
   } else {
+    const int lo = full ? 0 : g.coff[1];
     if (y32)
-      launch_fill<float>((float*)zdst + (full ? 0 : g.NR), L_, full ? g.N : g.N - g.NR, B, 0.f, st);
+      launch_fill<float>((float*)zdst + lo, L_, g.N - lo, B, 0.f, st);
     else
-      launch_fill<double>((double*)zdst + (full ? 0 : g.NR), L_, full ? g.N : g.N - g.NR, B, 0.0,
-                          st);
+      launch_fill<double>((double*)zdst + lo, L_, g.N - lo, B, 0.0, st);
   }
   double* pr0 = part_r0.as<double>();
   double* pr1 = flex ? part_r1.as<double>() : nullptr;
-  double* pb0 = part_b0.as<double>();
-  double* pb1 = flex ? part_b1.as<double>() : nullptr;
+  // colour class c from the latest values of the others; its y^T r partials go to
+  // segment c (only from the sweep that leaves the class final)
   auto sweep = [&](int color, bool dots) {
-    ProfScope ps(ctx, color ? "gs_black" : "gs_red", st);
+    ProfScope ps(ctx, color == 0 ? "gs_red" : "gs_black", st);
+    double* d0 = dots ? pr0 + gsegs.off[color] : nullptr;
+    double* d1 = dots && pr1 ? pr1 + gsegs.off[color] : nullptr;
     if (y32)
       launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
-                             flex ? r_old : nullptr, L_, q.active, dots ? (color ? pb0 : pr0) : nullptr,
-                             dots ? (color ? pb1 : pr1) : nullptr, st);
+                             flex ? r_old : nullptr, L_, q.active, d0, d1, st);
     else
       launch_gs_color<double>(g, color, B, coef.as<double>(), y.as<double>(), L_, r, L_, nullptr,
-                              flex ? r_old : nullptr, L_, q.active,
-                              dots ? (color ? pb0 : pr0) : nullptr,
-                              dots ? (color ? pb1 : pr1) : nullptr, st);
+                              flex ? r_old : nullptr, L_, q.active, d0, d1, st);
   };
+  const int reps = std::max(1, opt.smooth_sweeps);
   switch (opt.smoother) {
     case RB_SMOOTH_RBGS:
-      sweep(0, true);
-      sweep(1, true);
+      for (int it = 0; it < reps; ++it)
+        for (int c = 0; c < g.C; ++c) sweep(c, it == reps - 1);
       break;
-    case RB_SMOOTH_RBGS_SYM:  // forward (red, black) then backward (black, red); the
-      sweep(0, false);        // repeated black sweep changes nothing
-      sweep(1, true);
-      sweep(0, true);
+    case RB_SMOOTH_RBGS_SYM:  // forward (classes 0..C-1) then backward (C-1..0); the
+      // repeated sweep of class C-1 changes nothing and is skipped
+      for (int it = 0; it < reps; ++it) {
+        const bool last = it == reps - 1;
+        for (int c = 0; c < g.C; ++c) sweep(c, last && c == g.C - 1);
+        for (int c = g.C - 2; c >= 0; --c) sweep(c, last);
+      }
       break;
     default: {  // Jacobi (omega 2/3) or none (omega 0): y = z + omega D^-1 (r - A z)
       const double om = opt.smoother == RB_SMOOTH_JACOBI ? 2.0 / 3.0 : 0.0;
@@ -252,9 +266,11 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   }
 }
 
-static bool dots_split(const rb_solve_opts& o) {
-  return o.solver != RB_SOLVER_CG &&
-         (o.smoother == RB_SMOOTH_RBGS || o.smoother == RB_SMOOTH_RBGS_SYM);
+// the partial-sum segments of y^T r for this solve's smoother
+const Segs& BatchSolver::dot_segs() const {
+  const bool gs = opt.solver != RB_SOLVER_CG &&
+                  (opt.smoother == RB_SMOOTH_RBGS || opt.smoother == RB_SMOOTH_RBGS_SYM);
+  return gs ? gsegs : jsegs;
 }
 
 // RBCG steps 0-3 (Alg. 3): x = 0, r = f, y = RBI(A, r, W, 1), p = y (beta = 0).
@@ -275,9 +291,7 @@ void BatchSolver::init_cg() {
   factor();
   launch_fill<int>(q.restart, 0, B, 1, 1, st);
   precondition(r0.as<double>(), nullptr);
-  const bool split = dots_split(opt);
-  launch_fin_beta(part_r0.as<double>(), split ? cR : cN, split ? part_b0.as<double>() : nullptr,
-                  cB, nullptr, nullptr, q, B, false, st);
+  launch_fin_beta(part_r0.as<double>(), nullptr, dot_segs(), q, B, false, st);
 }
 
 // One RBCG iteration (Alg. 3 steps 5-11) for every active query.
@@ -313,16 +327,16 @@ void BatchSolver::iterate_cg(int k) {
   launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
     ProfScope ps(ctx, "true_residual", st);
+    double* p2 = opt.floor_factor > 0.0 ? part_m2.as<double>() : nullptr;
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
-                 scale_d.as<double>(), q.flag, part_m.as<double>(), st);
-    launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st);
+                 scale_d.as<double>(), q.flag, part_m.as<double>(), st, p2);
+    launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st, p2,
+                    opt.floor_factor);
   }
   // steps 9-10
   precondition(rout, flex ? rin : nullptr);
-  const bool split = dots_split(opt);
-  launch_fin_beta(part_r0.as<double>(), split ? cR : cN, split ? part_b0.as<double>() : nullptr,
-                  cB, flex ? part_r1.as<double>() : nullptr,
-                  (flex && split) ? part_b1.as<double>() : nullptr, q, B, flex, st);
+  launch_fin_beta(part_r0.as<double>(), flex ? part_r1.as<double>() : nullptr, dot_segs(), q, B,
+                  flex, st);
 }
 
 // ---- stand-alone RBI (Alg. 2) ----------------------------------------------------------
@@ -382,22 +396,24 @@ void BatchSolver::iterate_rbi(int k) {
                         nuse_d.as<int>(), L.as<double>(), q.active, nullptr, e64.as<double>(),
                         e32.as<float>(), e_ld, true, st);
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
-                   q.active, xc, true, L_, full ? 0 : g.NR, g.N, true, st);
+                   q.active, xc, true, L_, full ? 0 : g.coff[1], g.N, true, st);
   }
   // step 7: x = S(A, f, x)
   auto sweep = [&](int color) {
     launch_gs_color<double>(g, color, B, coef.as<double>(), xc, L_, f_base, f_ld,
                             scale_d.as<double>(), nullptr, 0, q.active, nullptr, nullptr, st);
   };
+  const int reps = std::max(1, opt.smooth_sweeps);
   switch (opt.smoother) {
     case RB_SMOOTH_RBGS:
-      sweep(0);
-      sweep(1);
+      for (int it = 0; it < reps; ++it)
+        for (int c = 0; c < g.C; ++c) sweep(c);
       break;
     case RB_SMOOTH_RBGS_SYM:
-      sweep(0);
-      sweep(1);
-      sweep(0);
+      for (int it = 0; it < reps; ++it) {
+        for (int c = 0; c < g.C; ++c) sweep(c);
+        for (int c = g.C - 2; c >= 0; --c) sweep(c);
+      }
       break;
     case RB_SMOOTH_JACOBI:
       RB_REQUIRE(f_ld == L_ || prob->R == 1, RB_EUNSUPPORTED, "Jacobi RBI");
@@ -434,7 +450,7 @@ void BatchSolver::final_true_residual() {
 // are overwritten.
 void BatchSolver::autotune() {
   if (!opt.autotune || ctx->tuner.find(tune_key) || opt.solver == RB_SOLVER_RBI ||
-      opt.stencil_kind)
+      opt.stencil_kind || prob->g.csr)
     return;
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
@@ -626,7 +642,8 @@ void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_s
   hipStream_t st = s();
   final_true_residual();
   if (x_user) launch_from_storage(*prob, B, x.as<double>(), ld(), x_user, user_ld, st);
-  std::vector<int> it(B), stt(B), nu(B, n);
+  std::vector<int> it(B), stt(B), nu(B, n), af(B);
+  RB_HIP(hipMemcpyAsync(af.data(), q.at_floor, sizeof(int) * B, hipMemcpyDeviceToHost, st));
   std::vector<double> rr(B), rec(B), fn(B);
   if (n > 0)
     RB_HIP(hipMemcpyAsync(nu.data(), nuse_d.p, sizeof(int) * B, hipMemcpyDeviceToHost, st));
@@ -643,6 +660,7 @@ void BatchSolver::gather(double* x_user, int64_t user_ld, std::vector<rb_query_s
     stats[i].rel_res_true = std::sqrt(rr[i] / fn[i]);
     stats[i].rel_res_recursive = rec[i];
     stats[i].n_used = n > 0 ? nu[i] : 0;
+    stats[i].at_floor = af[i];
   }
 }
 

@@ -21,7 +21,8 @@ struct BatchSolver {
   int n = 0;        // basis columns used (max over queries)
   int e_ld = 16;    // row stride of e
   const int pt = 4;  // nodes per thread of the init/dot kernels (matches stencil_chunks)
-  int cN = 1, cR = 1, cB = 1;  // partial-sum chunks for all / red / black nodes
+  int cN = 1;        // partial-sum chunks of an all-node pass
+  Segs gsegs, jsegs;  // y^T r partial segments: per colour sweep / one whole-vector pass
   int pstride = 1;             // per-query stride of the partial-sum arrays
   bool y32 = false;            // y stored in FP32
   bool adaptive = false;       // adaptive basis size (opt.adapt_gamma > 0)
@@ -32,7 +33,7 @@ struct BatchSolver {
   // device buffers (views of the context's workspace)
   Buf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
   Buf x, r0, r1, p0, p1, y, z;
-  Buf part_m, part_r0, part_r1, part_b0, part_b1;
+  Buf part_m, part_m2, part_r0, part_r1;
   Buf qbuf;  // QState arrays
   QState q{};
   const double* f_base = nullptr;  // right-hand side term(s), storage order
@@ -59,6 +60,7 @@ struct BatchSolver {
   void init_cg();
   void iterate_cg(int k);
   void precondition(const double* r, const double* r_old);
+  const Segs& dot_segs() const;
   // RBI
   void init_rbi();
   void iterate_rbi(int k);

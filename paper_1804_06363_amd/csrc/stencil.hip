@@ -73,6 +73,7 @@ __global__ void k_coef_tables(StencilGeom g, const double* __restrict__ theta,
 
 void launch_coef_tables(const StencilGeom& g, int B, const double* theta, const int* qidx,
                         double* coef, hipStream_t s) {
+  if (g.csr) return csr_coef_tables(g, B, theta, qidx, coef, s);
   const double hx = 1.0 / (g.nx + 1), hy = 1.0 / (g.ny + 1), hz = 1.0 / (g.nz + 1);
   hipLaunchKernelGGL(k_coef_tables, dim3(B), dim3(64), 0, s, g, theta, qidx, coef,
                      1.0 / (hx * hx), 1.0 / (hy * hy), 1.0 / (hz * hz));
@@ -257,6 +258,9 @@ __device__ __forceinline__ T diag_of(const Node<DIM>& n, const T* cf) {
 // ---- y = A(theta) u, or y = rhs - A u with partial ||y||^2 ------------------------------
 // mode 0: y = A u for every query.  mode 1: y = rhs_scale[b] * rhs_b - A u for queries
 // with flag[b] != 0 (others untouched) and partial sums of y^2.
+// group bitmap of the apply kernel: at most 65535 queries, 4 slots -> 16384 groups per block
+constexpr int kApplyMaxGroupWords = 512;
+
 template <int DIM, int QPB>
 __global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, int B, int chunks,
                                                     const double* coef,
@@ -266,40 +270,75 @@ __global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, i
                                                     int64_t rhs_ld,
                                                     const double* __restrict__ rhs_scale,
                                                     const int* __restrict__ flag,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part,
+                                                    double* __restrict__ part2) {
   extern __shared__ double dyn[];
   __shared__ double red[4 * QPB];
+  // A block owns one chunk and the query groups slot, slot + slots, ...: with few slots
+  // an all-but-empty launch (mode 1 with few flagged queries) costs few blocks.  Mode 1
+  // first marks the groups holding a flagged query (one pass over the flags), then
+  // visits only those.
+  __shared__ unsigned gbits[kApplyMaxGroupWords];
   const Tile tl = tile_of(chunks);
-  const int q0 = tl.q0 * QPB;
-  const unsigned mask = load_group<QPB>(g, coef, q0, B, mode == 1 ? flag : nullptr, dyn);
-  if (!mask) return;
-  double acc[QPB];
+  const int slots = gridDim.x / chunks;
+  const int groups = (B + QPB - 1) / QPB;
+  const int mine = (groups - tl.q0 + slots - 1) / slots;  // groups of this block
+  if (mode == 1) {
+    for (int w = threadIdx.x; w < (mine + 31) / 32; w += blockDim.x) gbits[w] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < mine * QPB; i += blockDim.x) {
+      const int b = (tl.q0 + (i / QPB) * slots) * QPB + i % QPB;
+      if (b < B && flag[b]) atomicOr(&gbits[(i / QPB) >> 5], 1u << ((i / QPB) & 31));
+    }
+    __syncthreads();
+  }
+  for (int k_ = 0; k_ < mine; ++k_) {
+    if (mode == 1 && !((gbits[k_ >> 5] >> (k_ & 31)) & 1u)) continue;
+    const int grp = tl.q0 + k_ * slots;
+    const int q0 = grp * QPB;
+    const unsigned mask = load_group<QPB>(g, coef, q0, B, mode == 1 ? flag : nullptr, dyn);
+    if (!mask) continue;
+    double acc[QPB], acc2[QPB];
 #pragma unroll
-  for (int k = 0; k < QPB; ++k) acc[k] = 0.0;
+    for (int k = 0; k < QPB; ++k) acc[k] = acc2[k] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 2 * kPH; ++t) {
-    const int pos = paired_pos(g, tl.chunk, t);
-    if (pos >= 0) {
-      Node<DIM> n;
-      node_at<DIM>(g, pos, n);
+    for (int t = 0; t < 2 * kPH; ++t) {
+      const int pos = paired_pos(g, tl.chunk, t);
+      if (pos >= 0) {
+        Node<DIM> n;
+        node_at<DIM>(g, pos, n);
 #pragma unroll
-      for (int k = 0; k < QPB; ++k) {
-        if (!((mask >> k) & 1u)) continue;
-        const double* cf = dyn + k * g.ct_size;
-        const double* ub = u + (size_t)(q0 + k) * ld;
-        double d;
-        const double Au = apply_at<DIM, double>(n, cf, ub[pos], [&](int s) { return ub[s]; }, d);
-        if (mode == 0) {
-          y[(size_t)(q0 + k) * ld + pos] = Au;
-        } else {
-          const double r = rhs_scale[q0 + k] * rhs[(size_t)(q0 + k) * rhs_ld + pos] - Au;
-          y[(size_t)(q0 + k) * ld + pos] = r;
-          acc[k] += r * r;
+        for (int k = 0; k < QPB; ++k) {
+          if (!((mask >> k) & 1u)) continue;
+          const double* cf = dyn + k * g.ct_size;
+          const double* ub = u + (size_t)(q0 + k) * ld;
+          double d;
+          const double Au =
+              apply_at<DIM, double>(n, cf, ub[pos], [&](int s) { return ub[s]; }, d);
+          if (mode == 0) {
+            y[(size_t)(q0 + k) * ld + pos] = Au;
+          } else {
+            const double r = rhs_scale[q0 + k] * rhs[(size_t)(q0 + k) * rhs_ld + pos] - Au;
+            y[(size_t)(q0 + k) * ld + pos] = r;
+            acc[k] += r * r;
+            if (part2) {  // (|A| |u|)_pos: the face coefficients are non-negative
+              double a = d * fabs(ub[pos]);
+#pragma unroll
+              for (int f = 0; f < 2 * DIM; ++f)
+                a += cf[n.ci[f]] * (((n.inner >> f) & 1u) ? fabs(ub[n.nb[f]]) : 0.0);
+              acc2[k] += a * a;
+            }
+          }
         }
       }
     }
+    if (mode == 1) store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
+    if (mode == 1 && part2) {
+      __syncthreads();
+      store_partials<QPB>(acc2, mask, q0, tl.chunk, chunks, part2, red);
+    }
+    __syncthreads();  // the next group reuses the tables and the reduction slots
   }
-  if (mode == 1) store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
 }
 
 // ---- pass A: p_new = y + beta p_old; q = A p_new; partial p_new^T q -------------------
@@ -505,11 +544,21 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     rowp[q] = (size_t)b * ld;
     rowy[q] = (size_t)b * y_ld;
   }
-  // Loaded raw (y and p separately for pass A) and combined one step later, so that no
-  // load is waited for in the step that issues it.
+  // Pipelining: every load is issued a full step before its use.  At the top of step k
+  // the block issues plane k+3 (raw: y and p apart for pass A, combined two steps later),
+  // the halo of plane k+1 and, for pass B, x and r of plane k+1; buffers alternate by the
+  // parity of k - k0 and the loop is unrolled by two, so they stay in fixed registers
+  // (a loop-carried copy of a just-loaded register waits for it).
   struct Raw {
     double p[kZNodes][QPB];
     TY y[kZNodes][QPB];
+  };
+  struct Halo {
+    double p[QPB];
+    TY y[QPB];
+  };
+  struct XR {
+    double x[kZNodes][QPB], r[kZNodes][QPB];
   };
   auto load_raw = [&](Raw& r, int k) {
 #pragma unroll
@@ -529,14 +578,24 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       for (int q = 0; q < QPB; ++q)
         v[s][q] = MODE == 0 ? (double)r.y[s][q] + sc[q] * r.p[s][q] : r.p[s][q];
   };
-  double hp[QPB];
-  TY hy[QPB];
-  auto load_halo = [&](int k) {
+  auto load_halo = [&](Halo& h, int k) {
     const int pos = spos(k * P + hm);
 #pragma unroll
     for (int q = 0; q < QPB; ++q) {
-      hp[q] = p_in[rowp[q] + pos];
-      if (MODE == 0) hy[q] = y[rowy[q] + pos];
+      h.p[q] = p_in[rowp[q] + pos];
+      if (MODE == 0) h.y[q] = y[rowy[q] + pos];
+    }
+  };
+  auto load_xr = [&](XR& t, int k) {
+    if (MODE != 1) return;
+#pragma unroll
+    for (int s = 0; s < kZNodes; ++s) {
+      const int pos = spos(k * P + m_[s]);
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) {
+        t.x[s][q] = __builtin_nontemporal_load(x + rowp[q] + pos);
+        t.r[s][q] = __builtin_nontemporal_load(r_in + rowp[q] + pos);
+      }
     }
   };
 
@@ -550,43 +609,35 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     zinfo[3 * kk + 2] = g.ct_off[2] + (int)((tz >> 16) & 0xff) * g.ct_s1[2] * g.ct_s2[2];
   }
 
-  // planes k-1, k, k+1 combined; k+2 in flight
+  const int klast = g.nz - 1;
+  // planes k-1, k, k+1 combined; later planes in flight (clamped planes are never used)
   double vb[kZNodes][QPB], vc[kZNodes][QPB], vn[kZNodes][QPB];
-  Raw r2;
+  Raw R0, R1;
+  Halo H0, H1;
+  XR X0, X1;
   {
     Raw t;
-    if (k0 > 0) {
-      load_raw(t, k0 - 1);
-      combine(vb, t);
-    }
+    load_raw(t, max(k0 - 1, 0));
+    combine(vb, t);
     load_raw(t, k0);
     combine(vc, t);
-    if (k0 + 1 < g.nz) {
-      load_raw(t, k0 + 1);
-      combine(vn, t);
-    }
+    load_raw(t, min(k0 + 1, klast));
+    combine(vn, t);
   }
-  load_raw(r2, min(k0 + 2, g.nz - 1));
-  load_halo(k0);
+  load_raw(R0, min(k0 + 2, klast));
+  load_halo(H0, k0);
+  load_xr(X0, k0);
 
   double acc[QPB];
 #pragma unroll
   for (int q = 0; q < QPB; ++q) acc[q] = 0.0;
 
-  for (int k = k0; k < k1; ++k) {
-    // this plane's x and r (pass B) ahead of the barriers
-    double xv[kZNodes][QPB], rv[kZNodes][QPB];
-    int pos_[kZNodes];
-#pragma unroll
-    for (int s = 0; s < kZNodes; ++s) {
-      pos_[s] = spos(k * P + m_[s]);
-      if (MODE == 1)
-#pragma unroll
-        for (int q = 0; q < QPB; ++q) {
-          xv[s][q] = __builtin_nontemporal_load(x + rowp[q] + pos_[s]);
-          rv[s][q] = __builtin_nontemporal_load(r_in + rowp[q] + pos_[s]);
-        }
-    }
+  // one plane; Rk2 holds plane k+2 (raw), Rk3 receives plane k+3; Hk / Xk hold this
+  // plane's halo and x, r; Hn / Xn receive the next plane's
+  auto step = [&](int k, Raw& Rk2, Raw& Rk3, Halo& Hk, Halo& Hn, XR& Xk, XR& Xn) {
+    load_raw(Rk3, min(k + 3, klast));
+    load_halo(Hn, min(k + 1, klast));
+    load_xr(Xn, min(k + 1, klast));
     __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
 #pragma unroll
     for (int s = 0; s < kZNodes; ++s)
@@ -596,16 +647,16 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     if (hv)
 #pragma unroll
       for (int q = 0; q < QPB; ++q)
-        pl[q * plane + hslot] = MODE == 0 ? (double)hy[q] + sc[q] * hp[q] : hp[q];
+        pl[q * plane + hslot] = MODE == 0 ? (double)Hk.y[q] + sc[q] * Hk.p[q] : Hk.p[q];
     __syncthreads();
-    load_halo(min(k + 1, g.nz - 1));
     const int sz = zinfo[3 * (k - k0)];
     const int zlo = zinfo[3 * (k - k0) + 1];
     const int zhi = zinfo[3 * (k - k0) + 2];
-    const unsigned zb = (k > 0 ? 16u : 0u) | (k < g.nz - 1 ? 32u : 0u);
+    const unsigned zb = (k > 0 ? 16u : 0u) | (k < klast ? 32u : 0u);
 #pragma unroll
     for (int s = 0; s < kZNodes; ++s) {
       if (!own[s]) continue;
+      const int pos = spos(k * P + m_[s]);
       const unsigned inner = inb[s] | zb;
       const int ci[6] = {cb[s][0] + sz, cb[s][1] + sz, cb[s][2] + sz, cb[s][3] + sz,
                          zlo + zxy[s], zhi + zxy[s]};
@@ -624,19 +675,18 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
         }
         const double vp = vc[s][q];
         const double Av = d * vp - off;
-        const size_t o = (size_t)(q0 + q) * ld + pos_[s];
+        const size_t o = (size_t)(q0 + q) * ld + pos;
         if (MODE == 0) {
           __builtin_nontemporal_store(vp, p_out + o);
           acc[q] += vp * Av;
         } else {
-          __builtin_nontemporal_store(xv[s][q] + sc[q] * vp, x + o);
-          const double r = rv[s][q] - sc[q] * Av;
+          __builtin_nontemporal_store(Xk.x[s][q] + sc[q] * vp, x + o);
+          const double r = Xk.r[s][q] - sc[q] * Av;
           __builtin_nontemporal_store(r, r_out + o);
           acc[q] += r * r;
         }
       }
     }
-    // shift the planes; the next plane in flight was issued a step ago
 #pragma unroll
     for (int s = 0; s < kZNodes; ++s)
 #pragma unroll
@@ -644,13 +694,11 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
         vb[s][q] = vc[s][q];
         vc[s][q] = vn[s][q];
       }
-    // Unconditional, from a clamped plane (values past the slab or the grid are never
-    // used): a conditional load makes the register allocator copy the loop-carried
-    // values at the back-edge, which waits for the loads just issued.  The loads stay
-    // below the combine so they can reuse its registers.
-    combine(vn, r2);
-    __builtin_amdgcn_sched_barrier(0);
-    load_raw(r2, min(k + 3, g.nz - 1));
+    combine(vn, Rk2);
+  };
+  for (int k = k0; k < k1; k += 2) {
+    step(k, R0, R1, H0, H1, X0, X1);
+    if (k + 1 < k1) step(k + 1, R1, R0, H1, H0, X1, X0);
   }
   // partial sums of the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -815,11 +863,14 @@ static dim3 conv_grid(int N, int B) {
 
 void launch_to_storage(const rb_problem& p, int B, const double* nat, int64_t nat_ld,
                        double* sto, int64_t sto_ld, hipStream_t s) {
+  if (p.g.csr) return csr_to_storage(p.g.N, p.perm.as<int>(), B, nat, nat_ld, sto, sto_ld, s);
   hipLaunchKernelGGL(k_to_storage, conv_grid(p.g.N, B), dim3(256), 0, s, p.g.N, p.g.NR, nat,
                      nat_ld, sto, sto_ld);
 }
 void launch_from_storage(const rb_problem& p, int B, const double* sto, int64_t sto_ld,
                          double* nat, int64_t nat_ld, hipStream_t s) {
+  if (p.g.csr)
+    return csr_from_storage(p.g.N, p.perm.as<int>(), B, sto, sto_ld, nat, nat_ld, s);
   hipLaunchKernelGGL(k_from_storage, conv_grid(p.g.N, B), dim3(256), 0, s, p.g.N, p.g.NR, sto,
                      sto_ld, nat, nat_ld);
 }
@@ -869,13 +920,19 @@ static dim3 grid_for(int chunks, int B, int qpb) {
 
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, hipStream_t s) {
+                  const int* flag, double* part, hipStream_t s, double* part2) {
+  if (g.csr)
+    return csr_apply(g, ld, B, coef, u, y, mode, rhs, rhs_ld, rhs_scale, flag, part, s, part2);
   const int chunks = stencil_chunks_all(g.N);
   const int qpb = pick_qpb(g, B, 8);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
-    hipLaunchKernelGGL((k_apply<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
-                       Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, u, y, mode, rhs, rhs_ld,
-                       rhs_scale, flag, part);
+    // mode 1 (true residual of the flagged queries) runs every iteration, mostly with
+    // no or few flags: 4 group slots per chunk instead of one block per group
+    const int groups = (B + Q.value - 1) / Q.value;
+    const int slots = mode == 1 ? std::min(groups, 4) : groups;
+    hipLaunchKernelGGL((k_apply<D.value, Q.value>), dim3((unsigned)((long)chunks * slots)),
+                       dim3(kThreads), Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, u, y,
+                       mode, rhs, rhs_ld, rhs_scale, flag, part, part2);
   });
 }
 
@@ -946,6 +1003,7 @@ template <typename TY>
 int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                   const int* active, double* part, hipStream_t s) {
+  if (g.csr) return csr_pass_a<TY>(g, ld, B, coef, y, y_ld, p_old, p_new, beta, active, part, s);
   // default 2 queries per block (chunked and marching alike)
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_a ? t_tiles.qpb_a : 2);
   if (const int t = launch_zmarch<0, TY>(g, qpb, ld, B, coef, y, y_ld, p_old, p_new, nullptr,
@@ -969,6 +1027,7 @@ template int launch_pass_a<float>(const StencilGeom&, int64_t, int, const double
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
                   const int* active, double* part, hipStream_t s) {
+  if (g.csr) return csr_pass_b(g, ld, B, coef, p, x, r_in, r_out, alpha, active, part, s);
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 4);
   if (const int t = launch_zmarch<1, double>(g, qpb, ld, B, coef, nullptr, 0, p, nullptr, x, r_in,
                                              r_out, alpha, active, part, s, t_tiles.kind_b))
@@ -987,6 +1046,9 @@ void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef,
                      int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                      const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                      double* part1, hipStream_t s) {
+  if (g.csr)
+    return csr_gs_color<TY>(g, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld,
+                            active, part0, part1, s);
   const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
   const int qpb = pick_qpb(g, B, (int)sizeof(TY), t_tiles.qpb_gs ? t_tiles.qpb_gs : 4);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
@@ -1009,6 +1071,9 @@ void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z,
                    int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                    double* part1, hipStream_t s) {
+  if (g.csr)
+    return csr_jacobi<TY>(g, B, coef, z, y, y_ld, omega, rhs, rhs_ld, rhs2, rhs2_ld, active,
+                          part0, part1, s);
   const int chunks = stencil_chunks_all(g.N);
   const int qpb = pick_qpb(g, B, (int)sizeof(TY));
   dispatch(g.dim, qpb, [&](auto D, auto Q) {

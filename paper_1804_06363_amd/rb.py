@@ -49,12 +49,14 @@ class SolveOpts(C.Structure):
                 ("smoother", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
                 ("beta_flexible", C.c_int), ("use_graph", C.c_int), ("fixed_iters", C.c_int),
                 ("check_every", C.c_int), ("autotune", C.c_int), ("stencil_kind", C.c_int),
-                ("adapt_gamma", C.c_double)]
+                ("adapt_gamma", C.c_double), ("floor_factor", C.c_double),
+                ("smooth_sweeps", C.c_int)]
 
 
 class QueryStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("rel_res_true", C.c_double),
-                ("rel_res_recursive", C.c_double), ("status", C.c_int), ("n_used", C.c_int)]
+                ("rel_res_recursive", C.c_double), ("status", C.c_int), ("n_used", C.c_int),
+                ("at_floor", C.c_int)]
 
 
 class Query(C.Structure):
@@ -100,6 +102,9 @@ _sig("rb_profile_reset", [_P])
 _sig("rb_profile_get", [_P, C.c_int, C.c_char_p, C.c_size_t, _D, C.POINTER(C.c_int64)])
 _sig("rb_problem_create_stencil", [_P, C.POINTER(StencilDesc), C.POINTER(_P)])
 _sig("rb_problem_set_rhs", [_P, C.c_int, _D])
+_sig("rb_problem_create_csr", [_P, C.c_int64, C.c_int, C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int32), _D, C.POINTER(_P)])
+_sig("rb_problem_colors", [_P, C.POINTER(C.c_int32), _I])
 _sig("rb_problem_info", [_P, C.POINTER(C.c_int64), _I, _I])
 _sig("rb_problem_destroy", [_P])
 _sig("rb_basis_from_host", [_P, _P, C.c_int, _D, C.POINTER(_P)])
@@ -130,7 +135,8 @@ _sig("rb_basis_from_parameters", [_P, _P, C.POINTER(GreedyOpts), C.c_int, _D, _D
 EXPORTED = [
     "rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_version",
     "rb_profile_enable", "rb_profile_reset", "rb_profile_get",
-    "rb_problem_create_stencil", "rb_problem_set_rhs", "rb_problem_info", "rb_problem_destroy",
+    "rb_problem_create_stencil", "rb_problem_create_csr", "rb_problem_colors",
+    "rb_problem_set_rhs", "rb_problem_info", "rb_problem_destroy",
     "rb_basis_from_host", "rb_basis_info", "rb_basis_save", "rb_basis_load", "rb_basis_destroy",
     "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi", "rb_apply_batch",
     "rb_precond_batch", "rb_project_batch", "rb_reduced_factor_batch",
@@ -204,21 +210,47 @@ class Context:
 
 
 class Problem:
-    def __init__(self, ctx: Context, dims, blocks):
-        d = StencilDesc()
-        d.dim = len(dims)
-        for a in range(3):
-            d.n[a] = dims[a] if a < len(dims) else 1
-            d.blocks[a] = blocks[a] if a < len(blocks) else 1
-        h = _P()
-        _check(_lib.rb_problem_create_stencil(ctx.h, C.byref(d), C.byref(h)))
+    def __init__(self, ctx: Context, dims=None, blocks=None, _handle=None):
+        if _handle is None:
+            d = StencilDesc()
+            d.dim = len(dims)
+            for a in range(3):
+                d.n[a] = dims[a] if a < len(dims) else 1
+                d.blocks[a] = blocks[a] if a < len(blocks) else 1
+            h = _P()
+            _check(_lib.rb_problem_create_stencil(ctx.h, C.byref(d), C.byref(h)))
+            self.dims, self.blocks = tuple(dims), tuple(blocks)
+        else:
+            h = _handle
+            self.dims, self.blocks = None, None
         self.h, self.ctx = h, ctx
-        self.dims, self.blocks = tuple(dims), tuple(blocks)
         N = C.c_int64()
         Q = C.c_int()
         R = C.c_int()
         _check(_lib.rb_problem_info(h, C.byref(N), C.byref(Q), C.byref(R)))
         self.N, self.Q, self.R = N.value, Q.value, R.value
+
+    @classmethod
+    def from_csr(cls, ctx: Context, rowptr, col, vals):
+        """General sparse affine problem: terms vals [Q][nnz] on the pattern (rowptr, col)."""
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        vals = _f64(np.atleast_2d(vals))
+        N = len(rowptr) - 1
+        h = _P()
+        _check(_lib.rb_problem_create_csr(ctx.h, N, vals.shape[0],
+                                          rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          col.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(vals),
+                                          C.byref(h)))
+        return cls(ctx, _handle=h)
+
+    def colors(self):
+        """Colour class of every unknown (natural order) of the Gauss-Seidel smoother."""
+        out = np.zeros(self.N, dtype=np.int32)
+        nc = C.c_int()
+        _check(_lib.rb_problem_colors(self.h, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      C.byref(nc)))
+        return out, nc.value
 
     def set_rhs(self, f):
         f = _f64(np.atleast_2d(f))
@@ -280,7 +312,7 @@ STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2}
 
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,
                flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False,
-               stencil="auto", adapt_gamma=0.0):
+               stencil="auto", adapt_gamma=0.0, sweeps=1, floor_factor=0.0):
     o = SolveOpts()
     _lib.rb_solve_opts_default(C.byref(o))
     o.solver = SOLVER[solver]
@@ -295,6 +327,8 @@ def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=20
     o.autotune = int(autotune)
     o.stencil_kind = STENCIL_KIND[stencil]
     o.adapt_gamma = adapt_gamma
+    o.smooth_sweeps = sweeps
+    o.floor_factor = floor_factor
     return o
 
 
@@ -305,6 +339,7 @@ class Stats:
     rel_res_recursive: np.ndarray
     status: np.ndarray
     n_used: np.ndarray
+    at_floor: np.ndarray
 
 
 def _stats(arr, B):
@@ -312,7 +347,8 @@ def _stats(arr, B):
                  np.array([arr[i].rel_res_true for i in range(B)]),
                  np.array([arr[i].rel_res_recursive for i in range(B)]),
                  np.array([arr[i].status for i in range(B)]),
-                 np.array([arr[i].n_used for i in range(B)]))
+                 np.array([arr[i].n_used for i in range(B)]),
+                 np.array([arr[i].at_floor for i in range(B)]))
 
 
 def solve_batch(ctx, prob, basis, theta, x=None, phi=None, n_use=None, **kw):

@@ -121,6 +121,29 @@ def test_preconditioner_fp64(lib, ctx, dims, blocks, smoother):
         assert _rel(y[b], ref) <= 1e-12, (b, _rel(y[b], ref))
 
 
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3))])
+@pytest.mark.parametrize("smoother,sweeps", [("rbgs", 2), ("rbgs", 3), ("rbgs_sym", 2)])
+def test_several_sweeps(lib, ctx, dims, blocks, smoother, sweeps):
+    """Several smoother sweeps per application: one preconditioner step and 5 RBCG
+    iterations against the oracle."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 5, seed=17)
+    theta = log_uniform_mu(18, 3, op.Q, 0.1, 10.0)
+    r = random_vectors(19, 3, op.N)
+    y = lib.precond_batch(ctx, prob, basis, theta, _t(r), smoother=smoother,
+                          sweeps=sweeps).cpu().numpy()
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, smoother=smoother, sweeps=sweeps,
+                            fixed_iters=5, flexible=True)
+    x = x.cpu().numpy()
+    for b in range(3):
+        _, M = orb.make_preconditioner(op, theta[b], W, AN, smoother_kind=smoother,
+                                       sweeps=sweeps)
+        assert _rel(y[b], M(r[b])) <= 1e-12
+        ref = orb.solve_rbcg(op, theta[b], W, AN, smoother_kind=smoother, sweeps=sweeps,
+                             fixed_iters=5, flexible=True)
+        assert _rel(x[b], ref.x) <= 1e-10
+
+
 def test_preconditioner_nested_n_use(lib, ctx):
     dims, blocks = (15, 15), (2, 2)
     op, prob, W, basis = _setup(lib, ctx, dims, blocks, 8, seed=10)
@@ -508,3 +531,37 @@ def test_autotuned_solve_matches_default(lib, ctx):
                 kappa = (theta[b].max() * 12.0 / h**2) / (
                     theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
                 assert _rel(b1[b], b0[b]) <= 2 * kappa * 1e-10
+
+
+@pytest.mark.parametrize("which", ["stencil", "csr"])
+def test_rounding_level_acceptance(lib, ctx, which):
+    """A tolerance below the FP64 rounding level of the residual (1e-17) is never met;
+    with floor_factor the true-residual test accepts eps-level residuals instead: status
+    OK, at_floor set, and the residual within floor_factor * eps * || |A||x| || / ||f||
+    (checked on the host).  Without it the solve stops at maxit."""
+    dims, blocks = (31, 31), (2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 4, seed=80)
+    if which == "stencil":
+        prob = lib.Problem(ctx, dims, blocks)
+    else:
+        U = sum(abs(a) for a in op.A_q).tocsr()
+        U.sort_indices()
+        r = np.repeat(np.arange(op.N), np.diff(U.indptr))
+        vals = np.stack([np.asarray(a.tocsr()[r, U.indices]).ravel() for a in op.A_q])
+        prob = lib.Problem.from_csr(ctx, U.indptr, U.indices, vals)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(81, 4, op.Q, 0.01, 100.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, rtol=1e-17, floor_factor=16.0,
+                            flexible=True, maxit=400)
+    x = x.cpu().numpy()
+    f = op.rhs()
+    for b in range(4):
+        assert st.status[b] == lib.RB_OK and st.at_floor[b] == 1
+        A = op.assemble(theta[b])
+        lvl = 16.0 * 2.0 ** -52 * np.linalg.norm(abs(A) @ abs(x[b])) / np.linalg.norm(f)
+        true = np.linalg.norm(f - A @ x[b]) / np.linalg.norm(f)
+        # the host residual carries its own rounding of the same size: a factor 2 of room
+        assert true <= 2.0 * lvl and st.rel_res_true[b] <= lvl * 1.01
+    _, s2 = lib.solve_batch(ctx, prob, basis, theta, rtol=1e-17, flexible=True, maxit=60)
+    assert (s2.status == lib.RB_ENOCONV).all() and (s2.at_floor == 0).all()

@@ -299,3 +299,23 @@ def test_adaptive_two_steps_by_hand():
     # and with gamma below the reduction factor the size stays
     ad2 = rb.solve_rbcg_adaptive(op, theta, W, 0.5 * ratio, n0, flexible=True, fixed_iters=2)
     assert ad2.n_history[:2] == [n0, n0]
+
+
+def test_several_sweeps_are_repeated_forward_substitution():
+    """k forward red-black sweeps equal k steps y <- y + (D + L)^-1 (b - A y) in the
+    red-first ordering, built from the dense matrix."""
+    op = BlockDiffusion((9, 7), (2, 2))
+    th = np.array([0.4, 3.0, 1.7, 0.9])
+    A = op.assemble(th)
+    c = op.colors()
+    order = np.argsort(c, kind="stable")
+    P = A.toarray()[np.ix_(order, order)]
+    DL = np.tril(P)
+    rng = np.random.default_rng(11)
+    b, y0 = rng.standard_normal(op.N), rng.standard_normal(op.N)
+    for k in (2, 3):
+        ref = y0[order].copy()
+        for _ in range(k):
+            ref = ref + np.linalg.solve(DL, b[order] - P @ ref)
+        y = Smoother(A, c, RBGS, sweeps=k)(b, y0)
+        assert np.abs(y[order] - ref).max() <= 1e-12 * np.abs(ref).max()
