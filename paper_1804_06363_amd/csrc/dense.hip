@@ -55,84 +55,88 @@ __device__ __forceinline__ int acc_row(int g, int i) {
 
 // PADDED: R has a multiple of 16*QT rows and W round_up(n, 16) rows, zero beyond B and
 // n, so the loads need no bounds checks (no branches between them).
+// One step = 16 DOFs: lane (qi, kg) holds R[q_base + 16 t + qi][k0 + 4 kg .. +3] of every
+// query tile t and W[16 u + qi][same DOFs] of every basis tile u.
+template <typename TW, int QT, int JT>
+struct ProjFrag {
+  double a[QT][4];
+  TW w[JT][4];
+};
+
 template <typename TW, int QT, int JT, bool PADDED>
-__device__ __forceinline__ void proj_step(const double* __restrict__ R, int64_t r_ld,
+__device__ __forceinline__ void proj_load(const double* __restrict__ R, int64_t r_ld,
                                           const TW* __restrict__ W, int64_t w_ld, int n,
                                           int q_base, int B, const int* __restrict__ active,
-                                          int k0, typename ProjTraits<TW>::Vec (&acc)[QT][JT]) {
+                                          int k0, ProjFrag<TW, QT, JT>& f) {
   const int lane = threadIdx.x & 63;
   const int qi = lane & 15, kg = lane >> 4;
   const int kk = k0 + 4 * kg;
-  double a[QT][4];
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     const int q = q_base + 16 * t + qi;
     if (PADDED || (q < B && active[q])) {
       const double2* src = reinterpret_cast<const double2*>(R + (size_t)q * r_ld + kk);
       const double2 v0 = src[0], v1 = src[1];
-      a[t][0] = v0.x; a[t][1] = v0.y; a[t][2] = v1.x; a[t][3] = v1.y;
+      f.a[t][0] = v0.x; f.a[t][1] = v0.y; f.a[t][2] = v1.x; f.a[t][3] = v1.y;
     } else {
-      a[t][0] = a[t][1] = a[t][2] = a[t][3] = 0.0;
+      f.a[t][0] = f.a[t][1] = f.a[t][2] = f.a[t][3] = 0.0;
     }
   }
+#pragma unroll
+  for (int u = 0; u < JT; ++u) {
+    const int j = 16 * u + qi;
+    const TW* src = W + (size_t)j * w_ld + kk;
+    if (PADDED || j < n) {
+      if constexpr (sizeof(TW) == 8) {
+        const double2 v0 = reinterpret_cast<const double2*>(src)[0];
+        const double2 v1 = reinterpret_cast<const double2*>(src)[1];
+        f.w[u][0] = v0.x; f.w[u][1] = v0.y; f.w[u][2] = v1.x; f.w[u][3] = v1.y;
+      } else if constexpr (sizeof(TW) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        f.w[u][0] = v.x; f.w[u][1] = v.y; f.w[u][2] = v.z; f.w[u][3] = v.w;
+      } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(src);
+        f.w[u][0] = (TW)(v.x & 0xffff); f.w[u][1] = (TW)(v.x >> 16);
+        f.w[u][2] = (TW)(v.y & 0xffff); f.w[u][3] = (TW)(v.y >> 16);
+      }
+    } else {
+      f.w[u][0] = f.w[u][1] = f.w[u][2] = f.w[u][3] = TW(0);
+    }
+  }
+}
+
+template <typename TW, int QT, int JT>
+__device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT>& f,
+                                         typename ProjTraits<TW>::Vec (&acc)[QT][JT]) {
   if constexpr (sizeof(TW) == 8) {  // FP64
-    double w[JT][4];
-#pragma unroll
-    for (int u = 0; u < JT; ++u) {
-      const int j = 16 * u + qi;
-      if (PADDED || j < n) {
-        const double2* src = reinterpret_cast<const double2*>(W + (size_t)j * w_ld + kk);
-        const double2 v0 = src[0], v1 = src[1];
-        w[u][0] = v0.x; w[u][1] = v0.y; w[u][2] = v1.x; w[u][3] = v1.y;
-      } else {
-        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0.0;
-      }
-    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int t = 0; t < QT; ++t)
 #pragma unroll
         for (int u = 0; u < JT; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], w[u][s], acc[t][u], 0, 0, 0);
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[t][s], f.w[u][s], acc[t][u], 0,
+                                                           0, 0);
   } else if constexpr (sizeof(TW) == 4) {  // FP32 operands, FP32 accumulation
-    float w[JT][4];
-#pragma unroll
-    for (int u = 0; u < JT; ++u) {
-      const int j = 16 * u + qi;
-      if (PADDED || j < n) {
-        const float4 v = *reinterpret_cast<const float4*>(W + (size_t)j * w_ld + kk);
-        w[u][0] = v.x; w[u][1] = v.y; w[u][2] = v.z; w[u][3] = v.w;
-      } else {
-        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0.f;
-      }
-    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int t = 0; t < QT; ++t)
 #pragma unroll
         for (int u = 0; u < JT; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[t][s], w[u][s], acc[t][u],
-                                                           0, 0, 0);
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)f.a[t][s], f.w[u][s],
+                                                           acc[t][u], 0, 0, 0);
   } else {  // BF16 operands, FP32 accumulation
     shortx4 w[JT];
 #pragma unroll
-    for (int u = 0; u < JT; ++u) {
-      const int j = 16 * u + qi;
-      if (PADDED || j < n) {
-        const uint2 v = *reinterpret_cast<const uint2*>(W + (size_t)j * w_ld + kk);
-        w[u][0] = (short)(v.x & 0xffff); w[u][1] = (short)(v.x >> 16);
-        w[u][2] = (short)(v.y & 0xffff); w[u][3] = (short)(v.y >> 16);
-      } else {
-        w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0;
-      }
-    }
+    for (int u = 0; u < JT; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) w[u][s] = (short)f.w[u][s];
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       shortx4 av;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) av[s] = (short)rbk::f32_to_bf16_rne((float)a[t][s]);
+      for (int s = 0; s < 4; ++s) av[s] = (short)rbk::f32_to_bf16_rne((float)f.a[t][s]);
 #pragma unroll
       for (int u = 0; u < JT; ++u)
         acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, w[u], acc[t][u], 0, 0, 0);
@@ -170,8 +174,23 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
   for (int t = 0; t < QT; ++t)
 #pragma unroll
     for (int u = 0; u < JT; ++u) acc[t][u] = Vec{0, 0, 0, 0};
-  for (int k0 = k_begin; k0 < k_stop; k0 += 16)
-    proj_step<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active, k0, acc);
+  // two fragments in fixed registers: step k+16 is loaded while step k multiplies (the
+  // loop runs two steps per trip; a prefetch past the range reloads the last step)
+  if (k_begin < k_stop) {
+    const int klast = k_stop - 16;
+    ProjFrag<TW, QT, JT> f0, f1;
+    proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active, k_begin, f0);
+    for (int k0 = k_begin; k0 < k_stop; k0 += 32) {
+      proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active,
+                                    min(k0 + 16, klast), f1);
+      proj_mma<TW, QT, JT>(f0, acc);
+      if (k0 + 16 < k_stop) {
+        proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active,
+                                      min(k0 + 32, klast), f0);
+        proj_mma<TW, QT, JT>(f1, acc);
+      }
+    }
+  }
 
   const int qi = lane & 15, kg = lane >> 4;
   if (!WSPLIT) {
