@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # sources of the dominant kernel: a traffic figure measured on other sources is stale
 KERNEL_SOURCES = ("paper_1804_06363_amd/csrc/stencil.hip", "paper_1804_06363_amd/csrc/common.h",
                   "paper_1804_06363_amd/csrc/kernels.h")
-TRAFFIC_FILE = "profiles/k_pass_b_3d127_B256_fp32.md"
+TRAFFIC_FILE = "profiles/pass_b_zmarch_3d127_B256_fp32.md"
 
 
 def kernel_source_hash():
@@ -42,20 +42,39 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, prec, B):
-    """HBM bytes per launch of k_pass_b from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by the calibration kernels), or None when the summary is for
-    another configuration or the kernel's sources changed since it was taken."""
+def measured_traffic(workload, prec, B, kernel):
+    """HBM bytes per launch of pass B's kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the calibration kernels), or None when the summary
+    is for another configuration or kernel, or the kernel's sources changed since."""
     import re
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if workload != "3d127" or prec != "fp32" or B != 256 or not os.path.exists(path):
         return None
     with open(path) as f:
-        m = re.search(r"^traffic_bytes_per_launch: (\d+) sources_sha256: ([0-9a-f]+)$", f.read(),
-                      re.M)
-    if not m or m.group(2) != kernel_source_hash():
+        m = re.search(r"^traffic_bytes_per_launch: (\d+) sources_sha256: ([0-9a-f]+) "
+                      r"kernel: (.+)$", f.read(), re.M)
+    if not m or m.group(2) != kernel_source_hash() or m.group(3).strip() != kernel:
         return None
     return int(m.group(1))
+
+
+def pass_b_kernel(cache_path, dim, N, B, n, prec):
+    """Name of the kernel that ran pass B, from the tile choice the autotuner wrote to
+    its cache file: {"arch|d<dim>|N<log2 N>|B<log2 B>|n<ceil(n/16)>|p<prec>|s<smoother>":
+    [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b], ...}."""
+    suffix = (f"|d{dim}|N{int(N).bit_length() - 1}|B{int(B).bit_length() - 1}"
+              f"|n{(n + 15) // 16}|p{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[prec] }|s0")
+    try:
+        with open(cache_path) as f:
+            tiles = [v for k, v in json.load(f).items() if k.endswith(suffix)]
+    except (OSError, ValueError):
+        tiles = []
+    if len(tiles) != 1 or len(tiles[0]) < 6:
+        return "pass B (tiles unknown)"
+    qpb_b, kind_b = tiles[0][1], tiles[0][5]
+    if dim == 3 and kind_b == 2:
+        return f"k_zmarch<{qpb_b}, 1, double>"
+    return f"k_pass_b<{dim}, {qpb_b}>"
 
 
 def log(*a):
@@ -109,6 +128,12 @@ def main():
     B = args.B or w.B
     N, Q = w.N, w.Q
     log(f"workload {w.name}: N={N} Q={Q} n={w.n} B={B} prec={args.prec}")
+    # the autotuner's tile choice goes to this file, read back to name pass B's kernel
+    tune_cache = os.environ.get("RB_AUTOTUNE_CACHE")
+    if not tune_cache:
+        import tempfile
+        tune_cache = os.path.join(tempfile.mkdtemp(prefix="rb_tiles_"), "tiles.json")
+        os.environ["RB_AUTOTUNE_CACHE"] = tune_cache
     ctx = rb.Context(0)
     prob = rb.Problem(ctx, w.dims, w.blocks)
     train = w.train_mu()
@@ -165,9 +190,10 @@ def main():
     ms_b, n_b = prof.get("pass_b", (0.0, 0))
     bytes_b = 40.0 * N * iters_total
     achieved = bytes_b / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0
-    roofline = {"kernel": "k_pass_b", "bound": "hbm", "achieved": round(achieved, 1),
+    kernel_b = pass_b_kernel(tune_cache, len(w.dims), N, B, basis.n, args.prec)
+    roofline = {"kernel": kernel_b, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, args.prec, B),
+                "traffic": measured_traffic(args.workload, args.prec, B, kernel_b),
                 "bytes_per_launch": round(bytes_b / max(n_b, 1)),
                 "avg_launch_us": round(ms_b / max(n_b, 1) * 1e3, 1)}
 

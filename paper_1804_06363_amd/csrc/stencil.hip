@@ -593,8 +593,8 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       const int pos = spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
-        t.x[s][q] = __builtin_nontemporal_load(x + rowp[q] + pos);
-        t.r[s][q] = __builtin_nontemporal_load(r_in + rowp[q] + pos);
+        t.x[s][q] = x[rowp[q] + pos];
+        t.r[s][q] = r_in[rowp[q] + pos];
       }
     }
   };
@@ -680,9 +680,9 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
           __builtin_nontemporal_store(vp, p_out + o);
           acc[q] += vp * Av;
         } else {
-          __builtin_nontemporal_store(Xk.x[s][q] + sc[q] * vp, x + o);
+          x[o] = Xk.x[s][q] + sc[q] * vp;
           const double r = Xk.r[s][q] - sc[q] * Av;
-          __builtin_nontemporal_store(r, r_out + o);
+          r_out[o] = r;
           acc[q] += r * r;
         }
       }
@@ -961,12 +961,12 @@ static size_t z_lds(const StencilGeom& g, const ZTile& zt, int qpb) {
          (size_t)3 * zt.kslab * sizeof(int);
 }
 
-// kind: 1 chunked, 2 z-marching, 0 default: z-marching for pass A on 3D batches that
-// give at least one block per CU without slabs, chunked for pass B.  Measured on the
-// 127^3 workload (B = 256, all queries active): pass A 4.04 ms chunked vs 2.48 ms
-// marching; pass B 4.99 ms chunked vs 5.37 ms marching (its x and r streams dominate
-// and the marching blocks keep fewer bytes in flight).  Returns the number of partial
-// sums per query.
+// kind: 1 chunked, 2 z-marching, 0 default: z-marching on 3D batches that give at least
+// one block per CU without slabs.  Measured on the 127^3 workload (B = 256, all queries
+// active, 2 queries per block): pass A 4.04 ms chunked vs 2.35 ms marching; pass B
+// 5.02 ms chunked vs 4.19 ms marching.  Pass B's x and r go through plain loads and
+// stores: with non-temporal ones it took 5.22 ms.  Returns the number of partial sums
+// per query.
 template <int MODE, typename TY>
 static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const double* coef,
                          const TY* y, int64_t y_ld, const double* p_in, double* p_out, double* x,
@@ -977,7 +977,7 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   ZTile zt;
   const int groups = (B + qpb - 1) / qpb;
   if (!z_plan(g, groups, zt) || z_lds(g, zt, qpb) > 65536) return 0;
-  if (kind == 0 && (MODE == 1 || groups * zt.rt * zt.ct < 256)) return 0;
+  if (kind == 0 && groups * zt.rt * zt.ct < 256) return 0;
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const int pstride = stencil_chunks_all(g.N);  // row stride of the partial sums
   const dim3 grid((unsigned)(tiles * groups));
@@ -1004,10 +1004,12 @@ int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, c
                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                   const int* active, double* part, hipStream_t s) {
   if (g.csr) return csr_pass_a<TY>(g, ld, B, coef, y, y_ld, p_old, p_new, beta, active, part, s);
-  // default 2 queries per block (chunked and marching alike)
+  // untuned: 2 queries per block chunked, 1 marching (127^3, B = 256: 2.35 ms vs 2.51 ms
+  // with 2)
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_a ? t_tiles.qpb_a : 2);
-  if (const int t = launch_zmarch<0, TY>(g, qpb, ld, B, coef, y, y_ld, p_old, p_new, nullptr,
-                                         nullptr, nullptr, beta, active, part, s, t_tiles.kind_a))
+  if (const int t = launch_zmarch<0, TY>(g, t_tiles.qpb_a ? qpb : 1, ld, B, coef, y, y_ld, p_old,
+                                         p_new, nullptr, nullptr, nullptr, beta, active, part, s,
+                                         t_tiles.kind_a))
     return t;
   const int chunks = stencil_chunks_all(g.N);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
@@ -1028,7 +1030,7 @@ int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, c
                   double* x, const double* r_in, double* r_out, const double* alpha,
                   const int* active, double* part, hipStream_t s) {
   if (g.csr) return csr_pass_b(g, ld, B, coef, p, x, r_in, r_out, alpha, active, part, s);
-  const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 4);
+  const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 2);
   if (const int t = launch_zmarch<1, double>(g, qpb, ld, B, coef, nullptr, 0, p, nullptr, x, r_in,
                                              r_out, alpha, active, part, s, t_tiles.kind_b))
     return t;
