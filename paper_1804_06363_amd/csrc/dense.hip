@@ -877,9 +877,15 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
   if (threadIdx.x == 0) {
     const double rel = sqrt(rr / q.fnorm2[b]);
     const double lvl = floor_factor * 0x1p-52 * sqrt(aa / q.fnorm2[b]);
+    // The rounding level is a worst-case bound, often far above what the iteration still
+    // reaches, so it is accepted only once a residual replacement has stopped paying:
+    // this check's true residual is above half of the previous check's (0 before the
+    // first check).
+    const double prev = q.rel_true[b];
+    const bool stalled = prev > 0.0 && rel > 0.5 * prev;
     q.rel_true[b] = rel;
     q.flag[b] = 0;
-    if (rel <= rtol || (part2 && rel <= lvl)) {
+    if (rel <= rtol || (part2 && stalled && rel <= lvl)) {
       q.active[b] = 0;
       q.status[b] = RB_OK;
       if (q.at_floor && rel > rtol) q.at_floor[b] = 1;

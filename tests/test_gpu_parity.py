@@ -533,6 +533,35 @@ def test_autotuned_solve_matches_default(lib, ctx):
                 assert _rel(b1[b], b0[b]) <= 2 * kappa * 1e-10
 
 
+def test_rounding_level_needs_a_stall(lib, ctx):
+    """The rounding-level bound eps || |A||x| || / ||f|| is a worst case: on a 255^2 grid
+    with kappa contrast 1e4 it lies up to 1e-9 for these parameters (checked on the host
+    below), while the iteration still reaches 1e-10 (a sparse direct solve: 3e-11).  The
+    floor test accepts only after a residual replacement that did not pay, so every query
+    here ends at its tolerance, none at the bound."""
+    import scipy.sparse.linalg as spla
+    dims, blocks = (255, 255), (4, 4)
+    op = BlockDiffusion(dims, blocks)
+    f = op.rhs()
+    snaps = log_uniform_mu(84, 4, op.Q, 0.1, 10.0)
+    W, _ = np.linalg.qr(np.column_stack([spla.spsolve(op.assemble(m).tocsc(), f)
+                                         for m in snaps]))
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(85, 16, op.Q, 0.01, 100.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, rtol=1e-10, floor_factor=16.0,
+                            flexible=True, maxit=20000)
+    x = x.cpu().numpy()
+    lvl = [16.0 * 2.0 ** -52 * np.linalg.norm(abs(op.assemble(t)) @ abs(x[b])) /
+           np.linalg.norm(f) for b, t in enumerate(theta)]
+    assert max(lvl) > 5e-10
+    assert (st.status == lib.RB_OK).all() and (st.at_floor == 0).all()
+    assert st.rel_res_true.max() <= 1e-10, st.rel_res_true.max()
+    for b in range(16):
+        A = op.assemble(theta[b])
+        assert np.linalg.norm(f - A @ x[b]) / np.linalg.norm(f) <= 1.01e-10
+
+
 @pytest.mark.parametrize("which", ["stencil", "csr"])
 def test_rounding_level_acceptance(lib, ctx, which):
     """A tolerance below the FP64 rounding level of the residual (1e-17) is never met;
