@@ -162,9 +162,10 @@ typedef struct {
                       (problem shape, batch, basis size, precision) is solved and keep
                       the fastest in the context (and in the JSON file named by
                       RB_AUTOTUNE_CACHE, if set); 0: cached choice or built-in default */
-  int stencil_kind; /* 3D passes A and B: 0 = autotuned / default, 1 = chunked over storage
-                       positions, 2 = marching along z with the plane in LDS (3D only; other
-                       grids use 1).  Changes speed and summation order only. */
+  int stencil_kind; /* 3D passes A and B and the colour sweeps: 0 = autotuned / default,
+                       1 = chunked over storage positions, 2 = marching along z with the
+                       plane in LDS (3D only; other grids use 1).  Changes speed and
+                       summation order only. */
   double adapt_gamma; /* RBCG only.  > 0: adaptive basis size (Sec. 4.1, last
                          paragraph): query b starts with n_use[b] vectors (1 if n_use is
                          NULL) and uses one more (up to the basis size) for the next

@@ -124,6 +124,7 @@ struct TuneConfig {
   int qpb_a = 0, qpb_b = 0, qpb_gs = 0;  // queries per block of pass A / pass B / sweeps
   int proj_target = 0;                   // projection: target number of blocks
   int kind_a = 0, kind_b = 0;            // pass A / B: 0 default, 1 chunked, 2 z-marching
+  int kind_gs = 0;                       // colour sweeps: the same kinds
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

@@ -74,11 +74,13 @@ int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, c
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
                   const int* active, double* part, hipStream_t s);
+// returns the number of partial sums per query it wrote (row stride of part0 / part1;
+// at most stencil_chunks of the colour's node count)
 template <typename TY>
-void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
-                     int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                     double* part1, hipStream_t s);
+int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
+                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                    double* part1, hipStream_t s);
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
                    int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,

@@ -40,7 +40,8 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   gsegs.n = g.C;
   int64_t acc = 0;
   for (int c = 0; c < g.C; ++c) {
-    gsegs.cnt[c] = stencil_chunks(g.coff[c + 1] - g.coff[c]);
+    gsegs.cnt[c] = stencil_chunks(g.coff[c + 1] - g.coff[c]);  // at most; each sweep
+                                                                // records its own count
     gsegs.off[c] = acc;
     acc += (int64_t)B * gsegs.cnt[c];
   }
@@ -101,7 +102,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
                std::to_string((int)opt.precond_prec) + "|s" + std::to_string((int)opt.smoother);
     ctx->tuner.load();
     if (const TuneConfig* c = ctx->tuner.find(tune_key)) tc = *c;
-    if (opt.stencil_kind) tc.kind_a = tc.kind_b = opt.stencil_kind;
+    if (opt.stencil_kind) tc.kind_a = tc.kind_b = tc.kind_gs = opt.stencil_kind;
   }
   // projection plan first: for batches it reads residual rows in whole query tiles
   if (n > 0) {
@@ -233,12 +234,13 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     ProfScope ps(ctx, color == 0 ? "gs_red" : "gs_black", st);
     double* d0 = dots ? pr0 + gsegs.off[color] : nullptr;
     double* d1 = dots && pr1 ? pr1 + gsegs.off[color] : nullptr;
-    if (y32)
-      launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_, nullptr,
-                             flex ? r_old : nullptr, L_, q.active, d0, d1, st);
-    else
-      launch_gs_color<double>(g, color, B, coef.as<double>(), y.as<double>(), L_, r, L_, nullptr,
-                              flex ? r_old : nullptr, L_, q.active, d0, d1, st);
+    // the sweep reports how many partial sums per query it wrote (chunked or marching)
+    const int cnt =
+        y32 ? launch_gs_color<float>(g, color, B, coef.as<double>(), y.as<float>(), L_, r, L_,
+                                     nullptr, flex ? r_old : nullptr, L_, q.active, d0, d1, st)
+            : launch_gs_color<double>(g, color, B, coef.as<double>(), y.as<double>(), L_, r, L_,
+                                      nullptr, flex ? r_old : nullptr, L_, q.active, d0, d1, st);
+    if (dots) gsegs.cnt[color] = cnt;
   };
   const int reps = std::max(1, opt.smooth_sweeps);
   switch (opt.smoother) {
@@ -444,8 +446,8 @@ void BatchSolver::final_true_residual() {
 }
 
 // Times candidate tiles on this solve's own (not yet initialised) buffers and keeps the
-// fastest: kind (chunked or z-marching) and queries per block of pass A and pass B,
-// queries per block of the colour sweeps, and the number of projection blocks (timed
+// fastest: kind (chunked or z-marching) and queries per block of pass A, pass B and the
+// colour sweeps, and the number of projection blocks (timed
 // with the reduction of their partials).  Runs before init, so the values it computes
 // are overwritten.
 void BatchSolver::autotune() {
@@ -505,21 +507,26 @@ void BatchSolver::autotune() {
       if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; }
     }
   }
-  for (int c : caps) {
-    if (c > B) break;
-    cur = best;
-    cur.qpb_gs = c;
-    set_stencil_tiles(cur);
-    const float t3 = timed([&] {
-      if (y32)
-        launch_gs_color<float>(g, 0, B, coef.as<double>(), y.as<float>(), L_, r0.as<double>(), L_,
-                               nullptr, nullptr, L_, q.active, part_r0.as<double>(), nullptr, st);
-      else
-        launch_gs_color<double>(g, 0, B, coef.as<double>(), y.as<double>(), L_, r0.as<double>(),
-                                L_, nullptr, nullptr, L_, q.active, part_r0.as<double>(), nullptr,
-                                st);
-    });
-    if (t3 < tg) { tg = t3; best.qpb_gs = c; }
+  for (int kind : {1, 2}) {  // chunked, marching (3D only)
+    if (kind == 2 && g.dim != 3) break;
+    for (int c : caps) {
+      if (c > B || (kind == 2 && c > 4)) break;
+      cur = best;
+      cur.qpb_gs = c;
+      cur.kind_gs = kind;
+      set_stencil_tiles(cur);
+      const float t3 = timed([&] {
+        if (y32)
+          launch_gs_color<float>(g, 0, B, coef.as<double>(), y.as<float>(), L_, r0.as<double>(),
+                                 L_, nullptr, nullptr, L_, q.active, part_r0.as<double>(),
+                                 nullptr, st);
+        else
+          launch_gs_color<double>(g, 0, B, coef.as<double>(), y.as<double>(), L_,
+                                  r0.as<double>(), L_, nullptr, nullptr, L_, q.active,
+                                  part_r0.as<double>(), nullptr, st);
+      });
+      if (t3 < tg) { tg = t3; best.qpb_gs = c; best.kind_gs = kind; }
+    }
   }
   if (n > 0 && !plan.wsplit) {
     float tp = 1e30f;

@@ -785,6 +785,255 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
   }
 }
 
+// ---- one colour half-sweep marching along z (3D) ----------------------------------------
+// Same update and partial sums as k_gs_color, for the nodes of colour `color`.  A block
+// owns QPB queries, an in-plane tile of zr rows x zc columns (zc even) and a slab of
+// planes.  Thread t owns the x-adjacent pair of columns (i0 + 2u, i0 + 2u + 1) of one
+// tile row: on every plane one of the two nodes has the swept colour (it is updated) and
+// the other the opposite colour (its y is a neighbour value), and they swap from plane
+// to plane.  The opposite-colour values of the current plane go to LDS for the in-plane
+// neighbours; the z neighbours of an updated node are the opposite-colour values of its
+// own column on the planes below and above, which this thread loaded as its other node
+// there, so they stay in registers.  Loads are issued ahead as in the marching passes:
+// the neighbour values of plane k+3 (two steps ahead), the halo, rhs (and rhs2) of
+// plane k+1.  Partial sums go to part[b * tiles + tile].
+template <int QPB, typename TY, bool FLEX>
+__global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt, int color,
+                                                         int B, const double* coef,
+                                                         TY* __restrict__ y, int64_t y_ld,
+                                                         const double* __restrict__ rhs,
+                                                         int64_t rhs_ld,
+                                                         const double* __restrict__ rhs_scale,
+                                                         const double* __restrict__ rhs2,
+                                                         int64_t rhs2_ld,
+                                                         const int* __restrict__ active,
+                                                         double* __restrict__ part0,
+                                                         double* __restrict__ part1) {
+  constexpr int NW = kZThreads / 64;
+  extern __shared__ double dyn[];
+  __shared__ double red[NW * QPB];
+  const int tiles2 = zt.rt * zt.ct;
+  const int tiles = tiles2 * zt.slabs;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % tiles;
+  const int q0 = (blk / tiles) * QPB;
+  const int slab = tile / tiles2;
+  const int rtile = (tile % tiles2) / zt.ct, ctile = tile % zt.ct;
+  TY* cfs = reinterpret_cast<TY*>(dyn);
+  const int W2 = zt.zc + 2;  // LDS row pitch (halo column on each side)
+  const int plane = (zt.zr + 2) * W2;
+  TY* pl = cfs + QPB * g.ct_size;  // [QPB][zr + 2][zc + 2]
+  const unsigned mask = load_group<QPB, TY>(g, coef, q0, B, active, cfs);
+  if (!mask) return;
+  const int j0 = rtile * zt.zr, i0 = ctile * zt.zc;  // i0 is even
+  const int k0 = slab * zt.kslab;
+  const int k1 = min(g.nz, k0 + zt.kslab);
+  const int P = g.nxy;
+  const int klast = g.nz - 1;
+
+  double fsc[QPB];
+#pragma unroll
+  for (int q = 0; q < QPB; ++q)
+    fsc[q] = (rhs_scale && ((mask >> q) & 1u)) ? rhs_scale[q0 + q] : 1.0;
+
+  // the pair of columns of this thread: offsets, LDS slots, coefficient bases, boundary
+  const int pairs = zt.zc >> 1;
+  const int jj = threadIdx.x / pairs, pu = threadIdx.x - jj * pairs;
+  const int j = j0 + jj;
+  const bool rowok = jj < zt.zr && j < g.ny;
+  const int jc = rowok ? j : 0;
+  int m_[2], slot[2], cb[2][4], zxy[2];
+  unsigned inb[2];
+  bool own[2];
+#pragma unroll
+  for (int c2 = 0; c2 < 2; ++c2) {
+    const int i = i0 + 2 * pu + c2;
+    own[c2] = rowok && i < g.nx;
+    const int ic = own[c2] ? i : 0;
+    m_[c2] = ic + g.nx * jc;
+    slot[c2] = (jj + 1) * W2 + 2 * pu + c2 + 1;
+    const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
+    const int sx = tx & 0xff, sy = ty & 0xff;
+    cb[c2][0] = g.ct_off[0] + ((int)((tx >> 8) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+    cb[c2][1] = g.ct_off[0] + ((int)((tx >> 16) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+    cb[c2][2] = g.ct_off[1] + ((int)((ty >> 8) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+    cb[c2][3] = g.ct_off[1] + ((int)((ty >> 16) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+    zxy[c2] = sx * g.ct_s2[2] + sy;
+    inb[c2] = (ic > 0 ? 1u : 0u) | (ic < g.nx - 1 ? 2u : 0u) | (jc > 0 ? 4u : 0u) |
+              (jc < g.ny - 1 ? 8u : 0u);
+  }
+  // the column updated on plane k (the colour of node (i, j, k) is the parity of
+  // i + j + k, and i0 + 2u is even); the other one holds the neighbour value
+  auto ucol = [&](int k) { return (j + k + color) & 1; };
+  // halo cell of this thread (rows j0-1, j0+zr and columns i0-1, i0+zc of the tile)
+  int hm, hslot;
+  bool hv;
+  {
+    const int h = threadIdx.x;
+    int hj, hi;
+    if (h < zt.zc) { hj = -1; hi = h; }
+    else if (h < 2 * zt.zc) { hj = zt.zr; hi = h - zt.zc; }
+    else if (h < 2 * zt.zc + zt.zr) { hj = h - 2 * zt.zc; hi = -1; }
+    else { hj = h - 2 * zt.zc - zt.zr; hi = zt.zc; }
+    const int i = i0 + hi, jh = j0 + hj;
+    hv = h < 2 * (zt.zc + zt.zr) && i >= 0 && i < g.nx && jh >= 0 && jh < g.ny;
+    hm = hv ? i + g.nx * jh : 0;
+    hslot = (hj + 1) * W2 + hi + 1;
+  }
+
+  auto spos = [&](int L) { return (L & 1) ? g.NR + (L >> 1) : (L >> 1); };
+  auto live = [&](int q) { return ((mask >> q) & 1u) != 0; };
+  // Every load is unconditional, from a valid address (clamped query row; position
+  // m = 0 for columns outside the tile or the grid, whose values are never read).
+  size_t rowy[QPB], rowr[QPB], rowr2[QPB];
+#pragma unroll
+  for (int q = 0; q < QPB; ++q) {
+    const int b = min(q0 + q, B - 1);
+    rowy[q] = (size_t)b * y_ld;
+    rowr[q] = (size_t)b * rhs_ld;
+    rowr2[q] = FLEX ? (size_t)b * rhs2_ld : 0;
+  }
+  struct Raw {
+    TY v[QPB];
+  };
+  struct Rhs {
+    double r[QPB], r2[QPB];
+  };
+  // neighbour value of this thread's column pair on plane k
+  auto load_raw = [&](Raw& t, int k) {
+    const int c2 = 1 - ucol(k);
+    const int pos = spos(k * P + (c2 ? m_[1] : m_[0]));
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) t.v[q] = y[rowy[q] + pos];
+  };
+  auto load_halo = [&](Raw& t, int k) {
+    const int pos = spos(k * P + hm);
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) t.v[q] = y[rowy[q] + pos];
+  };
+  // right-hand side(s) at the node updated on plane k
+  auto load_rhs = [&](Rhs& t, int k) {
+    const int c2 = ucol(k);
+    const int pos = spos(k * P + (c2 ? m_[1] : m_[0]));
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) {
+      t.r[q] = rhs[rowr[q] + pos];
+      if (FLEX) t.r2[q] = rhs2[rowr2[q] + pos];
+    }
+  };
+
+  int* zinfo = reinterpret_cast<int*>(pl + QPB * plane);  // [kslab][3]
+  for (int kk = threadIdx.x; kk < k1 - k0; kk += kZThreads) {
+    const uint32_t tz = g.tab[2][k0 + kk];
+    zinfo[3 * kk] = tz & 0xff;
+    zinfo[3 * kk + 1] = g.ct_off[2] + (int)((tz >> 8) & 0xff) * g.ct_s1[2] * g.ct_s2[2];
+    zinfo[3 * kk + 2] = g.ct_off[2] + (int)((tz >> 16) & 0xff) * g.ct_s1[2] * g.ct_s2[2];
+  }
+
+  // neighbour values of planes k-1, k, k+1; plane k+2 in R0, later planes in flight
+  TY vb[QPB], vc[QPB], vn[QPB];
+  Raw R0, R1, H0, H1;
+  Rhs X0, X1;
+  {
+    Raw t;
+    load_raw(t, max(k0 - 1, 0));
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) vb[q] = t.v[q];
+    load_raw(t, k0);
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) vc[q] = t.v[q];
+    load_raw(t, min(k0 + 1, klast));
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) vn[q] = t.v[q];
+  }
+  load_raw(R0, min(k0 + 2, klast));
+  load_halo(H0, k0);
+  load_rhs(X0, k0);
+
+  double a0[QPB], a1[QPB];
+#pragma unroll
+  for (int q = 0; q < QPB; ++q) a0[q] = a1[q] = 0.0;
+
+  auto step = [&](int k, Raw& Rk2, Raw& Rk3, Raw& Hk, Raw& Hn, Rhs& Xk, Rhs& Xn) {
+    load_raw(Rk3, min(k + 3, klast));
+    load_halo(Hn, min(k + 1, klast));
+    load_rhs(Xn, min(k + 1, klast));
+    __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
+    const int cu = ucol(k);
+    const bool own_s = cu ? own[0] : own[1];
+    const int slot_s = cu ? slot[0] : slot[1];
+    if (own_s)
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) pl[q * plane + slot_s] = vc[q];
+    if (hv)
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) pl[q * plane + hslot] = Hk.v[q];
+    __syncthreads();
+    const bool own_u = cu ? own[1] : own[0];
+    if (own_u) {
+      const int sz = zinfo[3 * (k - k0)];
+      const int zlo = zinfo[3 * (k - k0) + 1];
+      const int zhi = zinfo[3 * (k - k0) + 2];
+      const unsigned zb = (k > 0 ? 16u : 0u) | (k < klast ? 32u : 0u);
+      const int pos = spos(k * P + (cu ? m_[1] : m_[0]));
+      const unsigned inner = (cu ? inb[1] : inb[0]) | zb;
+      const int su = cu ? slot[1] : slot[0];
+      const int zx = cu ? zxy[1] : zxy[0];
+      const int ci[6] = {(cu ? cb[1][0] : cb[0][0]) + sz, (cu ? cb[1][1] : cb[0][1]) + sz,
+                         (cu ? cb[1][2] : cb[0][2]) + sz, (cu ? cb[1][3] : cb[0][3]) + sz,
+                         zlo + zx, zhi + zx};
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) {
+        if (!live(q)) continue;
+        const TY* cf = cfs + q * g.ct_size;
+        const TY* lp = pl + q * plane + su;
+        const TY nv[6] = {lp[-1], lp[1], lp[-W2], lp[W2], vb[q], vn[q]};
+        TY d = TY(0), off = TY(0);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const TY c = cf[ci[f]];
+          d += c;
+          off += c * (((inner >> f) & 1u) ? nv[f] : TY(0));
+        }
+        const double fp = fsc[q] * Xk.r[q];
+        const TY v = (TY)(((TY)fp + off) / d);
+        y[(size_t)(q0 + q) * y_ld + pos] = v;
+        a0[q] += (double)v * fp;
+        if (FLEX) a1[q] += (double)v * Xk.r2[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) {
+      vb[q] = vc[q];
+      vc[q] = vn[q];
+      vn[q] = Rk2.v[q];
+    }
+  };
+  for (int k = k0; k < k1; k += 2) {
+    step(k, R0, R1, H0, H1, X0, X1);
+    if (k + 1 < k1) step(k + 1, R1, R0, H1, H0, X1, X0);
+  }
+  // partial sums of the block
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  auto store = [&](const double (&acc)[QPB], double* part) {
+    __syncthreads();  // red is free
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) {
+      const double v = rbk::wave_sum(acc[q]);
+      if (lane == 0) red[q * NW + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < QPB && live(threadIdx.x)) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) t += red[threadIdx.x * NW + i];
+      part[(size_t)(q0 + threadIdx.x) * tiles + tile] = t;
+    }
+  };
+  if (part0) store(a0, part0);
+  if (FLEX && part1) store(a1, part1);
+}
+
 // ---- damped Jacobi: y = z + omega D^-1 (rhs - A z), partial y^T rhs (and y^T rhs2) ------
 template <int DIM, int QPB, typename TY>
 __global__ __launch_bounds__(kThreads) void k_jacobi(StencilGeom g, int B, int chunks,
@@ -1043,30 +1292,96 @@ int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, c
   return chunks;
 }
 
+// Tile of the marching colour sweeps: an even number of columns (pairs per thread), at
+// most `cap` tiles per query (the partial sums the solver holds for one colour).
+static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
+  if (g.dim != 3) return false;
+  zt.zc = std::min(g.nx + 1, 128);  // nx is odd: the last column of the last tile is outside
+  const int pairs = zt.zc / 2;
+  zt.zr = std::min(g.ny, kZThreads / pairs);
+  if (zt.zr < 1 || 2 * (zt.zc + zt.zr) > kZThreads) return false;
+  zt.ct = (g.nx + zt.zc - 1) / zt.zc;
+  zt.rt = (g.ny + zt.zr - 1) / zt.zr;
+  const int tiles2 = zt.rt * zt.ct;
+  if (tiles2 > cap) return false;
+  int slabs = (2048 + groups * tiles2 - 1) / (groups * tiles2);
+  slabs = std::max(1, std::min({slabs, g.nz / 8, cap / tiles2}));
+  zt.kslab = (g.nz + slabs - 1) / slabs;
+  zt.slabs = (g.nz + zt.kslab - 1) / zt.kslab;
+  return true;
+}
+
+// kind: 1 chunked, 2 marching, 0 default: chunked.  Measured on the 127^3 workload
+// (B = 256, FP32): a sweep takes 1.03 ms chunked with 4 queries per block and 1.05-1.09 ms
+// marching with 1-4: a sweep moves only 8 B per node, so the two barriers per plane weigh
+// more than in pass B.  The autotuner tries both.  Returns the number of partial sums per
+// query (0: not run).
 template <typename TY>
-void launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
-                     int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
-                     double* part1, hipStream_t s) {
-  if (g.csr)
-    return csr_gs_color<TY>(g, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld,
-                            active, part0, part1, s);
-  const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
+static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, const double* coef,
+                            TY* y, int64_t y_ld, const double* rhs, int64_t rhs_ld,
+                            const double* rhs_scale, const double* rhs2, int64_t rhs2_ld,
+                            const int* active, double* part0, double* part1, hipStream_t s,
+                            int kind) {
+  if (kind != 2) return 0;
+  qpb = std::min(qpb, 4);
+  ZTile zt;
+  const int groups = (B + qpb - 1) / qpb;
+  if (!zg_plan(g, groups, stencil_chunks(color ? g.N - g.NR : g.NR), zt)) return 0;
+  const size_t lds = (size_t)qpb * (g.ct_size + (zt.zr + 2) * (zt.zc + 2)) * sizeof(TY) +
+                     (size_t)3 * zt.kslab * sizeof(int);
+  if (lds > 65536) return 0;
+  const int tiles = zt.rt * zt.ct * zt.slabs;
+  const dim3 grid((unsigned)(tiles * groups));
+  auto go = [&](auto Q, auto F) {
+    hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value>), grid, dim3(kZThreads), lds, s, g, zt,
+                       color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                       part0, part1);
+  };
+  auto by_q = [&](auto F) {
+    switch (qpb) {
+      case 4: go(std::integral_constant<int, 4>{}, F); break;
+      case 2: go(std::integral_constant<int, 2>{}, F); break;
+      default: go(std::integral_constant<int, 1>{}, F); break;
+    }
+  };
+  if (rhs2)
+    by_q(std::true_type{});
+  else
+    by_q(std::false_type{});
+  return tiles;
+}
+
+template <typename TY>
+int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
+                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                    const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
+                    double* part1, hipStream_t s) {
+  if (g.csr) {
+    csr_gs_color<TY>(g, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                     part0, part1, s);
+    return stencil_chunks(g.coff[color + 1] - g.coff[color]);
+  }
   const int qpb = pick_qpb(g, B, (int)sizeof(TY), t_tiles.qpb_gs ? t_tiles.qpb_gs : 4);
+  if (const int t = launch_gs_zmarch<TY>(g, color, qpb, B, coef, y, y_ld, rhs, rhs_ld,
+                                         rhs_scale, rhs2, rhs2_ld, active, part0, part1, s,
+                                         t_tiles.kind_gs))
+    return t;
+  const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY>), grid_for(chunks, B, Q.value),
                        dim3(kThreads), Q.value * g.ct_size * (int)sizeof(TY), s, g, color, B,
                        chunks, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
                        part0, part1);
   });
+  return chunks;
 }
-template void launch_gs_color<double>(const StencilGeom&, int, int, const double*, double*,
-                                      int64_t, const double*, int64_t, const double*,
-                                      const double*, int64_t, const int*, double*, double*,
-                                      hipStream_t);
-template void launch_gs_color<float>(const StencilGeom&, int, int, const double*, float*, int64_t,
-                                     const double*, int64_t, const double*, const double*,
-                                     int64_t, const int*, double*, double*, hipStream_t);
+template int launch_gs_color<double>(const StencilGeom&, int, int, const double*, double*,
+                                     int64_t, const double*, int64_t, const double*,
+                                     const double*, int64_t, const int*, double*, double*,
+                                     hipStream_t);
+template int launch_gs_color<float>(const StencilGeom&, int, int, const double*, float*, int64_t,
+                                    const double*, int64_t, const double*, const double*,
+                                    int64_t, const int*, double*, double*, hipStream_t);
 
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,

@@ -25,7 +25,8 @@ void Tuner::put(const std::string& key, const TuneConfig& c) {
 }
 
 // File format: one JSON object,
-// {"key": [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b], ...} (the last two optional)
+// {"key": [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs], ...} (the last
+// three optional)
 void Tuner::load() {
   if (loaded) return;
   loaded = true;
@@ -46,9 +47,10 @@ void Tuner::load() {
     const size_t r = t.find(']', l);
     if (b == std::string::npos || l == std::string::npos || r == std::string::npos) break;
     TuneConfig c;
-    const int got = std::sscanf(t.c_str() + l + 1, "%d , %d , %d , %d , %d , %d", &c.qpb_a,
-                                &c.qpb_b, &c.qpb_gs, &c.proj_target, &c.kind_a, &c.kind_b);
-    if (got == 4 || got == 6) put(t.substr(a + 1, b - a - 1), c);
+    const int got =
+        std::sscanf(t.c_str() + l + 1, "%d , %d , %d , %d , %d , %d , %d", &c.qpb_a, &c.qpb_b,
+                    &c.qpb_gs, &c.proj_target, &c.kind_a, &c.kind_b, &c.kind_gs);
+    if (got == 4 || got == 6 || got == 7) put(t.substr(a + 1, b - a - 1), c);
     i = r + 1;
   }
 }
@@ -61,7 +63,8 @@ void Tuner::save() const {
   for (size_t i = 0; i < table.size(); ++i) {
     const TuneConfig& c = table[i].second;
     f << "  \"" << table[i].first << "\": [" << c.qpb_a << ", " << c.qpb_b << ", " << c.qpb_gs
-      << ", " << c.proj_target << ", " << c.kind_a << ", " << c.kind_b << "]"
+      << ", " << c.proj_target << ", " << c.kind_a << ", " << c.kind_b << ", " << c.kind_gs
+      << "]"
       << (i + 1 < table.size() ? "," : "") << "\n";
   }
   f << "}\n";
