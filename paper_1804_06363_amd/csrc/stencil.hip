@@ -789,15 +789,16 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
 // ---- one colour half-sweep marching along z (3D) ----------------------------------------
 // Same update and partial sums as k_gs_color, for the nodes of colour `color`.  A block
 // owns QPB queries, an in-plane tile of zr rows x zc columns (zc even) and a slab of
-// planes.  Thread t owns the x-adjacent pair of columns (i0 + 2u, i0 + 2u + 1) of one
-// tile row: on every plane one of the two nodes has the swept colour (it is updated) and
-// the other the opposite colour (its y is a neighbour value), and they swap from plane
-// to plane.  The opposite-colour values of the current plane go to LDS for the in-plane
-// neighbours; the z neighbours of an updated node are the opposite-colour values of its
-// own column on the planes below and above, which this thread loaded as its other node
-// there, so they stay in registers.  Loads are issued ahead as in the marching passes:
-// the neighbour values of plane k+3 (two steps ahead), the halo, rhs (and rhs2) of
-// plane k+1.  Partial sums go to part[b * tiles + tile].
+// planes.  A thread owns kGsPairs x-adjacent pairs of columns (i0 + 2u, i0 + 2u + 1), in
+// rows kGsRowStep apart: on every plane one node of a pair has the swept colour (it is
+// updated) and the other the opposite colour (its y is a neighbour value), and they swap
+// from plane to plane.  The opposite-colour values of the current plane go to LDS for
+// the in-plane neighbours; the z neighbours of an updated node are the opposite-colour
+// values of its own column on the planes below and above, which this thread loaded as
+// the other node of the pair there, so they stay in registers.  Loads are issued ahead
+// as in the marching passes: the neighbour values of plane k+3 (two steps ahead), the
+// halo, rhs (and rhs2) of plane k+1.  Partial sums go to part[b * tiles + tile].
+constexpr int kGsPairs = 2;  // pairs per thread: tiles of up to 2 * 512 / (zc / 2) rows
 template <int QPB, typename TY, bool FLEX>
 __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt, int color,
                                                          int B, const double* coef,
@@ -811,6 +812,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
                                                          double* __restrict__ part0,
                                                          double* __restrict__ part1) {
   constexpr int NW = kZThreads / 64;
+  constexpr int NP = kGsPairs;
   extern __shared__ double dyn[];
   __shared__ double red[NW * QPB];
   const int tiles2 = zt.rt * zt.ct;
@@ -837,35 +839,40 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   for (int q = 0; q < QPB; ++q)
     fsc[q] = (rhs_scale && ((mask >> q) & 1u)) ? rhs_scale[q0 + q] : 1.0;
 
-  // the pair of columns of this thread: offsets, LDS slots, coefficient bases, boundary
+  // the pairs of columns of this thread: offsets, LDS slots, coefficient bases, boundary
   const int pairs = zt.zc >> 1;
-  const int jj = threadIdx.x / pairs, pu = threadIdx.x - jj * pairs;
-  const int j = j0 + jj;
-  const bool rowok = jj < zt.zr && j < g.ny;
-  const int jc = rowok ? j : 0;
-  int m_[2], slot[2], cb[2][4], zxy[2];
-  unsigned inb[2];
-  bool own[2];
+  const int rstep = kZThreads / pairs;  // rows between a thread's pairs
+  const int pu = threadIdx.x % pairs;
+  int j[NP], m_[NP][2], slot[NP][2], cb[NP][2][4], zxy[NP][2];
+  unsigned inb[NP][2];
+  bool own[NP][2];
 #pragma unroll
-  for (int c2 = 0; c2 < 2; ++c2) {
-    const int i = i0 + 2 * pu + c2;
-    own[c2] = rowok && i < g.nx;
-    const int ic = own[c2] ? i : 0;
-    m_[c2] = ic + g.nx * jc;
-    slot[c2] = (jj + 1) * W2 + 2 * pu + c2 + 1;
-    const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
-    const int sx = tx & 0xff, sy = ty & 0xff;
-    cb[c2][0] = g.ct_off[0] + ((int)((tx >> 8) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
-    cb[c2][1] = g.ct_off[0] + ((int)((tx >> 16) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
-    cb[c2][2] = g.ct_off[1] + ((int)((ty >> 8) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
-    cb[c2][3] = g.ct_off[1] + ((int)((ty >> 16) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
-    zxy[c2] = sx * g.ct_s2[2] + sy;
-    inb[c2] = (ic > 0 ? 1u : 0u) | (ic < g.nx - 1 ? 2u : 0u) | (jc > 0 ? 4u : 0u) |
-              (jc < g.ny - 1 ? 8u : 0u);
+  for (int a = 0; a < NP; ++a) {
+    const int jj = threadIdx.x / pairs + a * rstep;
+    j[a] = j0 + jj;
+    const bool rowok = jj < zt.zr && j[a] < g.ny;
+    const int jc = rowok ? j[a] : 0;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int i = i0 + 2 * pu + c2;
+      own[a][c2] = rowok && i < g.nx;
+      const int ic = own[a][c2] ? i : 0;
+      m_[a][c2] = ic + g.nx * jc;
+      slot[a][c2] = (jj + 1) * W2 + 2 * pu + c2 + 1;
+      const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
+      const int sx = tx & 0xff, sy = ty & 0xff;
+      cb[a][c2][0] = g.ct_off[0] + ((int)((tx >> 8) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+      cb[a][c2][1] = g.ct_off[0] + ((int)((tx >> 16) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+      cb[a][c2][2] = g.ct_off[1] + ((int)((ty >> 8) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+      cb[a][c2][3] = g.ct_off[1] + ((int)((ty >> 16) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+      zxy[a][c2] = sx * g.ct_s2[2] + sy;
+      inb[a][c2] = (ic > 0 ? 1u : 0u) | (ic < g.nx - 1 ? 2u : 0u) | (jc > 0 ? 4u : 0u) |
+                   (jc < g.ny - 1 ? 8u : 0u);
+    }
   }
-  // the column updated on plane k (the colour of node (i, j, k) is the parity of
-  // i + j + k, and i0 + 2u is even); the other one holds the neighbour value
-  auto ucol = [&](int k) { return (j + k + color) & 1; };
+  // the column of pair a updated on plane k (the colour of node (i, j, k) is the parity
+  // of i + j + k, and i0 + 2u is even); the other one holds the neighbour value
+  auto ucol = [&](int a, int k) { return (j[a] + k + color) & 1; };
   // halo cell of this thread (rows j0-1, j0+zr and columns i0-1, i0+zc of the tile)
   int hm, hslot;
   bool hv;
@@ -895,31 +902,38 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     rowr2[q] = FLEX ? (size_t)b * rhs2_ld : 0;
   }
   struct Raw {
+    TY v[NP][QPB];
+  };
+  struct Halo {
     TY v[QPB];
   };
   struct Rhs {
-    double r[QPB], r2[QPB];
+    double r[NP][QPB], r2[NP][QPB];
   };
-  // neighbour value of this thread's column pair on plane k
+  // neighbour values of this thread's column pairs on plane k
   auto load_raw = [&](Raw& t, int k) {
-    const int c2 = 1 - ucol(k);
-    const int pos = spos(k * P + (c2 ? m_[1] : m_[0]));
 #pragma unroll
-    for (int q = 0; q < QPB; ++q) t.v[q] = y[rowy[q] + pos];
+    for (int a = 0; a < NP; ++a) {
+      const int pos = spos(k * P + (ucol(a, k) ? m_[a][0] : m_[a][1]));
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) t.v[a][q] = y[rowy[q] + pos];
+    }
   };
-  auto load_halo = [&](Raw& t, int k) {
+  auto load_halo = [&](Halo& t, int k) {
     const int pos = spos(k * P + hm);
 #pragma unroll
     for (int q = 0; q < QPB; ++q) t.v[q] = y[rowy[q] + pos];
   };
-  // right-hand side(s) at the node updated on plane k
+  // right-hand side(s) at the nodes updated on plane k
   auto load_rhs = [&](Rhs& t, int k) {
-    const int c2 = ucol(k);
-    const int pos = spos(k * P + (c2 ? m_[1] : m_[0]));
 #pragma unroll
-    for (int q = 0; q < QPB; ++q) {
-      t.r[q] = rhs[rowr[q] + pos];
-      if (FLEX) t.r2[q] = rhs2[rowr2[q] + pos];
+    for (int a = 0; a < NP; ++a) {
+      const int pos = spos(k * P + (ucol(a, k) ? m_[a][1] : m_[a][0]));
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) {
+        t.r[a][q] = rhs[rowr[q] + pos];
+        if (FLEX) t.r2[a][q] = rhs2[rowr2[q] + pos];
+      }
     }
   };
 
@@ -932,21 +946,12 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   }
 
   // neighbour values of planes k-1, k, k+1; plane k+2 in R0, later planes in flight
-  TY vb[QPB], vc[QPB], vn[QPB];
-  Raw R0, R1, H0, H1;
+  Raw vb, vc, vn, R0, R1;
+  Halo H0, H1;
   Rhs X0, X1;
-  {
-    Raw t;
-    load_raw(t, max(k0 - 1, 0));
-#pragma unroll
-    for (int q = 0; q < QPB; ++q) vb[q] = t.v[q];
-    load_raw(t, k0);
-#pragma unroll
-    for (int q = 0; q < QPB; ++q) vc[q] = t.v[q];
-    load_raw(t, min(k0 + 1, klast));
-#pragma unroll
-    for (int q = 0; q < QPB; ++q) vn[q] = t.v[q];
-  }
+  load_raw(vb, max(k0 - 1, 0));
+  load_raw(vc, k0);
+  load_raw(vn, min(k0 + 1, klast));
   load_raw(R0, min(k0 + 2, klast));
   load_halo(H0, k0);
   load_rhs(X0, k0);
@@ -955,40 +960,46 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
 #pragma unroll
   for (int q = 0; q < QPB; ++q) a0[q] = a1[q] = 0.0;
 
-  auto step = [&](int k, Raw& Rk2, Raw& Rk3, Raw& Hk, Raw& Hn, Rhs& Xk, Rhs& Xn) {
+  auto step = [&](int k, Raw& Rk2, Raw& Rk3, Halo& Hk, Halo& Hn, Rhs& Xk, Rhs& Xn) {
     load_raw(Rk3, min(k + 3, klast));
     load_halo(Hn, min(k + 1, klast));
     load_rhs(Xn, min(k + 1, klast));
     __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
-    const int cu = ucol(k);
-    const bool own_s = cu ? own[0] : own[1];
-    const int slot_s = cu ? slot[0] : slot[1];
-    if (own_s)
 #pragma unroll
-      for (int q = 0; q < QPB; ++q) pl[q * plane + slot_s] = vc[q];
+    for (int a = 0; a < NP; ++a) {
+      const int cu = ucol(a, k);
+      if (cu ? own[a][0] : own[a][1]) {
+        const int ss = cu ? slot[a][0] : slot[a][1];
+#pragma unroll
+        for (int q = 0; q < QPB; ++q) pl[q * plane + ss] = vc.v[a][q];
+      }
+    }
     if (hv)
 #pragma unroll
       for (int q = 0; q < QPB; ++q) pl[q * plane + hslot] = Hk.v[q];
     __syncthreads();
-    const bool own_u = cu ? own[1] : own[0];
-    if (own_u) {
-      const int sz = zinfo[3 * (k - k0)];
-      const int zlo = zinfo[3 * (k - k0) + 1];
-      const int zhi = zinfo[3 * (k - k0) + 2];
-      const unsigned zb = (k > 0 ? 16u : 0u) | (k < klast ? 32u : 0u);
-      const int pos = spos(k * P + (cu ? m_[1] : m_[0]));
-      const unsigned inner = (cu ? inb[1] : inb[0]) | zb;
-      const int su = cu ? slot[1] : slot[0];
-      const int zx = cu ? zxy[1] : zxy[0];
-      const int ci[6] = {(cu ? cb[1][0] : cb[0][0]) + sz, (cu ? cb[1][1] : cb[0][1]) + sz,
-                         (cu ? cb[1][2] : cb[0][2]) + sz, (cu ? cb[1][3] : cb[0][3]) + sz,
-                         zlo + zx, zhi + zx};
+    const int sz = zinfo[3 * (k - k0)];
+    const int zlo = zinfo[3 * (k - k0) + 1];
+    const int zhi = zinfo[3 * (k - k0) + 2];
+    const unsigned zb = (k > 0 ? 16u : 0u) | (k < klast ? 32u : 0u);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      const int cu = ucol(a, k);
+      if (!(cu ? own[a][1] : own[a][0])) continue;
+      const int pos = spos(k * P + (cu ? m_[a][1] : m_[a][0]));
+      const unsigned inner = (cu ? inb[a][1] : inb[a][0]) | zb;
+      const int su = cu ? slot[a][1] : slot[a][0];
+      const int zx = cu ? zxy[a][1] : zxy[a][0];
+      const int ci[6] = {(cu ? cb[a][1][0] : cb[a][0][0]) + sz,
+                         (cu ? cb[a][1][1] : cb[a][0][1]) + sz,
+                         (cu ? cb[a][1][2] : cb[a][0][2]) + sz,
+                         (cu ? cb[a][1][3] : cb[a][0][3]) + sz, zlo + zx, zhi + zx};
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
         if (!live(q)) continue;
         const TY* cf = cfs + q * g.ct_size;
         const TY* lp = pl + q * plane + su;
-        const TY nv[6] = {lp[-1], lp[1], lp[-W2], lp[W2], vb[q], vn[q]};
+        const TY nv[6] = {lp[-1], lp[1], lp[-W2], lp[W2], vb.v[a][q], vn.v[a][q]};
         TY d = TY(0), off = TY(0);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
@@ -996,19 +1007,16 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
           d += c;
           off += c * (((inner >> f) & 1u) ? nv[f] : TY(0));
         }
-        const double fp = fsc[q] * Xk.r[q];
+        const double fp = fsc[q] * Xk.r[a][q];
         const TY v = (TY)(((TY)fp + off) / d);
         y[(size_t)(q0 + q) * y_ld + pos] = v;
         a0[q] += (double)v * fp;
-        if (FLEX) a1[q] += (double)v * Xk.r2[q];
+        if (FLEX) a1[q] += (double)v * Xk.r2[a][q];
       }
     }
-#pragma unroll
-    for (int q = 0; q < QPB; ++q) {
-      vb[q] = vc[q];
-      vc[q] = vn[q];
-      vn[q] = Rk2.v[q];
-    }
+    vb = vc;
+    vc = vn;
+    vn = Rk2;
   };
   for (int k = k0; k < k1; k += 2) {
     step(k, R0, R1, H0, H1, X0, X1);
@@ -1303,7 +1311,7 @@ static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
   if (g.dim != 3) return false;
   zt.zc = std::min(g.nx + 1, 128);  // nx is odd: the last column of the last tile is outside
   const int pairs = zt.zc / 2;
-  zt.zr = std::min(g.ny, kZThreads / pairs);
+  zt.zr = std::min(g.ny, kGsPairs * (kZThreads / pairs));
   if (zt.zr < 1 || 2 * (zt.zc + zt.zr) > kZThreads) return false;
   zt.ct = (g.nx + zt.zc - 1) / zt.zc;
   zt.rt = (g.ny + zt.zr - 1) / zt.zr;
@@ -1317,10 +1325,10 @@ static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
 }
 
 // kind: 1 chunked, 2 marching, 0 default: chunked.  Measured on the 127^3 workload
-// (B = 256, FP32): a sweep takes 1.03 ms chunked with 4 queries per block and 1.05-1.09 ms
-// marching with 1-4: a sweep moves only 8 B per node, so the two barriers per plane weigh
-// more than in pass B.  The autotuner tries both.  Returns the number of partial sums per
-// query (0: not run).
+// (B = 256, FP32): a sweep takes 1.03 ms chunked with 4 queries per block and 1.03-1.08 ms
+// marching with 2, 1 or 4 (1.05-1.09 ms with one column pair per thread): a sweep moves
+// only 8 B per node per barrier pair of each plane, against pass B's 40.  The autotuner
+// tries both.  Returns the number of partial sums per query (0: not run).
 template <typename TY>
 static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, const double* coef,
                             TY* y, int64_t y_ld, const double* rhs, int64_t rhs_ld,
