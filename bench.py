@@ -6,7 +6,8 @@ Workload (synthetic, seeded): 3D 7-point diffusion on a 127^3 interior grid
 (P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, residual
 indicator) over 256 training parameters; 256 test parameters per call.  A step is
 one rb_solve_batch of the 256 queries to relative residual 1e-10 (RBCG of Alg. 3,
-FP32 preconditioner, FP64 CG).  value = converged mu-solves per second.
+FP32 preconditioner, FP64 CG, iterations replayed from a captured HIP graph).  value =
+converged mu-solves per second.
 
 Also reported: the plain path (same library, FP64 everywhere, one query per call),
 the roofline of the dominant kernel (pass B of the iteration: x += alpha p,
@@ -90,7 +91,8 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--B", type=int, default=0, help="queries per call (default: workload's)")
     ap.add_argument("--flexible", type=int, default=0)
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="replay the iterations as a captured HIP graph (two per launch)")
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--greedy", default="residual", choices=["l1", "residual"])
