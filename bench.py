@@ -86,8 +86,8 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d127")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--B", type=int, default=0, help="queries per call (default: workload's)")
@@ -458,6 +458,19 @@ def cpu_baseline(basis, w, thetas):
         ok += int(res.converged and res.rel_res_true <= 1e-10)
     el = time.perf_counter() - t
     log(f"cpu baseline: {len(thetas)} solves in {el:.1f}s, iters {its}")
+    # the same oracle on one core (BLAS limited to one thread), first query only
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            r1 = orb.solve_rbcg(op, thetas[0], W, AN, rtol=1e-10)
+            el1 = time.perf_counter() - t1
+        ok1 = int(r1.converged and r1.rel_res_true <= 1e-10)
+        one = {"value": round(ok1 / el1, 5), "cores": 1, "sample": "the first test query"}
+        log(f"cpu baseline, one core: 1 solve in {el1:.1f}s")
+    except ImportError:
+        pass
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -472,7 +485,7 @@ def cpu_baseline(basis, w, thetas):
             "sample": f"the first {len(thetas)} test queries of the same workload and basis "
                       "(operator setup excluded; reduced assembly, Cholesky, RBCG iterations "
                       "and true residual timed)",
-            "iters": its}
+            "iters": its, "one_core": one}
 
 
 if __name__ == "__main__":
