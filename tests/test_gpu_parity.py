@@ -354,6 +354,32 @@ def test_rbi_parity(lib, ctx, smoother):
         assert _rel(x[b], xr) <= 1e-10
 
 
+@pytest.mark.parametrize("smoother", ["rbgs", "rbgs_sym"])
+def test_rbi_marching_sweep(lib, ctx, smoother):
+    """RBI smooths A x = phi f from one shared row f scaled per query: the marching colour
+    sweep gives exactly the chunked sweep's iterates (the same update per node, and RBI
+    takes no partial sums from its sweeps), and phi times the oracle's unscaled iterates
+    (every step is linear in the right-hand side)."""
+    dims, blocks = (15, 13, 11), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 4, seed=43)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(44, 5, op.Q, 0.1, 10.0)
+    phi = np.linspace(0.5, 2.0, 5)
+    m = 8
+    xm, _ = lib.solve_batch(ctx, prob, basis, theta, phi=phi, solver="rbi", fixed_iters=m,
+                            smoother=smoother, stencil="zmarch")
+    xc, _ = lib.solve_batch(ctx, prob, basis, theta, phi=phi, solver="rbi", fixed_iters=m,
+                            smoother=smoother, stencil="chunked")
+    xm, xc = xm.cpu().numpy(), xc.cpu().numpy()
+    assert np.array_equal(xm, xc)
+    for b in range(5):
+        xr, k, _ = orb.solve_rbi(op, theta[b], W, AN, m=m, rtol=0.0, smoother_kind=smoother)
+        assert _rel(xm[b], phi[b] * xr) <= 1e-10
+
+
 def test_rbi_converges(lib, ctx):
     dims, blocks = (31, 31), (2, 2)
     op = BlockDiffusion(dims, blocks)
