@@ -63,19 +63,20 @@ struct ProjFrag {
   TW w[JT][4];
 };
 
+// row[t] / ok[t]: the residual row of this lane in query tile t and whether it is loaded
+// (PADDED: always; rows are valid addresses either way).
 template <typename TW, int QT, int JT, bool PADDED>
 __device__ __forceinline__ void proj_load(const double* __restrict__ R, int64_t r_ld,
                                           const TW* __restrict__ W, int64_t w_ld, int n,
-                                          int q_base, int B, const int* __restrict__ active,
-                                          int k0, ProjFrag<TW, QT, JT>& f) {
+                                          const int (&row)[QT], const bool (&ok)[QT], int k0,
+                                          ProjFrag<TW, QT, JT>& f) {
   const int lane = threadIdx.x & 63;
   const int qi = lane & 15, kg = lane >> 4;
   const int kk = k0 + 4 * kg;
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
-    const int q = q_base + 16 * t + qi;
-    if (PADDED || (q < B && active[q])) {
-      const double2* src = reinterpret_cast<const double2*>(R + (size_t)q * r_ld + kk);
+    if (PADDED || ok[t]) {
+      const double2* src = reinterpret_cast<const double2*>(R + (size_t)row[t] * r_ld + kk);
       const double2 v0 = src[0], v1 = src[1];
       f.a[t][0] = v0.x; f.a[t][1] = v0.y; f.a[t][2] = v1.x; f.a[t][3] = v1.y;
     } else {
@@ -147,11 +148,15 @@ __device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT>& f,
 // WSPLIT = true: the block's 4 waves split the DOF range of one query tile and are
 // reduced through LDS (small batches).  WSPLIT = false: the 4 waves own 4 query tiles
 // over the same DOF range (large batches).
+// qlist (batched path only, nullable): the active queries in increasing order, their
+// count in qlist[B]; the wave tiles then run over that list (tiles past the count exit)
+// and partial sums still go to the query's own row.
 template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED>
 __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, int64_t r_ld,
                                                  const TW* __restrict__ W, int64_t w_ld, int n,
                                                  int B, int kend, int steps,
                                                  const int* __restrict__ active,
+                                                 const int* __restrict__ qlist,
                                                  typename ProjTraits<TW>::Acc* __restrict__ part) {
   using Acc = typename ProjTraits<TW>::Acc;
   using Vec = typename ProjTraits<TW>::Vec;
@@ -169,6 +174,22 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
   }
   k_stop = k_begin + steps * 16;
   if (k_stop > kend) k_stop = kend;
+  // this lane's residual rows (no barriers in the batched path: a wave may leave alone)
+  const int cnt = (!WSPLIT && qlist) ? qlist[B] : B;
+  if (!WSPLIT && qlist && q_base >= cnt) return;
+  int row[QT];
+  bool ok[QT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    const int c = q_base + 16 * t + (lane & 15);
+    if (!WSPLIT && qlist) {
+      row[t] = qlist[min(c, cnt - 1)];
+      ok[t] = c < cnt;
+    } else {
+      row[t] = c;
+      ok[t] = c < B && active[c];
+    }
+  }
   Vec acc[QT][JT];
 #pragma unroll
   for (int t = 0; t < QT; ++t)
@@ -179,14 +200,12 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
   if (k_begin < k_stop) {
     const int klast = k_stop - 16;
     ProjFrag<TW, QT, JT> f0, f1;
-    proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active, k_begin, f0);
+    proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, row, ok, k_begin, f0);
     for (int k0 = k_begin; k0 < k_stop; k0 += 32) {
-      proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active,
-                                    min(k0 + 16, klast), f1);
+      proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, row, ok, min(k0 + 16, klast), f1);
       proj_mma<TW, QT, JT>(f0, acc);
       if (k0 + 16 < k_stop) {
-        proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, q_base, B, active,
-                                      min(k0 + 32, klast), f0);
+        proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, row, ok, min(k0 + 32, klast), f0);
         proj_mma<TW, QT, JT>(f1, acc);
       }
     }
@@ -200,9 +219,9 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
       for (int u = 0; u < JT; ++u)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int q = q_base + 16 * t + acc_row<TW>(kg, i);
+          const int c = q_base + 16 * t + acc_row<TW>(kg, i);
           const int j = 16 * u + qi;
-          if (q < B) part[((size_t)chunk * B + q) * NJ + j] = acc[t][u][i];
+          if (c < cnt) part[((size_t)chunk * B + (qlist ? qlist[c] : c)) * NJ + j] = acc[t][u][i];
         }
   } else {
     __shared__ Acc sh[4][QW][NJ];
@@ -258,57 +277,57 @@ ProjPlan plan_projection(int N, int B, int n, int target_blocks) {
 
 template <typename TW, int QT, int JT>
 static void launch_proj_t(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
-                          int64_t w_ld, int n, int B, const int* active, void* part,
-                          hipStream_t s) {
+                          int64_t w_ld, int n, int B, const int* active, const int* qlist,
+                          void* part, hipStream_t s) {
   using Acc = typename ProjTraits<TW>::Acc;
   const dim3 grid(pl.chunks, pl.qgroups);
   if (pl.wsplit)
     hipLaunchKernelGGL((k_project<TW, QT, JT, true, false>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
+                       w_ld, n, B, pl.kend, pl.steps, active, nullptr, (Acc*)part);
   else if (pl.padded)
     hipLaunchKernelGGL((k_project<TW, QT, JT, false, true>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
+                       w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
   else
     hipLaunchKernelGGL((k_project<TW, QT, JT, false, false>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, (Acc*)part);
+                       w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
 }
 
 template <typename TW, int QT>
 static void launch_proj_q(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
-                          int64_t w_ld, int n, int B, const int* active, void* part,
-                          hipStream_t s) {
+                          int64_t w_ld, int n, int B, const int* active, const int* ql,
+                          void* part, hipStream_t s) {
   switch (pl.jt) {
-    case 1: launch_proj_t<TW, QT, 1>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
-    case 2: launch_proj_t<TW, QT, 2>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
-    case 3: launch_proj_t<TW, QT, 3>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
-    case 4: launch_proj_t<TW, QT, 4>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
-    default: launch_proj_t<TW, QT, 5>(pl, R, r_ld, W, w_ld, n, B, active, part, s); break;
+    case 1: launch_proj_t<TW, QT, 1>(pl, R, r_ld, W, w_ld, n, B, active, ql, part, s); break;
+    case 2: launch_proj_t<TW, QT, 2>(pl, R, r_ld, W, w_ld, n, B, active, ql, part, s); break;
+    case 3: launch_proj_t<TW, QT, 3>(pl, R, r_ld, W, w_ld, n, B, active, ql, part, s); break;
+    case 4: launch_proj_t<TW, QT, 4>(pl, R, r_ld, W, w_ld, n, B, active, ql, part, s); break;
+    default: launch_proj_t<TW, QT, 5>(pl, R, r_ld, W, w_ld, n, B, active, ql, part, s); break;
   }
 }
 
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
                        const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
-                       hipStream_t s) {
+                       hipStream_t s, const int* qlist) {
   if (prec == RB_PREC_FP64) {
     const double* w = (const double*)W;
     switch (pl.qt) {
-      case 1: launch_proj_q<double, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      case 2: launch_proj_q<double, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      default: launch_proj_q<double, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 1: launch_proj_q<double, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      case 2: launch_proj_q<double, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      default: launch_proj_q<double, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
     }
   } else if (prec == RB_PREC_FP32) {
     const float* w = (const float*)W;
     switch (pl.qt) {
-      case 1: launch_proj_q<float, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      case 2: launch_proj_q<float, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      default: launch_proj_q<float, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 1: launch_proj_q<float, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      case 2: launch_proj_q<float, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      default: launch_proj_q<float, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
     }
   } else {
     const uint16_t* w = (const uint16_t*)W;
     switch (pl.qt) {
-      case 1: launch_proj_q<uint16_t, 1>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      case 2: launch_proj_q<uint16_t, 2>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
-      default: launch_proj_q<uint16_t, 4>(pl, R, r_ld, w, w_ld, n, B, active, part, s); break;
+      case 1: launch_proj_q<uint16_t, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      case 2: launch_proj_q<uint16_t, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
+      default: launch_proj_q<uint16_t, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
     }
   }
 }
@@ -361,9 +380,12 @@ __global__ __launch_bounds__(256) void k_prolong(const TW* __restrict__ W, int64
 // 4(l/16)+i (queries) of column l%16 (node).  Blocks are remapped so that the query
 // groups of one node run sit on one XCD (their W tile is fetched once).
 template <typename TW, typename TO, int TP, bool ADD>
+// qlist (nullable): the active queries in increasing order, their count in qlist[B]; the
+// query groups then run over that list (groups past the count exit).
 __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, int64_t w_ld, int n,
                                                       const float* __restrict__ e, int e_ld, int B,
                                                       const int* __restrict__ active,
+                                                      const int* __restrict__ qlist,
                                                       TO* __restrict__ out, int64_t o_ld, int lo,
                                                       int hi, int qgroups) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -373,9 +395,14 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
   const int id = xcd < rd ? xcd * (qd + 1) + slot : rd * (qd + 1) + (xcd - rd) * qd + slot;
   const int run = id / qgroups, qg = id % qgroups;
+  const int cnt = qlist ? qlist[B] : B;
+  if (qg * 64 >= cnt) return;  // no barriers in this kernel
   const int pos0 = lo + run * 16 * TP;
   const int q0 = (qg * 4 + wave) * 16;
   const int r = lane & 15, g = lane >> 4;
+  // e row of this lane: its query (through the list; past the count any valid row, whose
+  // results are not stored)
+  const int erow = qlist ? qlist[min(q0 + r, cnt - 1)] : q0 + r;
   floatx4 acc[TP];
 #pragma unroll
   for (int p = 0; p < TP; ++p) acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -384,7 +411,7 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   // so every address is inside its buffer; columns pos >= hi are not stored.
   for (int j0 = 0; j0 < n; j0 += 4) {
     const int j = j0 + g;
-    const float ev = e[(size_t)(q0 + r) * e_ld + j];
+    const float ev = e[(size_t)erow * e_ld + j];
     const TW* wr = W + (size_t)j * w_ld + pos0 + r;
 #pragma unroll
     for (int p = 0; p < TP; ++p) {
@@ -398,8 +425,10 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int q = q0 + 4 * g + i;
-    if (q >= B || !active[q]) continue;
+    const int c = q0 + 4 * g + i;
+    if (c >= cnt) continue;
+    const int q = qlist ? qlist[c] : c;
+    if (!qlist && !active[q]) continue;
     TO* o = out + (size_t)q * o_ld + pos0 + r;
 #pragma unroll
     for (int p = 0; p < TP; ++p) {
@@ -415,13 +444,13 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
 
 template <typename TW, typename TO, bool ADD>
 static void launch_prolong_mfma(const TW* W, int64_t w_ld, int n, const float* e, int e_ld, int B,
-                                const int* active, TO* out, int64_t o_ld, int lo, int hi,
-                                hipStream_t s) {
+                                const int* active, const int* qlist, TO* out, int64_t o_ld,
+                                int lo, int hi, hipStream_t s) {
   constexpr int TP = 16;
   const int runs = (hi - lo + 16 * TP - 1) / (16 * TP);
   const int qgroups = (B + 63) / 64;
   hipLaunchKernelGGL((k_prolong_mfma<TW, TO, TP, ADD>), dim3(runs * qgroups), dim3(256), 0, s, W,
-                     w_ld, n, e, e_ld, B, active, out, o_ld, lo, hi, qgroups);
+                     w_ld, n, e, e_ld, B, active, qlist, out, o_ld, lo, hi, qgroups);
 }
 
 template <typename TW, typename TA, typename TO, bool ADD>
@@ -436,7 +465,8 @@ static void launch_prolong_t(const TW* W, int64_t w_ld, int n, const TA* e, int 
 
 void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const double* e64,
                     const float* e32, int e_ld, int B, const int* active, void* out,
-                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s) {
+                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s,
+                    const int* qlist) {
   if (hi <= lo || n == 0) return;
   if (prec == RB_PREC_FP64) {
     RB_REQUIRE(out_is_double, RB_EINVAL, "FP64 prolongation needs a double output");
@@ -449,21 +479,21 @@ void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const doub
     return;
   }
   if (B >= 16) {
-#define PM(TW)                                                                                   \
-  if (out_is_double) {                                                                           \
-    if (add)                                                                                     \
-      launch_prolong_mfma<TW, double, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,         \
-                                            (double*)out, o_ld, lo, hi, s);                      \
-    else                                                                                         \
-      launch_prolong_mfma<TW, double, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,        \
-                                             (double*)out, o_ld, lo, hi, s);                     \
-  } else {                                                                                       \
-    if (add)                                                                                     \
-      launch_prolong_mfma<TW, float, true>((const TW*)W, w_ld, n, e32, e_ld, B, active,          \
-                                           (float*)out, o_ld, lo, hi, s);                        \
-    else                                                                                         \
-      launch_prolong_mfma<TW, float, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,         \
-                                            (float*)out, o_ld, lo, hi, s);                       \
+#define PM(TW)                                                                                    \
+  if (out_is_double) {                                                                            \
+    if (add)                                                                                      \
+      launch_prolong_mfma<TW, double, true>((const TW*)W, w_ld, n, e32, e_ld, B, active, qlist,   \
+                                            (double*)out, o_ld, lo, hi, s);                       \
+    else                                                                                          \
+      launch_prolong_mfma<TW, double, false>((const TW*)W, w_ld, n, e32, e_ld, B, active,         \
+                                             qlist, (double*)out, o_ld, lo, hi, s);               \
+  } else {                                                                                        \
+    if (add)                                                                                      \
+      launch_prolong_mfma<TW, float, true>((const TW*)W, w_ld, n, e32, e_ld, B, active, qlist,    \
+                                           (float*)out, o_ld, lo, hi, s);                         \
+    else                                                                                          \
+      launch_prolong_mfma<TW, float, false>((const TW*)W, w_ld, n, e32, e_ld, B, active, qlist,   \
+                                            (float*)out, o_ld, lo, hi, s);                        \
   }
     if (prec == RB_PREC_FP32) {
       PM(float)
@@ -805,6 +835,41 @@ void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, in
   else
     hipLaunchKernelGGL(k_reduce_solve<float>, dim3(B), dim3(256), 0, s, (const float*)part,
                        chunks, B, nj, n, n_use, L, active, t_out, e64, e32, e_ld, solve ? 1 : 0);
+}
+
+// ---- active-query list ---------------------------------------------------------------
+// qlist[0..cnt) = the b < B with active[b] != 0, in increasing order; qlist[B] = cnt.  One
+// block scans the flags 1024 at a time (wave scans with shuffles, then the wave totals).
+__global__ __launch_bounds__(1024) void k_compact_active(const int* __restrict__ active, int B,
+                                                         int* __restrict__ qlist) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < B; c0 += 1024) {
+    const int b = c0 + (int)threadIdx.x;
+    const int f = (b < B && active[b]) ? 1 : 0;
+    int incl = f;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int off = base;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    if (f) qlist[off + incl - 1] = b;
+    __syncthreads();  // every thread has read base
+    if (threadIdx.x == 1023) base = off + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) qlist[B] = base;
+}
+
+void launch_compact_active(const int* active, int B, int* qlist, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_active, dim3(1), dim3(1024), 0, s, active, B, qlist);
 }
 
 // ---- CG scalars (Alg. 3) ----------------------------------------------------------------

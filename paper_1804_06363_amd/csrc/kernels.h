@@ -119,14 +119,20 @@ void csr_from_storage(int N, const int* perm, int B, const double* sto, int64_t 
 
 // dense.hip
 ProjPlan plan_projection(int N, int B, int n, int target_blocks);
+// qlist (nullable; the batched path only): active queries in increasing order with their
+// count in qlist[B] (launch_compact_active); rows of other queries are then not read.
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
                        const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
-                       hipStream_t s);
+                       hipStream_t s, const int* qlist = nullptr);
 // MFMA path (FP32/BF16, B >= 16): e must have round_up(B, 64) rows, zero beyond B, and
 // W basis_rows(n) rows plus kBasisTail elements, zero beyond n.
+// qlist as for launch_projection (MFMA path only)
 void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const double* e64,
                     const float* e32, int e_ld, int B, const int* active, void* out,
-                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s);
+                    bool out_is_double, int64_t o_ld, int lo, int hi, bool add, hipStream_t s,
+                    const int* qlist = nullptr);
+// qlist[B + 1]: the indices of the active queries in increasing order, then their count
+void launch_compact_active(const int* active, int B, int* qlist, hipStream_t s);
 void launch_cholesky(const double* AN, int n, int Q, int B, const double* theta, const int* n_use,
                      double* L, int* status, hipStream_t s);
 void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, int nj, int n,

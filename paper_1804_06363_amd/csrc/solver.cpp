@@ -144,6 +144,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     e32 = get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
     launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
     launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
+    qlist = get_ws(WS_QLIST, sizeof(int) * ((size_t)B + 1));
   }
 
   // per-query scalars
@@ -206,9 +207,16 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   // sweep overwrites every red node and reads only black ones)
   void* zdst = full ? z.p : y.p;
   if (n > 0) {
+    // batched path: the projection and the prolongation visit the active queries only
+    const int* ql = nullptr;
+    if (!plan.wsplit) {
+      launch_compact_active(q.active, B, qlist.as<int>(), st);
+      ql = qlist.as<int>();
+    }
     {
       ProfScope ps(ctx, "project", st);
-      launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st);
+      launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st,
+                        ql);
     }
     {
       ProfScope ps(ctx, "reduced_solve", st);
@@ -218,7 +226,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     }
     ProfScope ps(ctx, "prolong", st);
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
-                   q.active, zdst, !y32, L_, full ? 0 : g.coff[1], g.N, false, st);
+                   q.active, zdst, !y32, L_, full ? 0 : g.coff[1], g.N, false, st, ql);
   } else {
     const int lo = full ? 0 : g.coff[1];
     if (y32)

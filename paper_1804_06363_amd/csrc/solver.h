@@ -32,6 +32,7 @@ struct BatchSolver {
 
   // device buffers (views of the context's workspace)
   Buf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
+  Buf qlist;  // active queries in increasing order, then their count (batched coarse step)
   Buf x, r0, r1, p0, p1, y, z;
   Buf part_m, part_m2, part_r0, part_r1;
   Buf qbuf;  // QState arrays
