@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--greedy", default="residual", choices=["l1", "residual"])
     ap.add_argument("--uneven", type=int, default=0,
                     help="also time the uneven batch (1024 queries over four grids)")
+    ap.add_argument("--uneven-only", type=int, default=0,
+                    help="time only the uneven batch and print its record (for profiling)")
     ap.add_argument("--learned", type=int, default=0,
                     help="also compare the surrogate-ranked greedy with the plain greedy")
     ap.add_argument("--basis", default="",
@@ -119,6 +121,10 @@ def main():
     import torch
     from paper_1804_06363_amd import rb
     from workloads import WORKLOADS
+
+    if args.uneven_only:
+        print(json.dumps({"uneven_batch": uneven_leg(rb, torch)}), flush=True)
+        return
 
     if args.copy_calib > 0:
         # a plain copy of known size: the profiler's byte counters are scaled by what
