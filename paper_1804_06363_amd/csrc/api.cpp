@@ -283,7 +283,6 @@ rb_status rb_problem_create_stencil(rb_ctx* ctx, const rb_stencil_desc* d, rb_pr
     RB_REQUIRE(g.ct_size <= 1024, RB_EUNSUPPORTED, "too many kappa blocks for the stencil tables");
     // default right-hand side f = 1
     p->R = 1;
-    p->f_host.assign((size_t)N, 1.0);
     p->f.alloc(sizeof(double) * p->ld);
     launch_fill<double>(p->f.as<double>(), 0, N, 1, 1.0, ctx->stream);
     RB_HIP(hipStreamSynchronize(ctx->stream));
@@ -429,7 +428,6 @@ rb_status rb_problem_create_csr(rb_ctx* ctx, int64_t N, int Q, const int64_t* ro
     g.diag = p->diag.as<double>();
     g.ct_size = (Q + 7) / 8 * 8;
     p->R = 1;
-    p->f_host.assign((size_t)N, 1.0);
     p->f.alloc(sizeof(double) * p->ld);
     launch_fill<double>(p->f.as<double>(), 0, N, 1, 1.0, ctx->stream);
     RB_HIP(hipStreamSynchronize(ctx->stream));
@@ -461,7 +459,6 @@ rb_status rb_problem_set_rhs(rb_problem* p, int R, const double* f) {
     launch_to_storage(*p, R, nat.as<double>(), p->N, sto.as<double>(), p->ld, p->ctx->stream);
     RB_HIP(hipStreamSynchronize(p->ctx->stream));
     p->f = std::move(sto);
-    p->f_host.assign(f, f + (size_t)R * p->N);
     p->R = R;
   });
 }

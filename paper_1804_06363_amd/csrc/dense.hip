@@ -837,6 +837,27 @@ void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, in
                        chunks, B, nj, n, n_use, L, active, t_out, e64, e32, e_ld, solve ? 1 : 0);
 }
 
+// ---- right-hand sides of affine f (eq. 12) ----------------------------------------------
+// out[b][pos] = sum_r phi[b][r] f[r][pos] for pos < N, 0 on the padding up to ld.
+__global__ void k_combine_rhs(const double* __restrict__ f, int64_t ld, int R,
+                              const double* __restrict__ phi, int N, double* __restrict__ out) {
+  const int b = blockIdx.y;
+  const double* ph = phi + (size_t)b * R;
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < ld;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (pos < N)
+      for (int r = 0; r < R; ++r) v += ph[r] * f[(size_t)r * ld + pos];
+    out[(size_t)b * ld + pos] = v;
+  }
+}
+
+void launch_combine_rhs(const double* f, int64_t ld, int R, const double* phi, int B, int N,
+                        double* out, hipStream_t s) {
+  const int bx = (int)std::min<int64_t>((ld + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_combine_rhs, dim3(bx, B), dim3(256), 0, s, f, ld, R, phi, N, out);
+}
+
 // ---- active-query list ---------------------------------------------------------------
 // qlist[0..cnt) = the b < B with active[b] != 0, in increasing order; qlist[B] = cnt.  One
 // block scans the flags 1024 at a time (wave scans with shuffles, then the wave totals).

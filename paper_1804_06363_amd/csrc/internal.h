@@ -142,7 +142,8 @@ TuneConfig stencil_tiles();
 
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
-  WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_QLIST, WS_COUNT
+  WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_QLIST, WS_FB, WS_PHI,
+  WS_COUNT
 };
 }  // namespace rb
 
@@ -216,7 +217,6 @@ struct rb_problem {
     return pos < g.NR ? 2 * pos : 2 * (pos - g.NR) + 1;
   }
   rb::DevBuf f;          // double [R][ld], storage (red-black) order
-  std::vector<double> f_host;  // [R][N] natural order
 };
 
 struct rb_basis {

@@ -133,6 +133,10 @@ void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const doub
                     const int* qlist = nullptr);
 // qlist[B + 1]: the indices of the active queries in increasing order, then their count
 void launch_compact_active(const int* active, int B, int* qlist, hipStream_t s);
+// out[b] = sum_r phi[b][r] f_r over the R right-hand-side terms f (rows of ld, storage
+// order); B rows of ld, zero beyond N
+void launch_combine_rhs(const double* f, int64_t ld, int R, const double* phi, int B, int N,
+                        double* out, hipStream_t s);
 void launch_cholesky(const double* AN, int n, int Q, int B, const double* theta, const int* n_use,
                      double* L, int* status, hipStream_t s);
 void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, int nj, int n,

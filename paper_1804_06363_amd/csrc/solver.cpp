@@ -67,22 +67,15 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     f_base = prob->f.as<double>();
     f_ld = 0;
   } else {
-    // f_b = sum_r phi_br f_r, formed on the host once (R small) and uploaded
-    fb.alloc(sizeof(double) * B * L_);
-    std::vector<double> tmp((size_t)B * L_, 0.0);
-    // storage order of f_r is kept on the device; build from the host copy
-    std::vector<double> sto((size_t)g.N);
-    for (int i = 0; i < B; ++i) {
-      for (int pos = 0; pos < g.N; ++pos) {
-        const int Lx = prob->nat_index(pos);
-        double v = 0.0;
-        for (int r = 0; r < R; ++r)
-          v += (phi ? phi[(size_t)i * R + r] : 1.0) * prob->f_host[(size_t)r * g.N + Lx];
-        tmp[(size_t)i * L_ + pos] = v;
-      }
-    }
-    RB_HIP(hipMemcpyAsync(fb.p, tmp.data(), sizeof(double) * B * L_, hipMemcpyHostToDevice, st));
-    RB_HIP(hipStreamSynchronize(st));
+    // f_b = sum_r phi_br f_r, formed on the device from the terms in storage order
+    std::vector<double> ph((size_t)B * R, 1.0);
+    if (phi) std::copy(phi, phi + (size_t)B * R, ph.begin());
+    phi_d = get_ws(WS_PHI, sizeof(double) * (size_t)B * R);
+    RB_HIP(hipMemcpyAsync(phi_d.p, ph.data(), sizeof(double) * (size_t)B * R,
+                          hipMemcpyHostToDevice, st));
+    fb = get_ws(WS_FB, sizeof(double) * (size_t)B * L_);
+    launch_combine_rhs(prob->f.as<double>(), L_, R, phi_d.as<double>(), B, g.N, fb.as<double>(),
+                       st);
     f_base = fb.as<double>();
     f_ld = L_;
     std::fill(sc.begin(), sc.end(), 1.0);

@@ -39,7 +39,7 @@ struct BatchSolver {
   QState q{};
   const double* f_base = nullptr;  // right-hand side term(s), storage order
   int64_t f_ld = 0;                // 0: one shared term scaled per query
-  DevBuf fb;                       // materialised f_b when R > 1
+  Buf fb, phi_d;                   // f_b = sum_r phi_br f_r when R > 1, and phi
   TuneConfig tc;                    // tile choices of this solve
   std::string tune_key;
   hipGraphExec_t graph = nullptr;
