@@ -173,6 +173,10 @@ rb_status rb_ctx_destroy(rb_ctx* ctx) {
       (void)hipStreamSynchronize(ctx->stream);
       (void)hipStreamDestroy(ctx->stream);
     }
+    for (hipStream_t st : ctx->group_streams) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
     delete ctx;
   });
 }
@@ -737,7 +741,6 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       std::vector<int> nu;
       bool any_phi = false;
       hipStream_t st = nullptr;
-      std::unique_ptr<Workspace> ws;
       std::unique_ptr<BatchSolver> solver;
       bool running = false;
       rb_solve_opts opt;
@@ -769,27 +772,23 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       check_finite(g.th.data(), g.th.size(), "theta");
       gs.push_back(std::move(g));
     }
-    // streams and workspaces; destroyed on every exit path
-    struct Streams {
-      std::vector<hipStream_t> v;
-      ~Streams() {
-        for (auto s : v) (void)hipStreamDestroy(s);
-      }
-    } own;
-    for (size_t i = 0; i < gs.size(); ++i) {
-      if (i == 0) {
-        gs[i].st = ctx->stream;
-      } else {
-        RB_HIP(hipStreamCreate(&gs[i].st));  // blocking, default priority
-        own.v.push_back(gs[i].st);
-        gs[i].ws = std::make_unique<Workspace>();
-      }
+    // the first group runs on the context's stream and workspace, the others on the
+    // context's group streams and workspaces (created on first use, kept for later calls)
+    while (ctx->group_streams.size() + 1 < gs.size()) {
+      hipStream_t st = nullptr;
+      RB_HIP(hipStreamCreate(&st));  // blocking, default priority
+      ctx->group_streams.push_back(st);
+      ctx->group_ws.push_back(std::make_unique<Workspace>());
     }
-    for (auto& g : gs) {
+    for (size_t i = 0; i < gs.size(); ++i)
+      gs[i].st = i == 0 ? ctx->stream : ctx->group_streams[i - 1];
+    for (size_t i = 0; i < gs.size(); ++i) {
+      auto& g = gs[i];
       const rb_basis* bs = bases ? bases[g.idx.empty() ? 0 : qs[g.idx[0]].problem] : nullptr;
+      Workspace* ws = i == 0 ? &ctx->ws : ctx->group_ws[i - 1].get();
       g.solver = std::make_unique<BatchSolver>(ctx, g.p, bs, g.opt, (int)g.idx.size(), g.th.data(),
                                                g.any_phi ? g.ph.data() : nullptr, g.nu.data(),
-                                               g.st, g.ws ? g.ws.get() : &ctx->ws);
+                                               g.st, ws);
       g.solver->start();
       g.running = true;
     }
@@ -804,11 +803,13 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
           any |= g.running;
         }
     }
-    for (auto& g : gs) {
+    for (size_t i = 0; i < gs.size(); ++i) {
+      auto& g = gs[i];
       BatchSolver& sv = *g.solver;
       sv.finish();
       std::vector<rb_query_stats> st;
-      DevBuf xs(sizeof(double) * g.idx.size() * g.p->N);
+      Workspace* ws = i == 0 ? &ctx->ws : ctx->group_ws[i - 1].get();
+      Buf xs = ws->get(WS_GATHER, sizeof(double) * g.idx.size() * g.p->N, sv.s());
       sv.gather(xs.as<double>(), g.p->N, st);
       for (size_t k = 0; k < g.idx.size(); ++k) {
         RB_HIP(hipMemcpyAsync(qs[g.idx[k]].x, xs.as<double>() + k * g.p->N,

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/rb.h"
@@ -143,7 +144,7 @@ TuneConfig stencil_tiles();
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
   WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_QLIST, WS_FB, WS_PHI,
-  WS_COUNT
+  WS_GATHER, WS_COUNT
 };
 }  // namespace rb
 
@@ -172,6 +173,10 @@ struct rb_ctx {
   // uses it; concurrent groups of rb_solve_multi get their own)
   rb::Workspace ws;
   rb::Buf get_ws(int slot, size_t bytes) { return ws.get(slot, bytes, stream); }
+  // streams and workspaces of the further groups of rb_solve_multi, grown on demand and
+  // kept for later calls until the context is destroyed
+  std::vector<hipStream_t> group_streams;
+  std::vector<std::unique_ptr<rb::Workspace>> group_ws;
 };
 
 namespace rb {
