@@ -114,8 +114,8 @@ def main():
                     help="also fill and sum a buffer of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the queries are independent and the build "
-              "has no multi-GPU path (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the "
+              "queries are independent and would be split across GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 // Surrogate-ranked greedy step and the MLP diagnostics of the C ABI.
 //
 // Protocol of one greedy step N with the surrogate (the true indicator of Alg. 4
-// step 5 stays the judge of every pick):
+// step 5 still decides every pick):
 //  - full sweep of the true indicator for the first `warmup_full_sweeps` steps and
 //    every `full_sweep_every` steps; it also adds every unpicked candidate to the
 //    replay buffer as (features(mu), log10 indicator); targets are standardised over
@@ -157,7 +157,7 @@ int Surrogate::step(int k, double* value) {
       full = true;
       ++fallbacks;
     } else {
-      // the judge: argmax of the true indicator among the evaluated candidates
+      // the pick: argmax of the true indicator among the evaluated candidates
       std::vector<double> keep(M, -HUGE_VAL);
       for (int m : eval) keep[m] = gs.ind_h[m];
       gs.ind_h = keep;
