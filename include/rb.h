@@ -144,8 +144,8 @@ rb_status rb_basis_destroy(rb_basis* basis);
  * contractions W^T r and W e in FP32 / BF16 with FP32 accumulation and the
  * smoother and y in FP32, while x, r, p, every CG dot product, alpha, beta, the
  * true residual and the reduced Cholesky stay FP64.
- * beta_flexible: 0 = the ratio of step 10 of Alg. 3; 1 = y_{k+1}^T (r_{k+1}-r_k) /
- * y_k^T r_k.  use_graph: replay captured HIP graphs of the iteration.
+ * beta_flexible: 0 = the ratio of Alg. 3, y_{k+1}^T r_{k+1} / y_k^T r_k;
+ * 1 = y_{k+1}^T (r_{k+1}-r_k) / y_k^T r_k.  use_graph: replay captured HIP graphs of the iteration.
  * fixed_iters > 0: run exactly that many iterations, no stopping test (testing). */
 typedef struct {
   size_t struct_size; /* sizeof(rb_solve_opts) */
@@ -225,7 +225,7 @@ rb_status rb_apply_batch(rb_ctx* ctx, const rb_problem* prob, int B, const doubl
                          const double* u, double* y);
 /* y_b = RBI(A(theta_b), r_b, W_{n_use[b]}, 1): one RB iteration from x = 0 (projection
  * W^T r, reduced Cholesky solve, prolongation, one smoother application) as used by
- * RBCG (Alg. 3 steps 2 and 9).  r, y: [B][N] DEVICE FP64, natural ordering. */
+ * RBCG (Alg. 3).  r, y: [B][N] DEVICE FP64, natural ordering. */
 rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
                            const rb_solve_opts* opts, int B, const double* theta,
                            const int* n_use, const double* r, double* y);
@@ -244,7 +244,7 @@ rb_status rb_reduced_factor_batch(rb_ctx* ctx, const rb_basis* basis, int B,
  * Snapshot solves x(mu_N) = RBCG(A(mu_N), f, W_{N-1}) (W_0 empty: smoother-only
  * PCG), modified Gram-Schmidt, growth of A_{N,q} and f_{N,r}, and a sweep of the
  * indicator over Xi_train with argmax over the unpicked candidates (lowest index
- * wins ties).  Indicators: RB_IND_L1 = sum_n |a_n(mu)| (Alg. 1/4 step 6);
+ * wins ties).  Indicators: RB_IND_L1 = sum_n |a_n(mu)| (Alg. 1 / Alg. 4);
  * RB_IND_RESIDUAL = ||f - A(mu) W a(mu)|| / ||f||.
  * use_surrogate: rank candidates by an MLP (P -> 128 -> 128 -> 1, GELU) trained
  * on the GPU on the indicators already computed; the true indicator is evaluated
@@ -287,10 +287,10 @@ rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob, const rb_greedy_
                            int64_t M, int P, const double* mu, const double* theta,
                            const double* phi, rb_basis** out, rb_greedy_report* rep);
 
-/* Steps 3-4 of Alg. 4 for a given sequence of K <= 80 parameters: each snapshot
- * x(theta_k) = RBCG(A(theta_k), f, W_{k-1}) (snapshot_rtol, snapshot_maxit,
- * snapshot_flexible of opts; the other fields are ignored) is orthonormalised into the
- * basis; a degenerate snapshot (already in the span) is skipped.  With the picks of a
+/* Snapshot solves and basis updates of Alg. 4 for a given sequence of K <= 80
+ * parameters: each snapshot x(theta_k) = RBCG(A(theta_k), f, W_{k-1})
+ * (snapshot_rtol, snapshot_maxit, snapshot_flexible of opts; the other fields are
+ * ignored) is orthonormalised into the basis; a degenerate snapshot (already in the span) is skipped.  With the picks of a
  * greedy on a coarse grid (rb_greedy_report.picks) this is the multi-fidelity offline
  * build of Sec. 4.2 (last paragraph).  theta [K][Q], phi [K][R] or NULL, host.
  * rep (nullable): n_built, picks = indices k that entered the basis, snapshot_iters,

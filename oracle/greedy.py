@@ -1,22 +1,20 @@
 """Greedy construction of the reduced basis, oracle side (test infrastructure only).
 
 Adaptive greedy sampling (Alg. 4, Sec. 4.2), which is the greedy of Alg. 1 (Sec. 2.2)
-with the snapshot solve of step 3 done by RBCG with the basis built so far:
+with each snapshot solved by RBCG with the basis built so far:
 
-  0-1. mu_1 = Xi_train[seed_index]; S_1 = {mu_1}; W_0 = empty
-  for N = 1..N_max:
-    3. x(mu_N) = RBCG(A(mu_N), f, W_{N-1})   (N = 1: W_0 empty -> smoother-only PCG)
-    4. W_N = MGS(W_{N-1}, x(mu_N))
-       grow A_{N,q} = W_N^T A_q W_N and f_{N,r} = W_N^T f_r   (eq. 12c)
-    5. for every mu in Xi_train solve A_N(mu) a(mu) = f_N(mu)  (eq. 12b)
-    6. mu_{N+1} = argmax over Xi_train \\ S_N of the indicator
-    7. S_{N+1} = S_N + {mu_{N+1}}
+  - start: mu_1 = Xi_train[seed_index], S_1 = {mu_1}, W_0 empty;
+  - for N = 1..N_max: the snapshot x(mu_N) = RBCG(A(mu_N), f, W_{N-1}) (W_0 empty:
+    PCG with the smoother only); W_N = MGS(W_{N-1}, x(mu_N)), growing
+    A_{N,q} = W_N^T A_q W_N and f_{N,r} = W_N^T f_r (eq. 12c); the reduced solve
+    A_N(mu) a(mu) = f_N(mu) (eq. 12b) for every mu in Xi_train; the next sample
+    mu_{N+1} = argmax of the indicator over Xi_train without S_N, added to S_N.
 
 Snapshot solves use the flexible beta by default: with the post-smoothing-only
-preconditioner of Alg. 3 and very small bases (W_0 empty, W_1, W_2) the ratio of
-step 10 stagnates on these problems, while the flexible form converges.
+preconditioner of Alg. 3 and very small bases (W_0 empty, W_1, W_2) the literal
+ratio stagnates on these problems, while the flexible form converges.
 
-Indicators: "l1" = sum_n |a_n(mu)| (the paper's, Alg. 1 step 6); "residual" =
+Indicators: "l1" = sum_n |a_n(mu)| (the paper's, Alg. 1); "residual" =
 ||f - A(mu) W a(mu)|| / ||f|| evaluated directly.  Ties go to the lowest index.
 If MGS finds the snapshot degenerate, the candidate is excluded and the next best
 candidate of the same sweep is taken.
@@ -43,7 +41,7 @@ class GreedyResult:
 
 
 def reduced_coefficients(AN_q, fN, theta):
-    """a(mu) = A_N(mu)^-1 f_N for one parameter vector (Alg. 1/4 step 5)."""
+    """a(mu) = A_N(mu)^-1 f_N for one parameter vector (eq. 12b; Alg. 1 and 4)."""
     AN = assemble_reduced(AN_q, theta)
     return chol_solve(cholesky(AN), fN)
 
@@ -116,9 +114,9 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
         res = solve_rbcg(op, thetas[mu_next], W, AN_q if W.shape[1] else None,
                          rtol=snapshot_rtol, maxit=snapshot_maxit,
                          flexible=snapshot_flexible,
-                         phi=None if phis is None else phis[mu_next])   # step 3
+                         phi=None if phis is None else phis[mu_next])   # snapshot
         try:
-            w = mgs(W, res.x)                                            # step 4
+            w = mgs(W, res.x)                                            # orthonormalise
         except Degenerate:
             excluded.add(mu_next)
             if ind is None:
@@ -129,13 +127,13 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
         excluded.add(mu_next)
         snap_iters.append(res.iters)
         W, AN_q, fN = _append(op, W, AN_q, fN, w)
-        ind = indicator_values(op, W, AN_q, fN, thetas, indicator, phis)  # step 5
+        ind = indicator_values(op, W, AN_q, fN, thetas, indicator, phis)  # indicator sweep
         if keep_indicators:
             all_ind.append(ind.copy())
         if len(excluded) >= len(thetas):
             maxind.append(float(np.max(ind)))
             break
-        mu_next = masked_argmax(ind, excluded)                           # step 6
+        mu_next = masked_argmax(ind, excluded)                           # next sample
         maxind.append(float(ind[mu_next]))
     return GreedyResult(W, picks, maxind, AN_q, fN[0] if len(fN) == 1 else fN, snap_iters,
                         all_ind)
@@ -143,7 +141,7 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
 
 def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
                           snapshot_flexible=True, phis=None):
-    """Steps 3-4 of Alg. 4 for a given sequence of parameters: each snapshot is solved
+    """The snapshot solve and basis update of Alg. 4 for a given sequence of parameters: each snapshot is solved
     by RBCG with the basis built so far and orthonormalised into it (degenerate
     snapshots are skipped).  With the parameters picked by a greedy on a coarse grid
     this is the multi-fidelity construction of Sec. 4.2 (last paragraph).  picks lists
@@ -155,9 +153,9 @@ def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
     for i, th in enumerate(thetas):
         res = solve_rbcg(op, th, W, AN_q if W.shape[1] else None, rtol=snapshot_rtol,
                          maxit=snapshot_maxit, flexible=snapshot_flexible,
-                         phi=None if phis is None else phis[i])           # step 3
+                         phi=None if phis is None else phis[i])           # snapshot
         try:
-            w = mgs(W, res.x)                                               # step 4
+            w = mgs(W, res.x)                                               # orthonormalise
         except Degenerate:
             continue
         picks.append(i)

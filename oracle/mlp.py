@@ -1,7 +1,7 @@
 """MLP surrogate of the greedy error indicator, oracle side (test infrastructure only).
 
 Not part of the paper: the surrogate ranks the training-set candidates of the greedy
-(Alg. 4, step 6) so that the true indicator is only evaluated on a short list.
+(the argmax of Alg. 4) so that the true indicator is only evaluated on a short list.
 Network: P -> H -> H -> 1 with exact-erf GELU, MSE loss on log10(indicator), Adam.
 Everything here is float64 and written out by hand (no autograd).
 

@@ -17,7 +17,7 @@ Readings where the paper is silent (each also listed in the design notes):
   - the RBI preconditioner skips its own exit test (the outer test just failed)
   - the reduced matrix is factored once per mu; each application is two triangular
     solves (same result as re-inverting each iteration)
-  - beta is the ratio of step 10 of Alg. 3; "flexible" uses y_{k+1}^T (r_{k+1} - r_k)
+  - beta is the ratio y_{k+1}^T r_{k+1} / y_k^T r_k of Alg. 3; "flexible" uses y_{k+1}^T (r_{k+1} - r_k)
   - iteration count = number of products A p
   - adaptive basis size (Sec. 4.1, last paragraph): after each iteration, if
     ||r_in|| / ||r_{k+1}|| < gamma, with r_in the residual the current search direction
@@ -72,9 +72,9 @@ def chol_solve(L, t):
 
 # --- RBI (Alg. 2) -------------------------------------------------------------
 class RBPreconditioner:
-    """One RBI iteration from x = 0 applied to a right-hand side r (Alg. 3, steps 2/9).
+    """One RBI iteration from x = 0 applied to a right-hand side r (the preconditioner of Alg. 3).
 
-    With x = 0 the residual of step 2 of Alg. 2 is r itself (no product with A).
+    With x = 0 the residual that Alg. 2 starts from is r itself (no product with A).
     W may have zero columns (W_0 = empty): then the coarse correction is 0 and only
     the smoother acts, as in the first snapshot solve of the adaptive greedy.
     """
@@ -83,7 +83,7 @@ class RBPreconditioner:
         self.A, self.W, self.L, self.S = A, W, L, smoother
 
     def coarse(self, r):
-        """x = W e with A_N e = W^T r (Alg. 2 steps 4-6)."""
+        """x = W e with A_N e = W^T r (the coarse correction of Alg. 2, eq. 5)."""
         if self.W.shape[1] == 0:
             return np.zeros_like(r)
         t = self.W.T @ r
@@ -101,16 +101,16 @@ def rbi(A, b, W, L, smoother: Smoother, m, rtol=0.0):
     hist = []
     k = 0
     for k in range(1, m + 1):
-        r = b - A @ x                              # step 2
+        r = b - A @ x                              # residual
         hist.append(np.linalg.norm(r) / nb)
-        if hist[-1] <= rtol:                       # step 3 (relative reading)
+        if hist[-1] <= rtol:                       # exit test (relative reading)
             k -= 1
             break
         if W.shape[1] > 0:
-            t = W.T @ r                            # step 4
-            e = chol_solve(L, t)                   # step 5
-            x = x + W @ e                          # step 6
-        x = smoother(b, x)                         # step 7
+            t = W.T @ r                            # projection
+            e = chol_solve(L, t)                   # reduced solve
+            x = x + W @ e                          # coarse update
+        x = smoother(b, x)                         # post-smoothing
     return x, k, hist
 
 
@@ -151,10 +151,10 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
         return precond(v, n)
 
     precond_call = M
-    x = np.zeros_like(b)                    # step 0
-    r = b.copy()                            # step 1 (x0 = 0, no product needed)
-    y = precond_call(r)                     # step 2
-    p = y.copy()                            # step 3
+    x = np.zeros_like(b)
+    r = b.copy()                            # x0 = 0, no product needed
+    y = precond_call(r)
+    p = y.copy()
     rho = r @ y
     it = 0
     hist = [1.0]
@@ -162,7 +162,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
     status = "ok"
     rel_rec = 1.0
     vecs = {"r": [r.copy()], "p": [p.copy()]} if keep_vectors else None
-    while True:                             # step 4
+    while True:
         if fixed_iters is not None and it >= fixed_iters:
             break
         if it >= maxit:
@@ -173,10 +173,10 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
         if not pq > 0.0 or not rho > 0.0:
             status = "breakdown"
             break
-        alpha = rho / pq                    # step 5
-        x = x + alpha * p                   # step 6
+        alpha = rho / pq
+        x = x + alpha * p
         r_old = r
-        r = r - alpha * q                   # step 7
+        r = r - alpha * q
         it += 1
         rel_rec = np.linalg.norm(r) / nb
         hist.append(rel_rec)
@@ -184,7 +184,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
             iterates.append(x.copy())
         if adapt is not None and r_in[0] < adapt[0] * np.linalg.norm(r):
             n = min(n + 1, adapt[2])        # residual fell by less than gamma
-        if fixed_iters is None and rel_rec <= rtol:   # step 8
+        if fixed_iters is None and rel_rec <= rtol:   # stopping test
             rt = b - A @ x
             if np.linalg.norm(rt) / nb <= rtol:
                 break
@@ -193,13 +193,13 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
             p = y.copy()
             rho = r @ y
             continue
-        y = precond_call(r)                 # step 9
+        y = precond_call(r)
         rho_new = y @ r
         if flexible:
             beta = (y @ (r - r_old)) / rho
         else:
-            beta = rho_new / rho            # step 10
-        p = y + beta * p                    # step 11
+            beta = rho_new / rho
+        p = y + beta * p
         rho = rho_new
         if keep_vectors:
             vecs["r"].append(r.copy())
@@ -212,7 +212,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
     return out
 
 
-# --- modified Gram-Schmidt (Sec. 2.2, step 4 of Alg. 1 / Alg. 4) ---------------
+# --- modified Gram-Schmidt (Sec. 2.2; the basis update of Alg. 1 and Alg. 4) ---
 class Degenerate(Exception):
     pass
 

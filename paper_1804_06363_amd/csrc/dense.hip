@@ -1,9 +1,9 @@
 // Reduced-basis contractions and reduced solves.
 //
-//  * projection   t_b = W^T r_b            (eq. 5; Alg. 2 step 4)   MFMA, split-K partials
-//  * prolongation z_b = W e_b              (eq. 7; Alg. 2 step 6)   one node per thread
+//  * projection   t_b = W^T r_b            (eq. 5; Alg. 2)         MFMA, split-K partials
+//  * prolongation z_b = W e_b              (eq. 7; Alg. 2)         one node per thread
 //  * reduced assembly + Cholesky  A_N(mu) = sum_q Theta_q A_{N,q} = L L^T  (eq. 12b, Sec. 2.1)
-//  * reduced solve  e_b = L^-T L^-1 t_b    (eq. 6; Alg. 2 step 5)
+//  * reduced solve  e_b = L^-T L^-1 t_b    (eq. 6; Alg. 2)      
 //  * deterministic finalisation of per-block partial sums and the CG scalars of Alg. 3
 #include <hip/hip_runtime.h>
 
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(64) void k_cholesky(const double* __restrict__ AN, 
   if (lane == 0) status[b] = fail ? (int)RB_ENOTSPD : (int)RB_OK;
 }
 
-// Greedy sweep, steps 5-6 of Alg. 1/4: for candidate m, a(mu_m) = A_N(mu_m)^-1 f_N(mu_m)
+// Greedy sweep of Alg. 4 (reduced solve and indicator): for candidate m, a(mu_m) = A_N(mu_m)^-1 f_N(mu_m)
 // (assembly by eq. 12b, Cholesky, two triangular solves) and the L1 indicator
 // sum_n |a_n|.  a rows have stride a_ld; status[m] = RB_ENOTSPD on failure (l1 = NaN).
 template <int NMAX>
@@ -658,7 +658,7 @@ void launch_sweep_coeffs(const double* AN, const double* fN, int n, int Q, int R
                        a_ld, l1, status);
 }
 
-// Masked argmax over M values (Alg. 1/4 step 6): largest value among the entries with
+// Masked argmax over M values (the next sample of Alg. 4): largest value among the entries with
 // excluded[m] == 0; ties go to the lowest index.  out_val/out_idx; out_idx = -1 if every
 // entry is excluded; nan_flag = 1 if a non-excluded entry is NaN.
 __global__ __launch_bounds__(256) void k_argmax(const double* __restrict__ v,
@@ -900,7 +900,7 @@ __device__ __forceinline__ double sum_parts(const double* p, int cnt, double* sh
   return rbk::block_sum_256(s, sh);
 }
 
-// step 5: alpha = rho / p^T A p (breakdown if either is not positive)
+// Alg. 3, step length: alpha = rho / p^T A p (breakdown if either is not positive)
 __global__ __launch_bounds__(256) void k_fin_alpha(const double* __restrict__ part, int stride,
                                                    int cnt, QState q) {
   __shared__ double sh[4];
@@ -919,7 +919,7 @@ __global__ __launch_bounds__(256) void k_fin_alpha(const double* __restrict__ pa
   }
 }
 
-// step 8: recursive residual test; flags the query for the true-residual check
+// Alg. 3, stopping test on the recursive residual; flags the query for the true-residual check
 __global__ __launch_bounds__(256) void k_fin_rr(const double* __restrict__ part, int stride,
                                                 int cnt, QState q, double rtol, int maxit,
                                                 int fixed) {
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
   }
 }
 
-// steps 9-10: rho_new = y^T r (red + black partials); beta (literal or flexible)
+// Alg. 3, new direction: rho_new = y^T r (red + black partials); beta (literal or flexible)
 __global__ __launch_bounds__(256) void k_fin_beta(const double* __restrict__ pr,
                                                   const double* __restrict__ fr, Segs sg,
                                                   QState q, int flexible) {

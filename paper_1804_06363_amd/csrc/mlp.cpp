@@ -1,7 +1,7 @@
 // Surrogate-ranked greedy step and the MLP diagnostics of the C ABI.
 //
-// Protocol of one greedy step N with the surrogate (the true indicator of Alg. 4
-// step 5 still decides every pick):
+// Protocol of one greedy step N with the surrogate (the true indicator of Alg. 4 still
+// decides every pick):
 //  - full sweep of the true indicator for the first `warmup_full_sweeps` steps and
 //    every `full_sweep_every` steps; it also adds every unpicked candidate to the
 //    replay buffer as (features(mu), log10 indicator); targets are standardised over

@@ -1,5 +1,5 @@
 // Kernels of the MLP surrogate that ranks greedy candidates (not part of the paper's
-// method; it replaces most full sweeps of the indicator in Alg. 4 step 5).
+// method; it replaces most full sweeps of the indicator in Alg. 4).
 //
 // Network P -> H -> H -> 1 with exact-erf GELU, MSE loss on log10(indicator), Adam.
 // Products run on MFMA with FP32 accumulation; in BF16 mode both operands are rounded

@@ -81,7 +81,7 @@ double GreedyState::norm(const double* v) {
   return std::sqrt(s);
 }
 
-// Snapshot solve (step 3): RBCG with the current basis, FP64.  Returns its iteration
+// Snapshot solve of Alg. 4: RBCG with the current basis, FP64.  Returns its iteration
 // count; the solution (storage order) is left in `w`.
 int GreedyState::snapshot(int mu) {
   rb_solve_opts so;
@@ -167,7 +167,7 @@ void GreedyState::sweep(const std::vector<int>& idx) {
       ph_d = phg.as<double>();
     }
   }
-  // step 5: reduced coefficients and the L1 indicator of every listed candidate
+  // reduced coefficients and the L1 indicator of every listed candidate
   launch_sweep_coeffs(bs->AN.as<double>(), bs->fN.as<double>(), n, Q, R, cnt, th_d, ph_d,
                       coeffs.as<double>(), a_ld, l1.as<double>(), cstatus.as<int>(), st);
   std::vector<double> vals(cnt);
@@ -215,7 +215,7 @@ void GreedyState::sweep(const std::vector<int>& idx) {
   true_evals += cnt;
 }
 
-// Step 6 on the device: argmax of ind over the candidates not excluded.
+// Next sample of Alg. 4 on the device: argmax of ind over the candidates not excluded.
 int GreedyState::pick(double* value) {
   hipStream_t st = ctx->stream;
   RB_HIP(hipMemcpyAsync(ind.p, ind_h.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
@@ -294,9 +294,9 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
     int mu_next = (int)opts->seed_index;
     int step = 0;
     while (gs.bs->n < opts->n_max) {
-      const int it = gs.snapshot(mu_next);                  // step 3
+      const int it = gs.snapshot(mu_next);                  // snapshot
       gs.excl_h[mu_next] = 1;
-      if (!gs.orthonormalize_append()) {                    // step 4 (degenerate)
+      if (!gs.orthonormalize_append()) {                    // degenerate snapshot
         RB_REQUIRE(!gs.ind_h.empty(), RB_EDEGENERATE, "first snapshot is degenerate");
         mu_next = gs.pick(nullptr);
         RB_REQUIRE(mu_next >= 0, RB_EDEGENERATE, "no candidate left");
@@ -309,11 +309,11 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
       double v = 0.0;
       int nxt;
       if (sur)
-        nxt = sur->step(step, &v);                          // steps 5-6 via the surrogate
+        nxt = sur->step(step, &v);                          // sweep + pick, surrogate
       else {
-        gs.sweep({});                                       // step 5
+        gs.sweep({});                                       // indicator sweep
         gs.full_sweeps++;
-        nxt = gs.pick(&v);                                  // step 6
+        nxt = gs.pick(&v);                                  // next sample
       }
       maxind.push_back(v);
       if (nxt < 0) break;
@@ -345,8 +345,8 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
   }
 }
 
-// Steps 3-4 of Alg. 4 for a given parameter sequence (the multi-fidelity construction of
-// Sec. 4.2: the parameters are the picks of a greedy on a coarse grid).
+// Snapshot solves and basis updates of Alg. 4 for a given parameter sequence (the
+// multi-fidelity construction of Sec. 4.2: the parameters are the picks of a greedy on a coarse grid).
 extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* prob,
                                               const rb_greedy_opts* opts, int K,
                                               const double* theta, const double* phi,
@@ -369,8 +369,8 @@ extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* pro
     std::vector<int64_t> used;
     std::vector<int> snap_it;
     for (int i = 0; i < K; ++i) {
-      const int it = gs.snapshot(i);            // step 3
-      if (!gs.orthonormalize_append()) continue;  // step 4; degenerate: skipped
+      const int it = gs.snapshot(i);            // snapshot
+      if (!gs.orthonormalize_append()) continue;  // degenerate: skipped
       used.push_back(i);
       snap_it.push_back(it);
       gs.bs->picks.push_back(i);

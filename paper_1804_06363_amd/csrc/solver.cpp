@@ -182,8 +182,9 @@ void BatchSolver::factor() {
   RB_HIP(hipMemcpyAsync(q.active, act.data(), sizeof(int) * B, hipMemcpyHostToDevice, s()));
 }
 
-// One application y = RBI(A, r, W, 1) from x = 0 (Alg. 3 steps 2/9, i.e. Alg. 2 steps 4-7
-// with the residual equal to r), plus the partial sums of y^T r (and y^T r_old).
+// One application y = RBI(A, r, W, 1) from x = 0, the preconditioner of Alg. 3: one
+// iteration of Alg. 2 (coarse correction and smoothing) whose residual is r itself, plus
+// the partial sums of y^T r (and y^T r_old).
 void BatchSolver::precondition(const double* r, const double* r_old) {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
@@ -276,7 +277,7 @@ const Segs& BatchSolver::dot_segs() const {
   return gs ? gsegs : jsegs;
 }
 
-// RBCG steps 0-3 (Alg. 3): x = 0, r = f, y = RBI(A, r, W, 1), p = y (beta = 0).
+// RBCG start (Alg. 3): x = 0, r = f, y = RBI(A, r, W, 1), p = y (beta = 0).
 void BatchSolver::init_cg() {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
@@ -297,7 +298,7 @@ void BatchSolver::init_cg() {
   launch_fin_beta(part_r0.as<double>(), nullptr, dot_segs(), q, B, false, st);
 }
 
-// One RBCG iteration (Alg. 3 steps 5-11) for every active query.
+// One RBCG iteration (Alg. 3) for every active query.
 void BatchSolver::iterate_cg(int k) {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
@@ -307,7 +308,7 @@ void BatchSolver::iterate_cg(int k) {
   const bool flex = opt.beta_flexible != 0;
   double* rin = (flex && (k & 1)) ? r1.as<double>() : r0.as<double>();
   double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
-  // step 11 of the previous iteration fused with step 5's product: p = y + beta p; A p
+  // the previous iteration's direction update fused with the product: p = y + beta p; A p
   int ca, cb;
   {
     ProfScope ps(ctx, "pass_a", st);
@@ -319,13 +320,13 @@ void BatchSolver::iterate_cg(int k) {
                                  q.beta, q.active, part_m.as<double>(), st);
   }
   launch_fin_alpha(part_m.as<double>(), cN, ca, q, B, st);
-  // steps 6-7: x += alpha p, r -= alpha A p
+  // x += alpha p, r -= alpha A p
   {
     ProfScope ps(ctx, "pass_b", st);
     cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha,
                        q.active, part_m.as<double>(), st);
   }
-  // step 8
+  // stopping test: recursive, then the true residual of the flagged queries
   const bool fixed = opt.fixed_iters > 0;
   launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
@@ -336,7 +337,7 @@ void BatchSolver::iterate_cg(int k) {
     launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st, p2,
                     opt.floor_factor);
   }
-  // steps 9-10
+  // preconditioning and the new direction coefficient
   precondition(rout, flex ? rin : nullptr);
   launch_fin_beta(part_r0.as<double>(), flex ? part_r1.as<double>() : nullptr, dot_segs(), q, B,
                   flex, st);
@@ -376,22 +377,22 @@ void BatchSolver::init_rbi() {
   factor();
 }
 
-// Alg. 2 steps 2-7 for every active query (x lives in x, r in r0).
+// One iteration of Alg. 2 for every active query (x lives in x, r in r0).
 void BatchSolver::iterate_rbi(int k) {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
   double* xc = x.as<double>();
-  // step 2: r = f - A x, ||r||^2  (the active flags select the queries)
+  // r = f - A x, ||r||^2  (the active flags select the queries)
   launch_apply(g, L_, B, coef.as<double>(), xc, r0.as<double>(), 1, f_base, f_ld,
                scale_d.as<double>(), q.active, part_m.as<double>(), st);
   launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, q.active, B, st);
-  // step 3
+  // stopping test
   const bool fixed = opt.fixed_iters > 0;
   hipLaunchKernelGGL(k_fin_rbi, dim3((B + 63) / 64), dim3(64), 0, st, q, fixed ? -1.0 : opt.rtol,
                      fixed ? (1 << 30) : opt.maxit, B);
   const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
-  // steps 4-6: x += W A_N^-1 W^T r (black nodes only before a Gauss-Seidel sweep)
+  // coarse correction: x += W A_N^-1 W^T r (black nodes only before a Gauss-Seidel sweep)
   if (n > 0) {
     launch_projection(plan, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
                       projpart.p, st);
@@ -401,7 +402,7 @@ void BatchSolver::iterate_rbi(int k) {
     launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
                    q.active, xc, true, L_, full ? 0 : g.coff[1], g.N, true, st);
   }
-  // step 7: x = S(A, f, x)
+  // smoothing: x = S(A, f, x)
   auto sweep = [&](int color) {
     launch_gs_color<double>(g, color, B, coef.as<double>(), xc, L_, f_base, f_ld,
                             scale_d.as<double>(), nullptr, 0, q.active, nullptr, nullptr, st);

@@ -468,7 +468,7 @@ def offline_build(ctx, prob, theta, mu=None, phi=None, **kw):
 
 
 def basis_from_parameters(ctx, prob, theta, phi=None, **kw):
-    """Steps 3-4 of Alg. 4 for the given parameters (multi-fidelity build, Sec. 4.2)."""
+    """Snapshot solves and basis updates of Alg. 4 for the given parameters (multi-fidelity build, Sec. 4.2)."""
     theta = _f64(np.atleast_2d(theta))
     K = theta.shape[0]
     opts = greedy_opts(**kw)

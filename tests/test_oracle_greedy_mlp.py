@@ -126,7 +126,7 @@ def test_adam_first_step_is_signed_lr():
 
 # ---- multi-fidelity construction (Sec. 4.2, last paragraph) ----------------------------
 def test_basis_from_greedy_picks_reproduces_greedy_basis():
-    """Steps 3-4 replayed on the greedy's own picks give the greedy's basis exactly."""
+    """Snapshot solves and basis updates replayed on the greedy's own picks give the greedy's basis exactly."""
     op = BlockDiffusion((15, 15), (2, 2))
     thetas = log_uniform_mu(11, 40, op.Q, 0.1, 10.0)
     g = greedy.adaptive_greedy(op, thetas, 6, indicator="residual")

@@ -107,7 +107,7 @@ def test_cholesky_and_solve():
 
 # --- RBI: Galerkin step and Lemmas 1-3 (Sec. 3.2) ------------------------------
 def test_first_coarse_correction_is_galerkin():
-    """After step 6 of the first RBI iteration, W^T (f - A x_hat) = 0 (eq. 2b)."""
+    """After the coarse update of the first RBI iteration, W^T (f - A x_hat) = 0 (eq. 2b)."""
     op, theta, A = _problem()
     W = _snapshot_basis(op, 4)
     A_, M = rb.make_preconditioner(op, theta, W)
@@ -150,7 +150,7 @@ def test_lemma2_stagnation_without_smoother():
 
 
 def test_lemma3_error_approximation():
-    """W e_N of step 5 is the Galerkin approximation of the error A^-1 r."""
+    """The coarse correction W e_N is the Galerkin approximation of the error A^-1 r."""
     op, theta, A = _problem()
     W = _snapshot_basis(op, 4)
     Ad = A.toarray()
