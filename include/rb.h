@@ -194,8 +194,9 @@ typedef struct {
   int at_floor; /* 1: accepted at the rounding level (floor_factor), not at rtol */
 } rb_query_stats;
 
-/* B queries on one problem and basis.  theta [B][Q] host; phi [B][R] host or NULL
- * (all ones); n_use [B] host or NULL (= basis size): query b uses the leading
+/* B queries on one problem and basis, 0 <= B <= 65535 (B = 0: RB_OK, nothing read or
+ * written; theta, x and stats may then be NULL).  theta [B][Q] host; phi [B][R] host or
+ * NULL (all ones); n_use [B] host or NULL (= basis size): query b uses the leading
  * n_use[b] basis vectors; basis may be NULL for RB_SOLVER_CG.
  * x: [B][N] DEVICE doubles, natural ordering, written with the solutions.
  * stats: [B] host, written. */
@@ -206,7 +207,9 @@ rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* ba
 
 /* Queries on several problems/bases in one call (uneven batches).  The queries are
  * grouped by (problem, tolerance); every group is one batched solve on its own stream
- * and workspace, and the groups run concurrently.  Errors as rb_solve_batch. */
+ * and workspace, and the groups run concurrently.  At most 65535 queries per group;
+ * B = 0 returns RB_OK (queries and stats may then be NULL).  Errors as
+ * rb_solve_batch. */
 typedef struct {
   int problem;          /* index into probs/bases */
   int n_use;            /* <= 0: the whole basis */

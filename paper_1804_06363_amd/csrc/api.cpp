@@ -699,11 +699,12 @@ rb_status rb_solve_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
                          const rb_solve_opts* o, int B, const double* theta, const double* phi,
                          const int* n_use, double* x, rb_query_stats* stats) {
   return guarded([&] {
-    RB_REQUIRE(ctx && p && theta && x && stats && B >= 1 && B <= 65535, RB_EINVAL,
-               "bad solve arguments");
+    RB_REQUIRE(ctx && p && B >= 0 && B <= 65535, RB_EINVAL, "bad solve arguments");
     check_opts(o);
     RB_REQUIRE(bs || o->solver == RB_SOLVER_CG, RB_EINVAL, "basis required");
     RB_REQUIRE(!bs || bs->prob == p, RB_EINVAL, "basis belongs to another problem");
+    if (B == 0) return;  // an empty batch: nothing to solve, nothing written
+    RB_REQUIRE(theta && x && stats, RB_EINVAL, "bad solve arguments");
     check_finite(theta, (size_t)B * p->g.Q, "theta");
     if (phi) check_finite(phi, (size_t)B * p->R, "phi");
     DeviceGuard dg(ctx->device);
@@ -719,7 +720,7 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
                          const rb_basis* const* bases, const rb_solve_opts* o, int B,
                          const rb_query* qs, rb_query_stats* stats) {
   return guarded([&] {
-    RB_REQUIRE(ctx && probs && qs && stats && nprob >= 1 && B >= 0, RB_EINVAL,
+    RB_REQUIRE(ctx && probs && nprob >= 1 && B >= 0 && (B == 0 || (qs && stats)), RB_EINVAL,
                "bad multi-solve arguments");
     check_opts(o);
     // group the queries by problem; each group is one batched solver.  The groups run
@@ -756,6 +757,7 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       RB_REQUIRE(!bs || bs->prob == g.p, RB_EINVAL, "basis belongs to another problem");
       g.idx = kv.second;
       const int Bg = (int)g.idx.size();
+      RB_REQUIRE(Bg <= 65535, RB_EINVAL, "more than 65535 queries on one problem and tolerance");
       const int Q = g.p->g.Q, R = g.p->R;
       g.th.resize((size_t)Bg * Q);
       g.ph.assign((size_t)Bg * R, 1.0);
