@@ -37,7 +37,14 @@ class BlockDiffusion:
         self.h = tuple(1.0 / (n + 1) for n in self.dims)
         self.N = int(np.prod(self.dims))
         self.Q = int(np.prod(self.blocks))
-        self.A_q = [self._term(q) for q in range(self.Q)]
+        self._A_q = None
+
+    @property
+    def A_q(self):
+        """The sparse terms A_q, built on first use (large grids may need only apply())."""
+        if self._A_q is None:
+            self._A_q = [self._term(q) for q in range(self.Q)]
+        return self._A_q
 
     # --- geometry -------------------------------------------------------------
     def block_coords(self, q):
@@ -112,6 +119,33 @@ class BlockDiffusion:
         for q in range(1, self.Q):
             A = A + theta[q] * self.A_q[q]
         return A.tocsr()
+
+    def apply(self, theta, u):
+        """A(theta) u without a matrix: the same face sum, axis by axis.  The face
+        coefficients are sum_q theta_q h_a^-2 (block-q weight of the face), the flux
+        through face I along axis a is c_I (u_I - u_{I-1}) with u = 0 beyond the
+        boundary, and node i receives flux(i) - flux(i + 1)."""
+        theta = np.asarray(theta, dtype=np.float64)
+        shape = self.dims[::-1]  # numpy C-order: last axis = x
+        U = np.asarray(u, dtype=np.float64).reshape(shape)
+        out = np.zeros(shape)
+        for a in range(self.dim):
+            ax = self.dim - 1 - a
+            C = 0.0
+            for q in range(self.Q):
+                qc = self.block_coords(q)
+                w = None
+                for t in range(self.dim):
+                    wt = (self._normal_weight(t, qc[t]) if t == a
+                          else self._tangential_weight(t, qc[t]))
+                    w = wt if w is None else np.multiply.outer(wt, w)  # (.., y, x) order
+                C = C + theta[q] * w
+            C = C * (1.0 / self.h[a] ** 2)
+            pad = [(0, 0)] * self.dim
+            pad[ax] = (1, 1)
+            flux = C * np.diff(np.pad(U, pad), axis=ax)  # faces I = 0..n
+            out -= np.diff(flux, axis=ax)
+        return out.ravel()
 
     def rhs(self):
         """f = 1 (R = 1, Phi_1 = 1)."""

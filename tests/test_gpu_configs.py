@@ -1,0 +1,133 @@
+"""Parity cases at the shapes of the other workloads (the benchmark's own 127^3 batch is
+in test_gpu_fullsize.py):
+
+  * 2D 63x63, kappa on 2x2 blocks, greedy over 256 parameters to n = 20, 16 test
+    parameters solved one at a time in FP64: greedy picks and basis against the
+    oracle's greedy, every solve against the oracle's RBCG with the same basis;
+  * 3D 63^3, greedy over 10^4 parameters to n = 60, plain residual sweep vs the
+    MLP-ranked sweep: the surrogate saves true evaluations and its basis is about as
+    good on held-out parameters (indicators computed by the oracle's operator);
+  * 3D 255^3 (N = 16,581,375), n = 80, 64 queries per batch, FP32 preconditioner: too
+    large for the oracle's solver, so checked by properties that hold at any size.
+    The basis is the 80 smoothest discrete sine modes (orthonormal on the grid), which
+    the greedy would take minutes to match; every query converges, and sampled
+    solutions satisfy the residual bound under the oracle's own operator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import greedy as og
+from oracle import rb as orb
+from oracle.operator import BlockDiffusion
+from workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _kappa_bound(dims, theta):
+    # lambda_max <= max(mu) 4 d / h^2 (Gershgorin); lambda_min >= min(mu) times the
+    # smallest Dirichlet eigenvalue of the unit-coefficient Laplacian
+    h = 1.0 / (dims[0] + 1)
+    d = len(dims)
+    return (max(theta) * 4.0 * d / h**2) / (min(theta) * d * 4.0 / h**2 *
+                                            math.sin(math.pi * h / 2) ** 2)
+
+
+def test_plain_fp64_configuration(lib, ctx):
+    w = WORKLOADS["2d63"]
+    op = BlockDiffusion(w.dims, w.blocks)
+    train = w.train_mu()
+    ref = og.adaptive_greedy(op, train, w.n, indicator="residual", snapshot_rtol=1e-12)
+    prob = lib.Problem(ctx, w.dims, w.blocks)
+    basis, rep = lib.offline_build(ctx, prob, train, mu=train, n_max=w.n, indicator="residual",
+                                   snapshot_rtol=1e-12)
+    assert rep["picks"] == ref.picks
+    Wn, AN, fN = basis.info()
+    W = np.ascontiguousarray(Wn.T)
+    assert np.abs(Wn @ W - np.eye(w.n)).max() <= 1e-12
+    for j in range(w.n):
+        assert np.linalg.norm(W[:, j] - ref.W[:, j]) <= 1e-6, j
+    test = w.test_mu()
+    for b in range(w.B):
+        x, st = lib.solve_batch(ctx, prob, basis, test[b:b + 1])
+        r = orb.solve_rbcg(op, test[b], W, AN)
+        assert st.status[0] == lib.RB_OK and st.rel_res_true[0] <= 1e-10
+        assert r.converged and abs(int(st.iters[0]) - r.iters) <= 1, (b, st.iters[0], r.iters)
+        assert _rel(x[0].cpu().numpy(), r.x) <= 2 * _kappa_bound(w.dims, test[b]) * 1e-10
+
+
+def test_learned_greedy_configuration(lib, ctx):
+    w = WORKLOADS["3d63"]
+    op = BlockDiffusion(w.dims, w.blocks)
+    prob = lib.Problem(ctx, w.dims, w.blocks)
+    train = w.train_mu()
+    held = w.test_mu(100)
+    f = op.rhs()
+    out = {}
+    for name, kw in (("plain", {}), ("surrogate", dict(use_surrogate=1, topk=256, explore=64,
+                                                      warmup_full_sweeps=4, full_sweep_every=10,
+                                                      train_steps=50, lr=1e-3, mu_lo=0.1,
+                                                      mu_hi=10.0, seed=1004))):
+        basis, rep = lib.offline_build(ctx, prob, train, mu=train, n_max=w.n,
+                                       indicator="residual", **kw)
+        assert rep["n_built"] == w.n and len(set(rep["picks"])) == w.n
+        Wn, AN, fN = basis.info()
+        assert np.abs(Wn @ Wn.T - np.eye(w.n)).max() <= 1e-10
+        worst = 0.0
+        for th in held:
+            a = np.linalg.solve(np.tensordot(th, AN, axes=1), fN[0])
+            eta = np.linalg.norm(f - op.apply(th, Wn.T @ a)) / np.linalg.norm(f)
+            worst = max(worst, eta)
+        out[name] = (rep["true_evals"], worst)
+    print(f"true evaluations / held-out max eta: {out}")
+    assert out["plain"][0] == w.n * w.M_train
+    assert out["surrogate"][0] < 0.6 * out["plain"][0]
+    assert out["surrogate"][1] <= 3.0 * out["plain"][1]
+
+
+def _dst_basis(dims, n):
+    """The n discrete sine modes s_i(x) s_j(y) s_k(z) with the smallest i^2 + j^2 + k^2
+    (ties by index), rows of length N in natural order; orthonormal on the grid."""
+    modes = sorted((i * i + j * j + k * k, i, j, k)
+                   for i in range(1, 9) for j in range(1, 9) for k in range(1, 9))[:n]
+
+    def s(m, i):
+        return math.sqrt(2.0 / (m + 1)) * np.sin(i * math.pi * np.arange(1, m + 1) / (m + 1))
+
+    nx, ny, nz = dims
+    W = np.empty((n, nx * ny * nz))
+    for c, (_, i, j, k) in enumerate(modes):
+        W[c] = np.multiply.outer(s(nz, k), np.multiply.outer(s(ny, j), s(nx, i))).ravel()
+    return W
+
+
+def test_large_configuration_properties(lib, ctx):
+    import torch
+    w = WORKLOADS["3d255"]
+    op = BlockDiffusion(w.dims, w.blocks)
+    prob = lib.Problem(ctx, w.dims, w.blocks)
+    Wn = _dst_basis(w.dims, w.n)
+    basis = lib.Basis.from_host(ctx, prob, Wn)
+    del Wn
+    test = w.test_mu()
+    x, st = lib.solve_batch(ctx, prob, basis, test, prec="fp32", maxit=5000)
+    assert (st.status == lib.RB_OK).all()
+    assert st.rel_res_true.max() <= 1e-10
+    f = op.rhs()
+    for b in (0, 41):
+        xb = x[b].cpu().numpy()
+        assert np.linalg.norm(f - op.apply(test[b], xb)) / np.linalg.norm(f) <= 1.01e-10
+    print(f"255^3, n = 80, B = 64: iterations {st.iters.min()}..{st.iters.max()}")
+    del x, basis
+    torch.cuda.empty_cache()
