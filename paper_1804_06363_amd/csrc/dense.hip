@@ -376,9 +376,11 @@ __global__ __launch_bounds__(256) void k_prolong(const TW* __restrict__ W, int64
 // entries widen exactly to FP32).  A block is 4 waves x 16 queries over a run of
 // 16*TP consecutive nodes: every wave writes 64*TP contiguous bytes per query row
 // (DRAM-friendly) and the block's waves share the W tile through L1.  Lane l supplies
-// e[q0 + l%16][j0 + l/16] and W[j0 + l/16][pos0 + 16p + l%16] and receives rows
-// 4(l/16)+i (queries) of column l%16 (node).  Blocks are remapped so that the query
-// groups of one node run sit on one XCD (their W tile is fetched once).
+// e[q0 + l%16][j0 + l/16] and, for MFMA block p = 4k + u, W[j0 + l/16][pos0 + 64k +
+// 4(l%16) + u], and receives rows 4(l/16)+i (queries) of that column (node): its W
+// loads and its stores are 4 consecutive nodes wide (127^3, B = 256, FP32: 454 us per
+// launch against 512 us with one node per access).  Blocks are remapped so that the
+// query groups of one node run sit on one XCD (their W tile is fetched once).
 template <typename TW, typename TO, int TP, bool ADD>
 // qlist (nullable): the active queries in increasing order, their count in qlist[B]; the
 // query groups then run over that list (groups past the count exit).
@@ -397,7 +399,8 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   const int run = id / qgroups, qg = id % qgroups;
   const int cnt = qlist ? qlist[B] : B;
   if (qg * 64 >= cnt) return;  // no barriers in this kernel
-  const int pos0 = lo + run * 16 * TP;
+  // runs start at lo rounded down to a multiple of 4 (nodes below lo are not stored)
+  const int pos0 = (lo & ~3) + run * 16 * TP;
   const int q0 = (qg * 4 + wave) * 16;
   const int r = lane & 15, g = lane >> 4;
   // e row of this lane: its query (through the list; past the count any valid row, whose
@@ -406,21 +409,31 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   floatx4 acc[TP];
 #pragma unroll
   for (int p = 0; p < TP; ++p) acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // Column r of MFMA block p = 4k + u is node pos0 + 64k + 4r + u, so a lane loads the
+  // W entries of four blocks, and stores their results, as four consecutive nodes.
   // Loads are unconditional: the caller pads e to round_up(B, 64) zero rows and at
   // least round_up(n, 4) columns, and W to round_up(n, 4) + 1 rows (zero beyond n),
-  // so every address is inside its buffer; columns pos >= hi are not stored.
+  // so every address is inside its buffer; nodes outside [lo, hi) are not stored.
   for (int j0 = 0; j0 < n; j0 += 4) {
     const int j = j0 + g;
     const float ev = e[(size_t)erow * e_ld + j];
-    const TW* wr = W + (size_t)j * w_ld + pos0 + r;
+    const TW* wr = W + (size_t)j * w_ld + pos0 + 4 * r;
 #pragma unroll
-    for (int p = 0; p < TP; ++p) {
-      float wv;
-      if constexpr (sizeof(TW) == 2)
-        wv = rbk::bf16_to_f32(wr[16 * p]);
-      else
-        wv = (float)wr[16 * p];
-      acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev, wv, acc[p], 0, 0, 0);
+    for (int k = 0; k < TP / 4; ++k) {
+      float wv[4];
+      if constexpr (sizeof(TW) == 2) {
+        const uint2 v = *reinterpret_cast<const uint2*>(wr + 64 * k);
+        wv[0] = rbk::bf16_to_f32((uint16_t)(v.x & 0xffff));
+        wv[1] = rbk::bf16_to_f32((uint16_t)(v.x >> 16));
+        wv[2] = rbk::bf16_to_f32((uint16_t)(v.y & 0xffff));
+        wv[3] = rbk::bf16_to_f32((uint16_t)(v.y >> 16));
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(wr + 64 * k);
+        wv[0] = v.x; wv[1] = v.y; wv[2] = v.z; wv[3] = v.w;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[4 * k + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev, wv[u], acc[4 * k + u], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -429,14 +442,31 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
     if (c >= cnt) continue;
     const int q = qlist ? qlist[c] : c;
     if (!qlist && !active[q]) continue;
-    TO* o = out + (size_t)q * o_ld + pos0 + r;
+    TO* o = out + (size_t)q * o_ld;
 #pragma unroll
-    for (int p = 0; p < TP; ++p) {
-      if (pos0 + 16 * p + r < hi) {
-        if (ADD)
-          o[16 * p] += (TO)acc[p][i];
-        else
-          o[16 * p] = (TO)acc[p][i];
+    for (int k = 0; k < TP / 4; ++k) {
+      const int p0 = pos0 + 64 * k + 4 * r;
+      if (!ADD && p0 >= lo && p0 + 3 < hi) {
+        if constexpr (sizeof(TO) == 4) {
+          *reinterpret_cast<float4*>(o + p0) =
+              float4{acc[4 * k][i], acc[4 * k + 1][i], acc[4 * k + 2][i], acc[4 * k + 3][i]};
+        } else {
+          reinterpret_cast<double2*>(o + p0)[0] =
+              double2{(double)acc[4 * k][i], (double)acc[4 * k + 1][i]};
+          reinterpret_cast<double2*>(o + p0)[1] =
+              double2{(double)acc[4 * k + 2][i], (double)acc[4 * k + 3][i]};
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int pos = p0 + u;
+          if (pos >= lo && pos < hi) {
+            if (ADD)
+              o[pos] += (TO)acc[4 * k + u][i];
+            else
+              o[pos] = (TO)acc[4 * k + u][i];
+          }
+        }
       }
     }
   }
@@ -447,7 +477,8 @@ static void launch_prolong_mfma(const TW* W, int64_t w_ld, int n, const float* e
                                 const int* active, const int* qlist, TO* out, int64_t o_ld,
                                 int lo, int hi, hipStream_t s) {
   constexpr int TP = 16;
-  const int runs = (hi - lo + 16 * TP - 1) / (16 * TP);
+  static_assert(TP % 4 == 0, "four MFMA blocks per vector access");
+  const int runs = (hi - (lo & ~3) + 16 * TP - 1) / (16 * TP);
   const int qgroups = (B + 63) / 64;
   hipLaunchKernelGGL((k_prolong_mfma<TW, TO, TP, ADD>), dim3(runs * qgroups), dim3(256), 0, s, W,
                      w_ld, n, e, e_ld, B, active, qlist, out, o_ld, lo, hi, qgroups);
