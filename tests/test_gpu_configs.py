@@ -11,7 +11,8 @@ in test_gpu_fullsize.py):
     large for the oracle's solver, so checked by properties that hold at any size.
     The basis is the 80 smoothest discrete sine modes (orthonormal on the grid), which
     the greedy would take minutes to match; every query converges, and sampled
-    solutions satisfy the residual bound under the oracle's own operator.
+    solutions satisfy the residual bound under the oracle's own operator;
+  * the uneven batch (four grids, four basis sizes, one call), on 256 of its queries.
 """
 import math
 
@@ -131,3 +132,46 @@ def test_large_configuration_properties(lib, ctx):
     print(f"255^3, n = 80, B = 64: iterations {st.iters.min()}..{st.iters.max()}")
     del x, basis
     torch.cuda.empty_cache()
+
+
+def test_uneven_configuration(lib, ctx):
+    """The uneven batch's four grids (63^2, 255^2, 1023^2 with 4x4 kappa blocks, 63^3 with
+    2x2x2; mu log-uniform in [0.01, 100]) and basis sizes 10, 20, 40, 60 mixed in one call
+    with the benchmark's options (FP32 preconditioner, flexible beta, HIP graphs,
+    floor_factor 16, 1e-9 on 1023^2), 256 of its 1024 queries: every query meets its
+    tolerance or is accepted at the rounding level, and sampled queries on the 63^2 and
+    63^3 grids match the oracle's RBCG with the same leading basis vectors (solutions
+    within 2 kappa rtol of each other)."""
+    import torch
+    from workloads import UNEVEN_GRIDS, uneven_batch
+    probs, bases = [], []
+    for wk in UNEVEN_GRIDS:
+        pr = lib.Problem(ctx, wk.dims, wk.blocks)
+        tr = wk.train_mu()
+        b, _ = lib.offline_build(ctx, pr, tr, mu=tr, n_max=60, indicator="l1",
+                                 snapshot_maxit=100000, snapshot_rtol=wk.rtol)
+        probs.append(pr)
+        bases.append(b)
+    qs = uneven_batch(count=256)
+    xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda") for g, _, _ in qs]
+    queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
+    opts = lib.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0)
+    st = lib.solve_multi(ctx, probs, bases, queries, opts=opts)
+    tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
+    assert (st.status == lib.RB_OK).all()
+    assert ((st.rel_res_true <= tol) | (st.at_floor == 1)).all()
+    assert (st.rel_res_true[st.at_floor == 1] <= 1e-7).all()
+    # sampled queries of the small grids against the oracle (same basis, same n_use)
+    names = [wk.name for wk in UNEVEN_GRIDS]
+    want = [("u2d63", 10), ("u2d63", 60), ("u3d63", 60)]
+    picked = [next(k for k, (g, nu, _) in enumerate(qs) if (names[g], nu) == c) for c in want]
+    for k in picked:
+        g, nu, _ = qs[k]
+        wk = UNEVEN_GRIDS[g]
+        op = BlockDiffusion(wk.dims, wk.blocks)
+        Wn, AN, fN = bases[g].info()
+        W = np.ascontiguousarray(Wn[:nu].T)
+        ref = orb.solve_rbcg(op, qs[k][2], W, AN[:, :nu, :nu], flexible=True, rtol=wk.rtol,
+                             maxit=10000)
+        assert ref.converged
+        assert _rel(xs[k].cpu().numpy(), ref.x) <= 2 * _kappa_bound(wk.dims, qs[k][2]) * wk.rtol
