@@ -1209,9 +1209,12 @@ void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, c
 // suit them (not 3D, or more partial sums than the chunked passes produce).
 static bool z_plan(const StencilGeom& g, int groups, ZTile& zt) {
   if (g.dim != 3) return false;
-  zt.zc = g.nx <= 128 ? g.nx : 128;
+  // full rows while one thread per halo cell suffices: a tile as wide as the grid has no
+  // valid halo columns, so only its two halo rows need threads
+  zt.zc = 2 * g.nx <= kZThreads ? g.nx : 128;
   zt.zr = std::min(g.ny, (kZThreads * kZNodes) / zt.zc);
-  if (zt.zr < 1 || 2 * (zt.zc + zt.zr) > kZThreads) return false;
+  const int halo = zt.zc == g.nx ? 2 * zt.zc : 2 * (zt.zc + zt.zr);
+  if (zt.zr < 1 || halo > kZThreads) return false;
   zt.ct = (g.nx + zt.zc - 1) / zt.zc;
   zt.rt = (g.ny + zt.zr - 1) / zt.zr;
   const int tiles2 = zt.rt * zt.ct;
