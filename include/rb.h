@@ -271,6 +271,9 @@ typedef struct {
   double lr;             /* default 1e-3 */
   double mu_lo, mu_hi;   /* log range of mu for the features */
   uint64_t seed;
+  rb_prec snapshot_prec; /* preconditioner of the snapshot solves: RB_PREC_FP64 (default)
+                          * or RB_PREC_FP32 (an FP32 copy of the basis grown column by
+                          * column; the CG, its stopping test and Gram-Schmidt stay FP64) */
 } rb_greedy_opts;
 void rb_greedy_opts_default(rb_greedy_opts* opts);
 

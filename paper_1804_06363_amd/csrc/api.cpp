@@ -119,13 +119,22 @@ using namespace rb;
 
 static int64_t align_ld(int64_t N) { return (N + 63) / 64 * 64; }
 
+// The shadow has room for `cap` columns (zero beyond n); columns are converted once,
+// when they first exist, so a basis growing in place (the greedy) costs one column each.
 const void* rb_basis::shadow(rb_prec prec) {
   if (prec == RB_PREC_FP64) return W64.p;
-  DevBuf& dst = prec == RB_PREC_FP32 ? W32 : W16;
+  const bool f32 = prec == RB_PREC_FP32;
+  DevBuf& dst = f32 ? W32 : W16;
+  int& done = f32 ? n32 : n16;
+  const size_t es = f32 ? sizeof(float) : sizeof(uint16_t);
   if (!dst.p) {
-    const size_t es = prec == RB_PREC_FP32 ? sizeof(float) : sizeof(uint16_t);
-    dst.alloc(es * ((size_t)basis_rows(n) * ld + kBasisTail));
-    if (n > 0) launch_cast(W64.as<double>(), dst.p, (int64_t)n * ld, prec, ctx->stream);
+    dst.alloc(es * ((size_t)basis_rows(std::max(cap, n)) * ld + kBasisTail));
+    done = 0;
+  }
+  if (done < n) {
+    launch_cast(W64.as<double>() + (size_t)done * ld, static_cast<char*>(dst.p) + es * done * ld,
+                (int64_t)(n - done) * ld, prec, ctx->stream);
+    done = n;
   }
   return dst.p;
 }

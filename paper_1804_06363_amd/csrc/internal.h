@@ -228,10 +228,12 @@ struct rb_basis {
   rb_ctx* ctx = nullptr;
   const rb_problem* prob = nullptr;
   int n = 0;
+  int cap = 0;      // columns W64 has room for (n_max while the greedy grows it)
   int64_t ld = 0;
   rb::DevBuf W64;   // double [n][ld] storage order
-  rb::DevBuf W32;   // float  [n][ld] shadow (lazily)
-  rb::DevBuf W16;   // bf16   [n][ld] shadow (lazily)
+  rb::DevBuf W32;   // float  [n][ld] shadow (built on first use, extended as n grows)
+  rb::DevBuf W16;   // bf16   [n][ld] shadow (likewise)
+  int n32 = 0, n16 = 0;  // columns converted into W32 / W16
   rb::DevBuf AN;    // double [Q][n][n]
   rb::DevBuf fN;    // double [R][n]
   std::vector<double> AN_host, fN_host;

@@ -57,6 +57,7 @@ GreedyState::GreedyState(rb_ctx* c, const rb_problem* p, const rb_greedy_opts& o
   bs->n = 0;
   bs->ld = p->ld;
   bs->W64.alloc(sizeof(double) * ((size_t)basis_rows(o.n_max) * p->ld + kBasisTail));
+  bs->cap = o.n_max;
   w.alloc(sizeof(double) * p->ld);
   const int ncN = stencil_chunks_all(p->g.N);
   part.alloc(sizeof(double) * (size_t)std::max(ncN, 1) * 8);
@@ -81,14 +82,16 @@ double GreedyState::norm(const double* v) {
   return std::sqrt(s);
 }
 
-// Snapshot solve of Alg. 4: RBCG with the current basis, FP64.  Returns its iteration
-// count; the solution (storage order) is left in `w`.
+// Snapshot solve of Alg. 4: RBCG with the current basis (FP64 CG; the preconditioner in
+// opt.snapshot_prec).  Returns its iteration count; the solution (storage order) is left
+// in `w`.
 int GreedyState::snapshot(int mu) {
   rb_solve_opts so;
   rb_solve_opts_default(&so);
   so.rtol = opt.snapshot_rtol;
   so.maxit = opt.snapshot_maxit;
   so.beta_flexible = opt.snapshot_flexible;
+  so.precond_prec = opt.snapshot_prec;
   const double* th = theta_h.data() + (size_t)mu * prob->g.Q;
   const double* ph = phi_h.empty() ? nullptr : phi_h.data() + (size_t)mu * prob->R;
   BatchSolver s(ctx, prob, bs.get(), so, 1, th, ph, nullptr);
@@ -130,9 +133,7 @@ bool GreedyState::orthonormalize_append() {
   const double nw = norm(w.as<double>());
   if (!(nw >= 1e-12 * nx)) return false;
   launch_scale(bs->W64.as<double>() + (size_t)n * p->ld, w.as<double>(), p->ld, 1.0 / nw, st);
-  bs->n = n + 1;
-  bs->W32.release();
-  bs->W16.release();
+  bs->n = n + 1;  // a reduced-precision copy picks the new column up on its next use
   compute_reduced(bs.get(), n);
   return true;
 }
@@ -261,6 +262,7 @@ extern "C" void rb_greedy_opts_default(rb_greedy_opts* o) {
   o->mu_lo = 0.1;
   o->mu_hi = 10.0;
   o->seed = 1234;
+  o->snapshot_prec = RB_PREC_FP64;
 }
 
 extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
@@ -271,6 +273,8 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
     RB_REQUIRE(ctx && prob && opts && theta && out, RB_EINVAL, "null argument");
     RB_REQUIRE(opts->struct_size == sizeof(rb_greedy_opts), RB_EINVAL,
                "rb_greedy_opts.struct_size mismatch");
+    RB_REQUIRE(opts->snapshot_prec == RB_PREC_FP64 || opts->snapshot_prec == RB_PREC_FP32,
+               RB_EINVAL, "snapshot_prec must be FP64 or FP32");
     RB_REQUIRE(M >= 1 && M < (1 << 30), RB_EINVAL, "bad training-set size");
     RB_REQUIRE(opts->n_max >= 1 && opts->n_max <= 80, RB_EINVAL, "n_max must be 1..80");
     RB_REQUIRE(opts->seed_index >= 0 && opts->seed_index < M, RB_EINVAL, "bad seed_index");
@@ -355,6 +359,8 @@ extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* pro
     RB_REQUIRE(ctx && prob && opts && theta && out, RB_EINVAL, "null argument");
     RB_REQUIRE(opts->struct_size == sizeof(rb_greedy_opts), RB_EINVAL,
                "rb_greedy_opts.struct_size mismatch");
+    RB_REQUIRE(opts->snapshot_prec == RB_PREC_FP64 || opts->snapshot_prec == RB_PREC_FP32,
+               RB_EINVAL, "snapshot_prec must be FP64 or FP32");
     RB_REQUIRE(K >= 1 && K <= 80, RB_EINVAL, "K must be 1..80");
     for (int64_t i = 0; i < (int64_t)K * prob->g.Q; ++i)
       RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");

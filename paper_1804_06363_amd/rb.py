@@ -71,7 +71,7 @@ class GreedyOpts(C.Structure):
                 ("use_surrogate", C.c_int), ("topk", C.c_int), ("explore", C.c_int),
                 ("full_sweep_every", C.c_int), ("warmup_full_sweeps", C.c_int),
                 ("train_steps", C.c_int), ("lr", C.c_double), ("mu_lo", C.c_double),
-                ("mu_hi", C.c_double), ("seed", C.c_uint64)]
+                ("mu_hi", C.c_double), ("seed", C.c_uint64), ("snapshot_prec", C.c_int)]
 
 
 class GreedyReport(C.Structure):
@@ -438,6 +438,8 @@ def greedy_opts(**kw):
     for k, v in kw.items():
         if k == "indicator":
             v = INDICATOR[v]
+        elif k == "snapshot_prec":
+            v = PREC[v]
         setattr(o, k, v)
     return o
 

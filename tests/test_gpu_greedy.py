@@ -36,6 +36,30 @@ def test_greedy_matches_oracle(lib, ctx, indicator, dims, blocks):
     assert rep["true_evals"] == n_max * len(mus)
 
 
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3))])
+def test_greedy_fp32_snapshots(lib, ctx, dims, blocks):
+    """Snapshot solves preconditioned in FP32 (the basis's FP32 copy grows a column per
+    step; CG, stopping test and Gram-Schmidt in FP64): the oracle's picks, the basis
+    within 1e-7, and the grown FP32 copy serves a later FP32 solve as a fresh one does."""
+    op = BlockDiffusion(dims, blocks)
+    mus = log_uniform_mu(80, 24, op.Q, 0.1, 10.0)
+    n_max = 5
+    ref = og.adaptive_greedy(op, mus, n_max, indicator="residual", snapshot_rtol=1e-12)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis, rep = lib.offline_build(ctx, prob, mus, mu=mus, n_max=n_max, indicator="residual",
+                                   snapshot_rtol=1e-12, snapshot_prec="fp32")
+    assert rep["picks"] == ref.picks
+    W, AN, fN = basis.info()
+    for j in range(n_max):
+        assert np.linalg.norm(W[j] - ref.W[:, j]) <= 1e-7
+    theta = log_uniform_mu(81, 3, op.Q, 0.1, 10.0)
+    x1, _ = lib.solve_batch(ctx, prob, basis, theta, prec="fp32", fixed_iters=5)
+    fresh = lib.Basis.from_host(ctx, prob, W)
+    x2, _ = lib.solve_batch(ctx, prob, fresh, theta, prec="fp32", fixed_iters=5)
+    x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+    assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x2).max()
+
+
 def test_greedy_degenerate_candidate_is_skipped(lib, ctx):
     """A duplicated parameter gives a snapshot already in span(W): the greedy must skip
     it (RB_EDEGENERATE inside) and take the next candidate."""
