@@ -274,6 +274,9 @@ typedef struct {
   rb_prec snapshot_prec; /* preconditioner of the snapshot solves: RB_PREC_FP64 (default)
                           * or RB_PREC_FP32 (an FP32 copy of the basis grown column by
                           * column; the CG, its stopping test and Gram-Schmidt stay FP64) */
+  rb_prec surrogate_prec; /* the network's products: RB_PREC_BF16 (default; BF16 operands,
+                           * FP32 accumulation) or RB_PREC_FP32; master weights and Adam
+                           * moments are FP32 either way */
 } rb_greedy_opts;
 void rb_greedy_opts_default(rb_greedy_opts* opts);
 
@@ -321,6 +324,51 @@ rb_status rb_mlp_loss_grad(rb_ctx* ctx, int P, int H, rb_prec prec, const float*
  * params, updated in place; loss = loss after the last step. */
 rb_status rb_mlp_train(rb_ctx* ctx, int P, int H, rb_prec prec, float* params, int m,
                        const float* X, const float* y, int steps, double lr, float* loss);
+/* One surrogate-ranked greedy step from a given state (the step rb_offline_build takes
+ * with use_surrogate after each basis vector), for parity tests of the protocol.  The
+ * basis (n >= 1 columns) is the greedy's current W_N; theta [M][Q] and mu [M][P] the
+ * training set (R = 1); excluded [M] flags the candidates already picked; params
+ * [H*P + H*H + 3H + 1] (H = 128, packing as rb_mlp_forward) the FP32 master weights,
+ * overwritten with the weights after the step's training (Adam moments start at zero);
+ * the replay buffer holds nbuf entries (candidate buf_index[i], target buf_target[i] =
+ * log10 indicator, greedy step buf_step[i]).  Options used: indicator, topk, explore,
+ * warmup_full_sweeps, full_sweep_every, train_steps, lr, mu_lo, mu_hi, seed,
+ * surrogate_prec.  The step:
+ *  - is a full sweep (the plain greedy's sweep and argmax) if step <= warmup_full_sweeps
+ *    or step is a multiple of full_sweep_every;
+ *  - otherwise ranks every candidate with the network, evaluates the true indicator on
+ *    the top-K unpicked candidates (written to topk in increasing index order, ties at
+ *    the K-th value to the lower index) and on `explore` further unpicked candidates
+ *    drawn uniformly (index floor(u M), u the counter's next value; redrawn when picked
+ *    or listed; at most 100 * explore draws; written to explore in draw order); if at
+ *    least 3 were explored and the Spearman rank correlation of prediction and
+ *    log10(true indicator) over them is below 0.5 it falls back to a full sweep, else
+ *    picks the argmax of the true indicator over the short list (ties: lower index);
+ *  - appends every evaluated unpicked candidate with a positive finite indicator to
+ *    the buffer, keeps the entries of the last two steps, standardises the targets and
+ *    runs train_steps Adam steps on minibatches of min(256, size) entries drawn with
+ *    replacement (entry floor(u size)).
+ * The not-in-the-paper protocol is the library's own; the paper's greedy (Alg. 4,
+ * Sec. 4.2) is what its full sweeps compute. */
+typedef struct {
+  size_t struct_size;  /* sizeof(rb_surrogate_io) */
+  int step;            /* in: greedy step k >= 1 (basis vectors added so far) */
+  uint64_t counter;    /* in/out: position in the counter sequence of opts->seed (a fresh
+                        * surrogate starts at H*P + H*H + H, after its initial weights) */
+  int full_sweep;      /* out: 1 if every candidate was evaluated */
+  int fallback;        /* out: 1 if the ranking check failed */
+  int n_topk, n_explore; /* out: entries written to topk / explore */
+  int64_t pick;        /* out: next sample, -1 if no candidate is left */
+  double value;        /* out: its true indicator */
+  int64_t true_evals;  /* out: true indicator evaluations of this step */
+  float loss;          /* out: training loss of the last Adam step (0 if none) */
+} rb_surrogate_io;
+rb_status rb_surrogate_step(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
+                            const rb_greedy_opts* opts, int64_t M, int P, const double* mu,
+                            const double* theta, const int32_t* excluded, float* params,
+                            int nbuf, const int32_t* buf_index, const float* buf_target,
+                            const int32_t* buf_step, int32_t* topk, int32_t* explore,
+                            rb_surrogate_io* io);
 /* Indices of the K largest v[m] among the entries with excluded[m] == 0 (excluded may be
  * NULL), as a set: ties at the K-th value go to the lowest indices.  out [>= K] host,
  * count = number written (min(K, available)). */

@@ -99,15 +99,6 @@ static rb_status guarded(F&& f) {
   }
 }
 
-struct DeviceGuard {
-  int old = 0;
-  explicit DeviceGuard(int dev) {
-    (void)hipGetDevice(&old);
-    if (old != dev) RB_HIP(hipSetDevice(dev));
-  }
-  ~DeviceGuard() { (void)hipSetDevice(old); }
-};
-
 static void check_finite(const double* v, size_t n, const char* what) {
   for (size_t i = 0; i < n; ++i)
     RB_REQUIRE(std::isfinite(v[i]), RB_EINVAL, std::string(what) + " contains NaN or Inf");
@@ -121,7 +112,10 @@ static int64_t align_ld(int64_t N) { return (N + 63) / 64 * 64; }
 
 // The shadow has room for `cap` columns (zero beyond n); columns are converted once,
 // when they first exist, so a basis growing in place (the greedy) costs one column each.
-const void* rb_basis::shadow(rb_prec prec) {
+// The conversion runs on the consumer's stream; a consumer on another stream (a group
+// of rb_solve_multi, another context) waits for the latest conversion's event, so it
+// never reads a half-converted shadow.
+const void* rb_basis::shadow(rb_prec prec, hipStream_t consumer) {
   if (prec == RB_PREC_FP64) return W64.p;
   const bool f32 = prec == RB_PREC_FP32;
   DevBuf& dst = f32 ? W32 : W16;
@@ -132,9 +126,16 @@ const void* rb_basis::shadow(rb_prec prec) {
     done = 0;
   }
   if (done < n) {
+    if (cast_done && cast_stream != consumer)
+      RB_HIP(hipStreamWaitEvent(consumer, cast_done, 0));  // earlier columns' writers
     launch_cast(W64.as<double>() + (size_t)done * ld, static_cast<char*>(dst.p) + es * done * ld,
-                (int64_t)(n - done) * ld, prec, ctx->stream);
+                (int64_t)(n - done) * ld, prec, consumer);
     done = n;
+    if (!cast_done) RB_HIP(hipEventCreateWithFlags(&cast_done, hipEventDisableTiming));
+    RB_HIP(hipEventRecord(cast_done, consumer));
+    cast_stream = consumer;
+  } else if (cast_done && cast_stream != consumer) {
+    RB_HIP(hipStreamWaitEvent(consumer, cast_done, 0));
   }
   return dst.p;
 }
@@ -865,6 +866,7 @@ rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
     oo.solver = RB_SOLVER_RBCG;
     oo.beta_flexible = 0;
     BatchSolver s(ctx, p, bs, oo, B, theta, nullptr, n_use);
+    s.prepare();
     hipStream_t st = ctx->stream;
     launch_to_storage(*p, B, r, p->N, s.r0.as<double>(), p->ld, st);
     s.factor();
@@ -899,7 +901,7 @@ rb_status rb_project_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
     DevBuf part(acc * (size_t)pl.chunks * B * pl.nj);
     DevBuf ones(sizeof(int) * B);
     launch_fill<int>(ones.as<int>(), 0, B, 1, 1, st);
-    const void* W = const_cast<rb_basis*>(bs)->shadow(prec);
+    const void* W = const_cast<rb_basis*>(bs)->shadow(prec, st);
     launch_projection(pl, prec, rs.as<double>(), p->ld, W, p->ld, n, B, ones.as<int>(), part.p, st);
     DevBuf td(sizeof(double) * (size_t)B * n);
     launch_reduce_solve(prec == RB_PREC_FP64, part.p, pl.chunks, B, pl.nj, n, nullptr, nullptr,

@@ -49,6 +49,17 @@ struct DevBuf {
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
+// Makes `dev` the calling thread's current device for the guard's lifetime and restores
+// the previous one on every exit path (including exceptions).
+struct DeviceGuard {
+  int old = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&old);
+    if (old != dev) RB_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(old); }
+};
+
 }  // namespace rb
 
 // ---- stencil geometry (device-side view) --------------------------------------
@@ -144,7 +155,7 @@ TuneConfig stencil_tiles();
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
   WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_QLIST, WS_FB, WS_PHI,
-  WS_GATHER, WS_COUNT
+  WS_GATHER, WS_ONES, WS_COUNT
 };
 }  // namespace rb
 
@@ -238,7 +249,19 @@ struct rb_basis {
   rb::DevBuf fN;    // double [R][n]
   std::vector<double> AN_host, fN_host;
   std::vector<int64_t> picks;
-  const void* shadow(rb_prec prec);
+  // the latest cast into a shadow and the stream it ran on: a consumer on another
+  // stream waits for it
+  hipEvent_t cast_done = nullptr;
+  hipStream_t cast_stream = nullptr;
+  // the basis in precision `prec` for kernels issued on `consumer` (converting the
+  // columns not converted yet, stream-ordered before the consumer's later work)
+  const void* shadow(rb_prec prec, hipStream_t consumer);
+  rb_basis() = default;
+  rb_basis(const rb_basis&) = delete;
+  rb_basis& operator=(const rb_basis&) = delete;
+  ~rb_basis() {
+    if (cast_done) (void)hipEventDestroy(cast_done);
+  }
 };
 
 namespace rb {

@@ -13,6 +13,9 @@
 //    full sweep;
 //  - the replay buffer keeps the pairs of the last two steps (the indicator shrinks as
 //    N grows) and `train_steps` Adam steps on minibatches of 256 follow.
+// Random numbers: one counter-based SplitMix64 sequence (seed opts.seed); the initial
+// weights take its first H P + H H + H values, the exploration and minibatch draws
+// continue from there.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -83,15 +86,16 @@ struct Surrogate::Impl {
     int step;
   };
   std::vector<Entry> buf;
-  uint64_t seed, ctr = 0;
-  Impl(int P, int M, hipStream_t st, uint64_t s)
-      : net(P, kHidden, true, std::max(M, kMinibatch), st), seed(s) {}
+  uint64_t seed, ctr;
+  Impl(int P, int M, bool bf16, hipStream_t st, uint64_t s)
+      : net(P, kHidden, bf16, std::max(M, kMinibatch), st), seed(s),
+        ctr((uint64_t)kHidden * P + (uint64_t)kHidden * kHidden + kHidden) {}
 };
 
 Surrogate::Surrogate(GreedyState& g, const double* mu, int P_) : gs(g), P(P_) {
   hipStream_t st = gs.ctx->stream;
   const int M = gs.M;
-  impl = std::make_unique<Impl>(P, M, st, gs.opt.seed);
+  impl = std::make_unique<Impl>(P, M, gs.opt.surrogate_prec != RB_PREC_FP32, st, gs.opt.seed);
   RB_REQUIRE(gs.opt.mu_lo > 0 && gs.opt.mu_hi > gs.opt.mu_lo, RB_EINVAL, "bad mu range");
   const double l0 = std::log10(gs.opt.mu_lo), l1 = std::log10(gs.opt.mu_hi);
   DevBuf mud(sizeof(double) * (size_t)M * P);
@@ -110,12 +114,31 @@ Surrogate::Surrogate(GreedyState& g, const double* mu, int P_) : gs(g), P(P_) {
 }
 Surrogate::~Surrogate() = default;
 
+void Surrogate::set_state(const float* params, int nbuf, const int32_t* idx, const float* target,
+                          const int32_t* step, uint64_t counter) {
+  impl->net.set_params(params);
+  impl->buf.clear();
+  for (int i = 0; i < nbuf; ++i) {
+    RB_REQUIRE(idx[i] >= 0 && idx[i] < gs.M && std::isfinite(target[i]), RB_EINVAL,
+               "bad replay-buffer entry");
+    impl->buf.push_back({idx[i], target[i], step[i]});
+  }
+  impl->ctr = counter;
+  RB_HIP(hipStreamSynchronize(gs.ctx->stream));
+}
+void Surrogate::get_params(float* params) { impl->net.get_params(params); }
+uint64_t Surrogate::counter() const { return impl->ctr; }
+int Surrogate::param_count() const { return impl->net.count; }
+
 int Surrogate::step(int k, double* value) {
   Impl& im = *impl;
   hipStream_t st = gs.ctx->stream;
   const int M = gs.M;
   const rb_greedy_opts& o = gs.opt;
   bool full = k <= o.warmup_full_sweeps || (o.full_sweep_every > 0 && k % o.full_sweep_every == 0);
+  last_topk.clear();
+  last_explore.clear();
+  last_fallback = false;
   std::vector<int> eval;
   int pick = -1;
   double v = 0.0;
@@ -133,6 +156,8 @@ int Surrogate::step(int k, double* value) {
     RB_HIP(hipStreamSynchronize(st));
     eval.resize(cnt);
     if (cnt) RB_HIP(hipMemcpy(eval.data(), im.topk_out.p, sizeof(int) * cnt, hipMemcpyDeviceToHost));
+    std::sort(eval.begin(), eval.end());  // the top-K set in increasing index order
+    last_topk = eval;
     std::vector<char> in(M, 0);
     for (int m : eval) in[m] = 1;
     // exploration: uniformly random unpicked candidates outside the top-K
@@ -144,8 +169,12 @@ int Surrogate::step(int k, double* value) {
       in[m] = 1;
       expl.push_back(m);
     }
+    last_explore = expl;
     eval.insert(eval.end(), expl.begin(), expl.end());
-    if (eval.empty()) return -1;
+    if (eval.empty()) {
+      last_full = false;
+      return -1;
+    }
     gs.sweep(eval);  // true indicator on the short list
     // reliability of the ranking on the exploration sample
     std::vector<double> pe, te;
@@ -155,6 +184,7 @@ int Surrogate::step(int k, double* value) {
     }
     if ((int)expl.size() >= 3 && spearman(pe, te) < 0.5) {
       full = true;
+      last_fallback = true;
       ++fallbacks;
     } else {
       // the pick: argmax of the true indicator among the evaluated candidates
@@ -164,6 +194,7 @@ int Surrogate::step(int k, double* value) {
       pick = gs.pick(&v);
     }
   }
+  last_full = full;
   if (full) {
     gs.sweep({});
     gs.full_sweeps++;
@@ -242,6 +273,7 @@ extern "C" rb_status rb_mlp_forward(rb_ctx* ctx, int P, int H, rb_prec prec, con
   return mlp_guard([&] {
     check_mlp_args(ctx, P, H, prec, params, m);
     RB_REQUIRE(X && out, RB_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
     hipStream_t st = ctx->stream;
     MLP net(P, H, prec == RB_PREC_BF16, m, st);
     net.set_params(params);
@@ -259,6 +291,7 @@ extern "C" rb_status rb_mlp_loss_grad(rb_ctx* ctx, int P, int H, rb_prec prec, c
   return mlp_guard([&] {
     check_mlp_args(ctx, P, H, prec, params, m);
     RB_REQUIRE(X && y && loss && grad, RB_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
     hipStream_t st = ctx->stream;
     MLP net(P, H, prec == RB_PREC_BF16, m, st);
     net.set_params(params);
@@ -277,6 +310,7 @@ extern "C" rb_status rb_mlp_train(rb_ctx* ctx, int P, int H, rb_prec prec, float
   return mlp_guard([&] {
     check_mlp_args(ctx, P, H, prec, params, m);
     RB_REQUIRE(X && y && steps >= 0 && lr > 0, RB_EINVAL, "bad arguments");
+    DeviceGuard dg(ctx->device);
     hipStream_t st = ctx->stream;
     MLP net(P, H, prec == RB_PREC_BF16, m, st);
     net.set_params(params);
@@ -295,10 +329,70 @@ extern "C" rb_status rb_mlp_train(rb_ctx* ctx, int P, int H, rb_prec prec, float
   });
 }
 
+extern "C" rb_status rb_surrogate_step(rb_ctx* ctx, const rb_problem* prob, const rb_basis* basis,
+                                       const rb_greedy_opts* opts, int64_t M, int P,
+                                       const double* mu, const double* theta,
+                                       const int32_t* excluded, float* params, int nbuf,
+                                       const int32_t* buf_index, const float* buf_target,
+                                       const int32_t* buf_step, int32_t* topk, int32_t* explore,
+                                       rb_surrogate_io* io) {
+  return mlp_guard([&] {
+    RB_REQUIRE(ctx && prob && basis && opts && mu && theta && excluded && params && io,
+               RB_EINVAL, "null argument");
+    RB_REQUIRE(opts->struct_size == sizeof(rb_greedy_opts), RB_EINVAL,
+               "rb_greedy_opts.struct_size mismatch");
+    RB_REQUIRE(io->struct_size == sizeof(rb_surrogate_io), RB_EINVAL,
+               "rb_surrogate_io.struct_size mismatch");
+    RB_REQUIRE(basis->prob == prob && basis->n >= 1, RB_EINVAL,
+               "need a non-empty basis of this problem");
+    RB_REQUIRE(M >= 1 && M < (1 << 30) && P >= 1 && P <= 64, RB_EINVAL, "bad M or P");
+    RB_REQUIRE(io->step >= 1, RB_EINVAL, "step must be >= 1");
+    RB_REQUIRE(opts->topk >= 0 && opts->explore >= 0 && opts->train_steps >= 0, RB_EINVAL,
+               "bad surrogate options");
+    RB_REQUIRE((opts->topk == 0 || topk) && (opts->explore == 0 || explore), RB_EINVAL,
+               "topk / explore outputs missing");
+    RB_REQUIRE(nbuf >= 0 && (nbuf == 0 || (buf_index && buf_target && buf_step)), RB_EINVAL,
+               "bad replay buffer");
+    RB_REQUIRE(opts->indicator == RB_IND_L1 || prob->R == 1, RB_EUNSUPPORTED,
+               "residual indicator needs R = 1");
+    RB_REQUIRE(opts->surrogate_prec == RB_PREC_BF16 || opts->surrogate_prec == RB_PREC_FP32,
+               RB_EINVAL, "surrogate_prec must be BF16 or FP32");
+    RB_REQUIRE(opts->mu_lo > 0 && opts->mu_hi > opts->mu_lo, RB_EINVAL, "bad mu range");
+    for (int64_t i = 0; i < M * prob->g.Q; ++i)
+      RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");
+    DeviceGuard dg(ctx->device);
+    rb_greedy_opts o = *opts;
+    o.n_max = basis->n;
+    o.use_surrogate = 1;
+    GreedyState gs(ctx, prob, o, M, theta, nullptr);
+    gs.adopt(basis);
+    for (int64_t m = 0; m < M; ++m) gs.excl_h[m] = excluded[m] ? 1 : 0;
+    Surrogate sur(gs, mu, P);
+    sur.set_state(params, nbuf, buf_index, buf_target, buf_step, io->counter);
+    double v = 0.0;
+    const int pick = sur.step(io->step, &v);
+    std::vector<float> out((size_t)sur.param_count());
+    sur.get_params(out.data());
+    std::copy(out.begin(), out.end(), params);
+    std::copy(sur.last_topk.begin(), sur.last_topk.end(), topk);
+    std::copy(sur.last_explore.begin(), sur.last_explore.end(), explore);
+    io->counter = sur.counter();
+    io->full_sweep = sur.last_full ? 1 : 0;
+    io->fallback = sur.last_fallback ? 1 : 0;
+    io->n_topk = (int)sur.last_topk.size();
+    io->n_explore = (int)sur.last_explore.size();
+    io->pick = pick;
+    io->value = v;
+    io->true_evals = gs.true_evals;
+    io->loss = sur.last_loss;
+  });
+}
+
 extern "C" rb_status rb_topk(rb_ctx* ctx, int M, int K, const float* v, const int* excluded,
                              int* out, int* count) {
   return mlp_guard([&] {
     RB_REQUIRE(ctx && v && out && count && M >= 1 && K >= 0, RB_EINVAL, "bad arguments");
+    DeviceGuard dg(ctx->device);
     hipStream_t st = ctx->stream;
     DevBuf vd(sizeof(float) * M), ed(sizeof(int) * M), od(sizeof(int) * M), cd(sizeof(int) * 4);
     RB_HIP(hipMemcpyAsync(vd.p, v, vd.bytes, hipMemcpyHostToDevice, st));

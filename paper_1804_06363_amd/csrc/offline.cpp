@@ -71,6 +71,27 @@ GreedyState::GreedyState(rb_ctx* c, const rb_problem* p, const rb_greedy_opts& o
   for (double v : ph) fnorm2 += v;
 }
 
+void GreedyState::adopt(const rb_basis* src) {
+  RB_REQUIRE(src->prob == prob, RB_EINVAL, "basis belongs to another problem");
+  RB_REQUIRE(src->n <= opt.n_max, RB_EINVAL, "basis larger than the greedy's capacity");
+  hipStream_t st = ctx->stream;
+  if (src->n > 0)
+    RB_HIP(hipMemcpyAsync(bs->W64.p, src->W64.p, sizeof(double) * (size_t)src->n * prob->ld,
+                          hipMemcpyDeviceToDevice, st));
+  bs->n = src->n;
+  bs->AN_host = src->AN_host;
+  bs->fN_host = src->fN_host;
+  bs->AN.alloc(sizeof(double) * std::max<size_t>(1, bs->AN_host.size()));
+  bs->fN.alloc(sizeof(double) * std::max<size_t>(1, bs->fN_host.size()));
+  if (!bs->AN_host.empty())
+    RB_HIP(hipMemcpyAsync(bs->AN.p, bs->AN_host.data(), sizeof(double) * bs->AN_host.size(),
+                          hipMemcpyHostToDevice, st));
+  if (!bs->fN_host.empty())
+    RB_HIP(hipMemcpyAsync(bs->fN.p, bs->fN_host.data(), sizeof(double) * bs->fN_host.size(),
+                          hipMemcpyHostToDevice, st));
+  RB_HIP(hipStreamSynchronize(st));
+}
+
 double GreedyState::norm(const double* v) {
   hipStream_t st = ctx->stream;
   const int nc = launch_dot(v, v, prob->ld, prob->g.N, 1, part.as<double>(), 4, st);
@@ -263,6 +284,7 @@ extern "C" void rb_greedy_opts_default(rb_greedy_opts* o) {
   o->mu_hi = 10.0;
   o->seed = 1234;
   o->snapshot_prec = RB_PREC_FP64;
+  o->surrogate_prec = RB_PREC_BF16;
 }
 
 extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
@@ -282,13 +304,16 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
                "bad indicator");
     RB_REQUIRE(opts->indicator == RB_IND_L1 || prob->R == 1, RB_EUNSUPPORTED,
                "residual indicator needs R = 1");
-    RB_REQUIRE(!opts->use_surrogate || (mu && P >= 1), RB_EINVAL, "surrogate needs mu");
+    RB_REQUIRE(!opts->use_surrogate || (mu && P >= 1 && P <= 64), RB_EINVAL,
+               "surrogate needs mu with 1 <= P <= 64");
+    RB_REQUIRE(opts->surrogate_prec == RB_PREC_BF16 || opts->surrogate_prec == RB_PREC_FP32,
+               RB_EINVAL, "surrogate_prec must be BF16 or FP32");
+    RB_REQUIRE(opts->topk >= 0 && opts->explore >= 0 && opts->train_steps >= 0, RB_EINVAL,
+               "bad surrogate options");
     for (int64_t i = 0; i < M * prob->g.Q; ++i)
       RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");
     const auto t0 = std::chrono::steady_clock::now();
-    int dev_old = 0;
-    (void)hipGetDevice(&dev_old);
-    RB_HIP(hipSetDevice(ctx->device));
+    DeviceGuard dg(ctx->device);
     GreedyState gs(ctx, prob, *opts, M, theta, phi);
     std::unique_ptr<Surrogate> sur;
     if (opts->use_surrogate) sur = std::make_unique<Surrogate>(gs, mu, P);
@@ -323,7 +348,6 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
       if (nxt < 0) break;
       mu_next = nxt;
     }
-    (void)hipSetDevice(dev_old);
     if (rep) {
       rep->n_built = gs.bs->n;
       for (size_t i = 0; i < picks.size() && i < (size_t)opts->n_max; ++i) {
@@ -365,9 +389,7 @@ extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* pro
     for (int64_t i = 0; i < (int64_t)K * prob->g.Q; ++i)
       RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");
     const auto t0 = std::chrono::steady_clock::now();
-    int dev_old = 0;
-    (void)hipGetDevice(&dev_old);
-    RB_HIP(hipSetDevice(ctx->device));
+    DeviceGuard dg(ctx->device);
     rb_greedy_opts o = *opts;
     o.n_max = K;
     o.use_surrogate = 0;
@@ -382,7 +404,6 @@ extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* pro
       gs.bs->picks.push_back(i);
     }
     RB_REQUIRE(gs.bs->n > 0, RB_EDEGENERATE, "every snapshot was degenerate");
-    (void)hipSetDevice(dev_old);
     if (rep) {
       rep->n_built = gs.bs->n;
       for (size_t i = 0; i < used.size(); ++i) {

@@ -17,6 +17,9 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
                          const int* n_use, hipStream_t stream, Workspace* ws)
     : ctx(c), prob(p), basis(b), opt(o), B(B_), stream_(stream ? stream : c->stream),
       ws_(ws ? ws : &c->ws) {
+  // Host-side set-up only: sizes, tile plan and the workspace views.  Nothing is issued
+  // on the stream before prepare(), so a workspace that is too small fails here, before
+  // any work.
   const StencilGeom& g = prob->g;
   const int Q = g.Q;
   if (opt.solver == RB_SOLVER_CG) {
@@ -24,14 +27,23 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     opt.precond_prec = RB_PREC_FP64;
   }
   n = basis ? basis->n : 0;
-  std::vector<int> nu(B, n);
+  nu_h.assign(B, n);
   adaptive = opt.adapt_gamma > 0.0 && opt.solver == RB_SOLVER_RBCG && n > 0;
-  if (adaptive && !n_use) std::fill(nu.begin(), nu.end(), 1);
+  if (adaptive && !n_use) std::fill(nu_h.begin(), nu_h.end(), 1);
   if (n_use && basis)
     for (int i = 0; i < B; ++i) {
       RB_REQUIRE(n_use[i] >= 0, RB_EINVAL, "n_use must be >= 0");
-      nu[i] = std::min(n_use[i], n);
+      nu_h[i] = std::min(n_use[i], n);
     }
+  theta_h.assign(theta, theta + (size_t)B * Q);
+  const int R = prob->R;
+  sc_h.assign(B, 1.0);
+  if (R == 1 && phi)
+    for (int i = 0; i < B; ++i) sc_h[i] = phi[i];
+  if (R > 1) {
+    phi_h.assign((size_t)B * R, 1.0);
+    if (phi) std::copy(phi, phi + (size_t)B * R, phi_h.begin());
+  }
   e_ld = std::max(16, (n + 15) / 16 * 16);
   y32 = opt.precond_prec != RB_PREC_FP64 && opt.solver != RB_SOLVER_RBI;
   cN = stencil_chunks_all(g.N);
@@ -50,40 +62,6 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   jsegs.off[0] = 0;
   const int64_t dot_elems = std::max<int64_t>(acc, (int64_t)B * pstride);
   const int64_t L_ = ld();
-  hipStream_t st = s();
-
-  // per-query inputs
-  theta_d = get_ws(WS_THETA, sizeof(double) * B * Q);
-  RB_HIP(hipMemcpyAsync(theta_d.p, theta, sizeof(double) * B * Q, hipMemcpyHostToDevice, st));
-  const int R = prob->R;
-  std::vector<double> sc(B, 1.0);
-  if (R == 1 && phi)
-    for (int i = 0; i < B; ++i) sc[i] = phi[i];
-  scale_d = get_ws(WS_SCALE, sizeof(double) * B);
-  RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-  nuse_d = get_ws(WS_NUSE, sizeof(int) * B);
-  RB_HIP(hipMemcpyAsync(nuse_d.p, nu.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-  if (R == 1) {
-    f_base = prob->f.as<double>();
-    f_ld = 0;
-  } else {
-    // f_b = sum_r phi_br f_r, formed on the device from the terms in storage order
-    std::vector<double> ph((size_t)B * R, 1.0);
-    if (phi) std::copy(phi, phi + (size_t)B * R, ph.begin());
-    phi_d = get_ws(WS_PHI, sizeof(double) * (size_t)B * R);
-    RB_HIP(hipMemcpyAsync(phi_d.p, ph.data(), sizeof(double) * (size_t)B * R,
-                          hipMemcpyHostToDevice, st));
-    fb = get_ws(WS_FB, sizeof(double) * (size_t)B * L_);
-    launch_combine_rhs(prob->f.as<double>(), L_, R, phi_d.as<double>(), B, g.N, fb.as<double>(),
-                       st);
-    f_base = fb.as<double>();
-    f_ld = L_;
-    std::fill(sc.begin(), sc.end(), 1.0);
-    RB_HIP(hipMemcpyAsync(scale_d.p, sc.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-  }
-
-  coef = get_ws(WS_COEF, sizeof(double) * B * g.ct_size);
-  launch_coef_tables(g, B, theta_d.as<double>(), nullptr, coef.as<double>(), st);
 
   // tile choices: cached by the autotuner for this shape, else the defaults
   {
@@ -104,7 +82,17 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     plan.padded = !plan.wsplit;
   }
   rrows = (n > 0 && plan.padded) ? plan.qgroups * 64 * plan.qt : B;
-  // state vectors
+
+  // workspace views
+  theta_d = get_ws(WS_THETA, sizeof(double) * B * Q);
+  scale_d = get_ws(WS_SCALE, sizeof(double) * B);
+  nuse_d = get_ws(WS_NUSE, sizeof(int) * B);
+  ones_d = get_ws(WS_ONES, sizeof(int) * B);
+  if (R > 1) {
+    phi_d = get_ws(WS_PHI, sizeof(double) * (size_t)B * R);
+    fb = get_ws(WS_FB, sizeof(double) * (size_t)B * L_);
+  }
+  coef = get_ws(WS_COEF, sizeof(double) * B * g.ct_size);
   const size_t vb = sizeof(double) * (size_t)B * L_;
   const size_t vr = sizeof(double) * (size_t)rrows * L_;
   x = get_ws(WS_X, vb);
@@ -122,25 +110,18 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   if (opt.floor_factor > 0.0) part_m2 = get_ws(WS_PM2, sizeof(double) * (size_t)B * pstride);
   part_r0 = get_ws(WS_PR0, sizeof(double) * (size_t)dot_elems);
   part_r1 = get_ws(WS_PR1, sizeof(double) * (size_t)dot_elems);
-
-  // reduced basis data
   if (n > 0) {
-    Wsh = const_cast<rb_basis*>(basis)->shadow(opt.precond_prec);
-    const size_t acc = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t accb = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
     // room for the largest candidate plan of the autotuner
     const ProjPlan big = plan_projection(g.N, B, n, 4096);
-    projpart = get_ws(WS_PROJ, acc * (size_t)std::max(plan.chunks, big.chunks) * B * plan.nj);
+    projpart = get_ws(WS_PROJ, accb * (size_t)std::max(plan.chunks, big.chunks) * B * plan.nj);
     L = get_ws(WS_L, sizeof(double) * (size_t)B * n * n);
-    // the prolongations read e in groups of up to 256 queries: pad and zero the rows
+    // the prolongations read e in groups of up to 256 queries: padded rows
     const int Bp = padded_queries(B);
     e64 = get_ws(WS_E64, sizeof(double) * (size_t)Bp * e_ld);
     e32 = get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
-    launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
-    launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
     qlist = get_ws(WS_QLIST, sizeof(int) * ((size_t)B + 1));
   }
-
-  // per-query scalars
   qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 6) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
@@ -149,13 +130,47 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in);
   takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
   takeI(q.at_floor);
-  launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
-  launch_fill<int>(q.at_floor, 0, (int64_t)B, 1, 0, st);
   if (adaptive) {
     q.nuse = nuse_d.as<int>();
     q.gamma2 = opt.adapt_gamma * opt.adapt_gamma;
     q.nmax = n;
   }
+}
+
+// Uploads the per-query inputs, builds the coefficient tables and the right-hand sides,
+// and sets the per-query state; every buffer a solve reads before writing is set here.
+void BatchSolver::prepare() {
+  const StencilGeom& g = prob->g;
+  const int Q = g.Q, R = prob->R;
+  const int64_t L_ = ld();
+  hipStream_t st = s();
+  RB_HIP(hipMemcpyAsync(theta_d.p, theta_h.data(), sizeof(double) * B * Q, hipMemcpyHostToDevice,
+                        st));
+  RB_HIP(hipMemcpyAsync(nuse_d.p, nu_h.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  launch_fill<int>(ones_d.as<int>(), 0, B, 1, 1, st);
+  if (R == 1) {
+    f_base = prob->f.as<double>();
+    f_ld = 0;
+  } else {
+    // f_b = sum_r phi_br f_r, formed on the device from the terms in storage order
+    RB_HIP(hipMemcpyAsync(phi_d.p, phi_h.data(), sizeof(double) * (size_t)B * R,
+                          hipMemcpyHostToDevice, st));
+    launch_combine_rhs(prob->f.as<double>(), L_, R, phi_d.as<double>(), B, g.N, fb.as<double>(),
+                       st);
+    f_base = fb.as<double>();
+    f_ld = L_;
+    std::fill(sc_h.begin(), sc_h.end(), 1.0);
+  }
+  RB_HIP(hipMemcpyAsync(scale_d.p, sc_h.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+  launch_coef_tables(g, B, theta_d.as<double>(), nullptr, coef.as<double>(), st);
+  if (n > 0) {
+    Wsh = const_cast<rb_basis*>(basis)->shadow(opt.precond_prec, st);
+    const int Bp = padded_queries(B);
+    launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
+    launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
+  }
+  launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
+  launch_fill<int>(q.at_floor, 0, (int64_t)B, 1, 0, st);
   launch_fill<int>(q.status, 0, (int64_t)B, 1, (int)RB_OK, st);
   launch_fill<int>(q.active, 0, (int64_t)B, 1, 1, st);
   launch_fill<int>(q.iters, 0, 3 * (int64_t)B, 1, 0, st);  // iters, flag, restart
@@ -438,11 +453,9 @@ void BatchSolver::final_true_residual() {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
-  DevBuf ones(sizeof(int) * B);
-  launch_fill<int>(ones.as<int>(), 0, B, 1, 1, st);
   double* tmp = r0.as<double>();
   launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), tmp, 1, f_base, f_ld,
-               scale_d.as<double>(), ones.as<int>(), part_m.as<double>(), st);
+               scale_d.as<double>(), ones_d.as<int>(), part_m.as<double>(), st);
   launch_fin_sum(part_m.as<double>(), cN, cN, q.scalar, nullptr, B, st);
   RB_HIP(hipStreamSynchronize(st));
 }
@@ -558,6 +571,7 @@ void BatchSolver::autotune() {
 }
 
 void BatchSolver::start() {
+  prepare();
   rbi_ = opt.solver == RB_SOLVER_RBI;
   set_stencil_tiles(tc);
   autotune();

@@ -31,7 +31,10 @@ struct BatchSolver {
   const void* Wsh = nullptr;   // basis in the preconditioner's precision
 
   // device buffers (views of the context's workspace)
-  Buf theta_d, scale_d, nuse_d, coef, L, e64, e32, projpart;
+  Buf theta_d, scale_d, nuse_d, ones_d, coef, L, e64, e32, projpart;
+  // host copies of the per-query inputs (uploaded by prepare())
+  std::vector<double> theta_h, phi_h, sc_h;
+  std::vector<int> nu_h;
   Buf qlist;  // active queries in increasing order, then their count (batched coarse step)
   Buf x, r0, r1, p0, p1, y, z;
   Buf part_m, part_m2, part_r0, part_r1;
@@ -56,6 +59,9 @@ struct BatchSolver {
   ~BatchSolver();
 
   hipStream_t s() const { return stream_; }
+  // uploads and per-query initial state (start() calls it; single-step users call it
+  // after construction)
+  void prepare();
   int64_t ld() const { return prob->ld; }
   // RBCG / CG
   void init_cg();

@@ -71,7 +71,15 @@ class GreedyOpts(C.Structure):
                 ("use_surrogate", C.c_int), ("topk", C.c_int), ("explore", C.c_int),
                 ("full_sweep_every", C.c_int), ("warmup_full_sweeps", C.c_int),
                 ("train_steps", C.c_int), ("lr", C.c_double), ("mu_lo", C.c_double),
-                ("mu_hi", C.c_double), ("seed", C.c_uint64), ("snapshot_prec", C.c_int)]
+                ("mu_hi", C.c_double), ("seed", C.c_uint64), ("snapshot_prec", C.c_int),
+                ("surrogate_prec", C.c_int)]
+
+
+class SurrogateIO(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("step", C.c_int), ("counter", C.c_uint64),
+                ("full_sweep", C.c_int), ("fallback", C.c_int), ("n_topk", C.c_int),
+                ("n_explore", C.c_int), ("pick", C.c_int64), ("value", C.c_double),
+                ("true_evals", C.c_int64), ("loss", C.c_float)]
 
 
 class GreedyReport(C.Structure):
@@ -126,6 +134,9 @@ _sig("rb_mlp_forward", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F])
 _sig("rb_mlp_loss_grad", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F, _F, _F])
 _sig("rb_mlp_train", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F, C.c_int, C.c_double, _F])
 _sig("rb_topk", [_P, C.c_int, C.c_int, _F, _I, _I, _I])
+_I32 = C.POINTER(C.c_int32)
+_sig("rb_surrogate_step", [_P, _P, _P, C.POINTER(GreedyOpts), C.c_int64, C.c_int, _D, _D, _I32,
+                           _F, C.c_int, _I32, _F, _I32, _I32, _I32, C.POINTER(SurrogateIO)])
 _sig("rb_greedy_opts_default", [C.POINTER(GreedyOpts)], None)
 _sig("rb_offline_build", [_P, _P, C.POINTER(GreedyOpts), C.c_int64, C.c_int, _D, _D, _D,
                           C.POINTER(_P), C.POINTER(GreedyReport)])
@@ -138,10 +149,11 @@ EXPORTED = [
     "rb_problem_create_stencil", "rb_problem_create_csr", "rb_problem_colors",
     "rb_problem_set_rhs", "rb_problem_info", "rb_problem_destroy",
     "rb_basis_from_host", "rb_basis_info", "rb_basis_save", "rb_basis_load", "rb_basis_destroy",
-    "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi", "rb_apply_batch",
+    "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi",
+    "rb_apply_batch",
     "rb_precond_batch", "rb_project_batch", "rb_reduced_factor_batch",
     "rb_greedy_opts_default", "rb_offline_build", "rb_basis_from_parameters",
-    "rb_mlp_forward", "rb_mlp_loss_grad", "rb_mlp_train", "rb_topk",
+    "rb_mlp_forward", "rb_mlp_loss_grad", "rb_mlp_train", "rb_topk", "rb_surrogate_step",
 ]
 
 
@@ -438,7 +450,7 @@ def greedy_opts(**kw):
     for k, v in kw.items():
         if k == "indicator":
             v = INDICATOR[v]
-        elif k == "snapshot_prec":
+        elif k in ("snapshot_prec", "surrogate_prec"):
             v = PREC[v]
         setattr(o, k, v)
     return o
@@ -531,3 +543,34 @@ def topk(ctx, v, K, excluded=None):
     _check(_lib.rb_topk(ctx.h, M, K, _fptr(v), ex.ctypes.data_as(_I) if ex is not None else None,
                         out.ctypes.data_as(_I), C.byref(cnt)))
     return out[:cnt.value]
+
+
+def surrogate_step(ctx, prob, basis, theta, mu, excluded, params, step, counter,
+                   buffer=(), **kw):
+    """One surrogate-ranked greedy step (rb_surrogate_step).  buffer: iterable of
+    (candidate, target, step).  Returns a dict with the pick, its value, the top-K and
+    exploration lists, the flags, the weights after training and the new counter."""
+    theta = _f64(np.atleast_2d(theta))
+    mu = _f64(np.atleast_2d(mu))
+    M, P = mu.shape
+    opts = greedy_opts(**kw)
+    ex = np.ascontiguousarray(excluded, dtype=np.int32)
+    par = _f32(params).copy()
+    buf = list(buffer)
+    bi = np.ascontiguousarray([b[0] for b in buf], dtype=np.int32)
+    bt = _f32([b[1] for b in buf])
+    bs = np.ascontiguousarray([b[2] for b in buf], dtype=np.int32)
+    tk = np.zeros(max(opts.topk, 1), dtype=np.int32)
+    xp = np.zeros(max(opts.explore, 1), dtype=np.int32)
+    io = SurrogateIO()
+    io.struct_size = C.sizeof(SurrogateIO)
+    io.step = step
+    io.counter = counter
+    i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+    _check(_lib.rb_surrogate_step(ctx.h, prob.h, basis.h, C.byref(opts), M, P, _dptr(mu),
+                                  _dptr(theta), i32(ex), _fptr(par), len(buf), i32(bi),
+                                  _fptr(bt), i32(bs), i32(tk), i32(xp), C.byref(io)))
+    return {"pick": io.pick, "value": io.value, "topk": tk[:io.n_topk].tolist(),
+            "explore": xp[:io.n_explore].tolist(), "full_sweep": bool(io.full_sweep),
+            "fallback": bool(io.fallback), "params": par, "counter": io.counter,
+            "true_evals": io.true_evals, "loss": io.loss}

@@ -90,6 +90,26 @@ def test_adam_matches_oracle(lib, ctx):
     assert loss == pytest.approx(l1, rel=1e-3) and loss < l0
 
 
+def test_adam_bf16_matches_oracle(lib, ctx):
+    """Training with BF16 products (FP32 masters and moments) against the FP64 oracle's
+    Adam: the weights after 20 steps within 1e-2, and so is the change the training
+    made (a CPU emulation of BF16 operand rounding puts the change's error near 5e-3)."""
+    P, H, m = 8, 128, 256
+    params, X, y = _case(P, H, m, seed=9)
+    steps, lr = 20, 1e-2
+    newp, loss = lib.mlp_train(ctx, P, H, pack(params), X, y, steps, lr, prec="bf16")
+    ref = {k: v.copy() for k, v in params.items()}
+    opt = omlp.Adam(ref, lr=lr)
+    for _ in range(steps):
+        _, g = omlp.loss_and_grads(ref, X, y)
+        opt.step(ref, g)
+    p0, pr = pack(params), pack(ref)
+    assert _rel(newp, pr) <= 1e-2
+    assert _rel(newp - p0, pr - p0) <= 1e-2, _rel(newp - p0, pr - p0)
+    l0, _ = omlp.loss_and_grads(params, X, y)
+    assert loss < l0
+
+
 @pytest.mark.parametrize("M,K", [(1000, 64), (10000, 256), (50, 80), (5000, 0)])
 def test_topk(lib, ctx, M, K):
     rng = np.random.default_rng(M + K)

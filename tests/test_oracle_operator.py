@@ -170,3 +170,31 @@ def test_matrix_free_apply_equals_assembly(dims, blocks):
         ref = A @ u
         scale = abs(A) @ np.abs(u)
         assert np.max(np.abs(op.apply(theta, u) - ref) / scale) <= 1e-14
+
+
+SMOOTHER_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "smoother_hand.txt")
+
+
+def test_smoothers_match_hand_derived_steps():
+    """Jacobi (omega = 2/3), red-black Gauss-Seidel and its symmetric form on the 1D
+    three-node case, against steps worked out by hand (tests/golden/smoother_hand.txt)."""
+    from fractions import Fraction
+
+    from oracle.smoother import Smoother
+
+    op = BlockDiffusion((3,), (2,))
+    A = op.assemble(np.array([1.0, 3.0]))
+    b = np.ones(3)
+    rows = []
+    with open(SMOOTHER_GOLDEN) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                kind, step, *vals = line.split()
+                rows.append((kind, int(step), [float(Fraction(v)) for v in vals]))
+    assert {r[0] for r in rows} == {"jacobi", "rbgs", "rbgs_sym"}
+    for kind, step, want in rows:
+        S = Smoother(A, op.colors(), kind)
+        y = np.zeros(3)
+        for _ in range(step):
+            y = S(b, y)
+        assert np.allclose(y, want, rtol=1e-14, atol=0), (kind, step, y, want)

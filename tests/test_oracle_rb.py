@@ -319,3 +319,52 @@ def test_several_sweeps_are_repeated_forward_substitution():
             ref = ref + np.linalg.solve(DL, b[order] - P @ ref)
         y = Smoother(A, c, RBGS, sweeps=k)(b, y0)
         assert np.abs(y[order] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_residual_replacement_restarts_on_the_residual_equation():
+    """R4 (stopping rule): when the recursive residual passes and the true residual
+    f - A x does not, r is replaced by the true residual and CG restarts with p = M r.
+    One product A p of the recursion is perturbed (a transient error), so the recursive
+    residual drifts from the true one and the replacement must happen.  Pins: the solve
+    still ends with a true residual <= rtol, and every iterate after the restart equals
+    x_k + (the RBCG iterate of the residual equation A e = f - A x_k started from 0),
+    which is what a restart is; a kept beta, a stale rho or an unpreconditioned restart
+    direction each break the equality."""
+    op, theta, A = _problem((15, 15), (2, 2), seed=11)
+    W = _snapshot_basis(op, 3, seed=12)
+    f = op.rhs()
+    AN, _ = rb.reduced_operators(op.A_q, [f], W)
+    Wr = W
+    S = Smoother(A, op.colors(), RBGS)
+    L = rb.cholesky(rb.assemble_reduced(AN, theta))
+    precond = rb.RBPreconditioner(A, Wr, L, S)
+    rng = np.random.default_rng(13)
+    delta = rng.standard_normal(op.N)
+
+    class Perturbed:
+        """A whose third matrix-vector product (q = A p of iteration 3) is off by 1e-4."""
+
+        def __init__(self):
+            self.calls = 0
+
+        def __matmul__(self, v):
+            self.calls += 1
+            out = A @ v
+            if self.calls == 3:
+                out = out + 1e-4 * np.linalg.norm(out) / np.linalg.norm(delta) * delta
+            return out
+
+    res = rb.rbcg(Perturbed(), f, precond, rtol=1e-10, keep_iterates=True)
+    assert res.converged and res.rel_res_true <= 1e-10
+    hist = np.array(res.history)
+    k = int(np.flatnonzero(hist <= 1e-10)[0])          # first recursive pass = restart
+    assert k < res.iters, "the true residual check must have failed once"
+    # the restarted residual is the true one: the next recursive value jumps up
+    assert hist[k + 1] > 1e3 * hist[k]
+    xk = res.iterates[k - 1]
+    rk = f - A @ xk
+    for m in (1, 2, 5, res.iters - k):
+        e = rb.rbcg(A, rk, precond, fixed_iters=m).x
+        want = xk + e
+        got = res.iterates[k - 1 + m]
+        assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(e), m
