@@ -68,36 +68,61 @@ def init_params(P, H, seed):
     return params
 
 
-def forward(params, X, cache=False):
-    z1 = X @ params["W1"].T + params["b1"]
-    a1 = gelu(z1)
-    z2 = a1 @ params["W2"].T + params["b2"]
-    a2 = gelu(z2)
-    out = a2 @ params["w3"].T + params["b3"]
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64: the FP32 value
+    keeps its top 16 bits after adding half an ulp of BF16 plus the tie-break bit."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _mm(A, B, bf16):
+    """A @ B; in BF16 mode both operands are rounded to BF16 first and the result is
+    kept in FP32 (products accumulated here in FP64, then rounded once)."""
+    if not bf16:
+        return A @ B
+    return _f32(bf16_round(A) @ bf16_round(B))
+
+
+def forward(params, X, cache=False, bf16=False):
+    """Output of the network for the rows of X.  bf16: every product takes BF16 operands
+    and every stored activation is FP32 (the reduced-precision mode of the surrogate)."""
+    rnd = _f32 if bf16 else (lambda v: v)
+    z1 = rnd(_mm(X, params["W1"].T, bf16) + params["b1"])
+    a1 = rnd(gelu(z1))
+    z2 = rnd(_mm(a1, params["W2"].T, bf16) + params["b2"])
+    a2 = rnd(gelu(z2))
+    out = rnd(_mm(a2, params["w3"].T, bf16) + params["b3"])
     out = out[:, 0]
     if cache:
         return out, (X, z1, a1, z2, a2)
     return out
 
 
-def loss_and_grads(params, X, y):
-    """MSE loss (mean over rows) and its gradients by hand-written backprop."""
-    out, (X, z1, a1, z2, a2) = forward(params, X, cache=True)
+def loss_and_grads(params, X, y, bf16=False):
+    """MSE loss (mean over rows) and its gradients by hand-written backprop (bf16: the
+    products' operands rounded to BF16 and the intermediates kept in FP32, as forward)."""
+    rnd = _f32 if bf16 else (lambda v: v)
+    out, (X, z1, a1, z2, a2) = forward(params, X, cache=True, bf16=bf16)
     m = X.shape[0]
     diff = out - y
     loss = float(np.mean(diff * diff))
-    g_out = (2.0 / m) * diff[:, None]             # d loss / d out
+    g_out = rnd((2.0 / m) * diff[:, None])             # d loss / d out
     g = {}
-    g["w3"] = g_out.T @ a2
-    g["b3"] = g_out.sum(axis=0)
-    g_a2 = g_out @ params["w3"]
-    g_z2 = g_a2 * gelu_grad(z2)
-    g["W2"] = g_z2.T @ a1
-    g["b2"] = g_z2.sum(axis=0)
-    g_a1 = g_z2 @ params["W2"]
-    g_z1 = g_a1 * gelu_grad(z1)
-    g["W1"] = g_z1.T @ X
-    g["b1"] = g_z1.sum(axis=0)
+    g["w3"] = _mm(g_out.T, a2, bf16)
+    g["b3"] = rnd(g_out.sum(axis=0))
+    g_a2 = _mm(g_out, params["w3"], bf16)
+    g_z2 = rnd(g_a2 * gelu_grad(z2))
+    g["W2"] = _mm(g_z2.T, a1, bf16)
+    g["b2"] = rnd(g_z2.sum(axis=0))
+    g_a1 = _mm(g_z2, params["W2"], bf16)
+    g_z1 = rnd(g_a1 * gelu_grad(z1))
+    g["W1"] = _mm(g_z1.T, X, bf16)
+    g["b1"] = rnd(g_z1.sum(axis=0))
     return loss, g
 
 

@@ -91,21 +91,31 @@ def test_adam_matches_oracle(lib, ctx):
 
 
 def test_adam_bf16_matches_oracle(lib, ctx):
-    """Training with BF16 products (FP32 masters and moments) against the FP64 oracle's
-    Adam: the weights after 20 steps within 1e-2, and so is the change the training
-    made (a CPU emulation of BF16 operand rounding puts the change's error near 5e-3)."""
+    """Training with BF16 products (FP32 masters and moments) against the oracle's Adam.
+    The weights after 20 steps are within 1e-2 of the FP64 oracle's.  The change the
+    training made is compared with the oracle's BF16 mode (every product's operands
+    rounded to BF16, intermediates in FP32): against FP64 it differs by about 1.5e-2,
+    since Adam divides each gradient by its own magnitude and so amplifies the relative
+    error of the small components, and the BF16 model reproduces that."""
     P, H, m = 8, 128, 256
     params, X, y = _case(P, H, m, seed=9)
     steps, lr = 20, 1e-2
     newp, loss = lib.mlp_train(ctx, P, H, pack(params), X, y, steps, lr, prec="bf16")
-    ref = {k: v.copy() for k, v in params.items()}
-    opt = omlp.Adam(ref, lr=lr)
-    for _ in range(steps):
-        _, g = omlp.loss_and_grads(ref, X, y)
-        opt.step(ref, g)
-    p0, pr = pack(params), pack(ref)
-    assert _rel(newp, pr) <= 1e-2
-    assert _rel(newp - p0, pr - p0) <= 1e-2, _rel(newp - p0, pr - p0)
+
+    def oracle_adam(bf16):
+        ref = {k: v.copy() for k, v in params.items()}
+        opt = omlp.Adam(ref, lr=lr)
+        for _ in range(steps):
+            _, g = omlp.loss_and_grads(ref, X, y, bf16=bf16)
+            opt.step(ref, g)
+        return pack(ref)
+
+    p0, p64, pbf = pack(params), oracle_adam(False), oracle_adam(True)
+    e64, ebf = _rel(newp, p64), _rel(newp - p0, pbf - p0)
+    print(f"bf16 Adam: weights vs FP64 oracle {e64:.2e}, change vs BF16 oracle {ebf:.2e}, "
+          f"change vs FP64 oracle {_rel(newp - p0, p64 - p0):.2e}")
+    assert e64 <= 1e-2
+    assert ebf <= 3e-3, ebf
     l0, _ = omlp.loss_and_grads(params, X, y)
     assert loss < l0
 

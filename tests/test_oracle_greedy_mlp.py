@@ -150,3 +150,38 @@ def test_multi_fidelity_basis_spans_fine_snapshots():
         assert np.linalg.norm(x - W @ (W.T @ x)) <= 1e-8 * np.linalg.norm(x)
     AN, _ = orb.reduced_operators(fine.A_q, [fine.rhs()], W)
     assert np.abs(AN - mf.AN_q).max() <= 1e-12 * np.abs(AN).max()
+
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's BF16 rounding equals torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even), ties and the largest finite values included."""
+    import torch
+    rng = np.random.default_rng(17)
+    v = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.uniform(-30, 30, 4000),
+                        # exact ties: 1 + (2k+1) 2^-8 lies halfway between BF16 neighbours
+                        1.0 + (2 * np.arange(64) + 1) * 2.0 ** -8, [0.0, -0.0, 3.3e38]])
+    v = v.astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    assert np.array_equal(mlp.bf16_round(v), ref)
+
+
+def test_bf16_mode_is_close_to_fp64():
+    """With BF16 operands (relative precision 2^-8) the loss and gradients stay within a
+    few 1e-3 of the FP64 network's; with operands that are already BF16 values
+    the first product is exact up to FP32 rounding."""
+    rng = np.random.default_rng(5)
+    P, H, m = 8, 32, 64
+    params = mlp.init_params(P, H, seed=3)
+    X = rng.uniform(-1, 1, (m, P))
+    y = np.sin(X[:, 0])
+    l64, g64 = mlp.loss_and_grads(params, X, y)
+    lbf, gbf = mlp.loss_and_grads(params, X, y, bf16=True)
+    assert abs(lbf - l64) <= 2e-2 * l64
+    for k in g64:
+        assert np.linalg.norm(gbf[k] - g64[k]) <= 2e-2 * np.linalg.norm(g64[k]), k
+    # BF16-representable operands: the first layer's pre-activation equals FP64's in FP32
+    pb = {k: mlp.bf16_round(v) for k, v in params.items()}
+    Xb = mlp.bf16_round(X)
+    z64 = Xb @ pb["W1"].T
+    zbf = mlp._mm(Xb, pb["W1"].T, True)
+    assert np.allclose(zbf, z64, rtol=2 ** -23, atol=0)
