@@ -241,6 +241,20 @@ rb_status rb_project_batch(rb_ctx* ctx, const rb_problem* prob, const rb_basis* 
 rb_status rb_reduced_factor_batch(rb_ctx* ctx, const rb_basis* basis, int B,
                                   const double* theta, double* L, rb_status* status);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc): rb_reduced_factor_batch with the same arguments and results, except
+ * that it allocates nothing.  theta is staged on the device, and L and status are formed
+ * there, in one fixed buffer of RB_NOALLOC_SCRATCH_BYTES per GPU that the library holds
+ * until the process ends (its address is resolved when the first context on that GPU is
+ * created).  Requires 256-byte-rounded sizes B*Q*8 + B*n*n*8 + B*4 to fit in it (e.g.
+ * B = 512 queries at n = 40, Q = 8); larger requests fail with RB_EINVAL and a message
+ * naming the sizes, before any work.  Every call on one GPU shares that buffer: calls
+ * that overlap on one GPU (from several threads or contexts) race.  It synchronises the
+ * context's stream before returning, like rb_reduced_factor_batch. */
+#define RB_NOALLOC_SCRATCH_BYTES (8u << 20)
+rb_status rb_reduced_factor_batch_noalloc(rb_ctx* ctx, const rb_basis* basis, int B,
+                                          const double* theta, double* L, rb_status* status);
+
 /* ---- Offline: adaptive greedy (Alg. 4) --------------------------------------
  * Training set Xi_train of M parameters: theta [M][Q] host (and phi [M][R] or
  * NULL).  mu [M][P] host or NULL is used only for the surrogate's features.

@@ -79,31 +79,6 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-template <typename F>
-static rb_status guarded(F&& f) {
-  try {
-    f();
-    return RB_OK;
-  } catch (const Error& e) {
-    set_error(e.msg);
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return RB_ENOMEM;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return RB_EINVAL;
-  } catch (...) {
-    set_error("unknown error");
-    return RB_EINVAL;
-  }
-}
-
-static void check_finite(const double* v, size_t n, const char* what) {
-  for (size_t i = 0; i < n; ++i)
-    RB_REQUIRE(std::isfinite(v[i]), RB_EINVAL, std::string(what) + " contains NaN or Inf");
-}
-
 }  // namespace rb
 
 using namespace rb;
@@ -166,6 +141,7 @@ rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx** out) {
     c->device = device;
     DeviceGuard dg(device);
     RB_HIP(hipGetDeviceProperties(&c->prop, device));
+    noalloc_attach(device);  // the fixed buffer of the allocation-free entry points
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {

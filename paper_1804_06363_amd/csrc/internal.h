@@ -3,7 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <memory>
 #include <vector>
@@ -59,6 +62,36 @@ struct DeviceGuard {
   }
   ~DeviceGuard() { (void)hipSetDevice(old); }
 };
+
+// Runs an entry point's body: RB_OK, or the status and message of whatever it threw.
+template <typename F>
+inline rb_status guarded(F&& f) {
+  try {
+    f();
+    return RB_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return RB_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RB_EINVAL;
+  } catch (...) {
+    set_error("unknown error");
+    return RB_EINVAL;
+  }
+}
+
+inline void check_finite(const double* v, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    RB_REQUIRE(std::isfinite(v[i]), RB_EINVAL, std::string(what) + " contains NaN or Inf");
+}
+
+// The fixed device buffer of the entry points that allocate nothing: resolves its
+// address on `device` (the current device) once; called when a context is created.
+void noalloc_attach(int device);
 
 }  // namespace rb
 

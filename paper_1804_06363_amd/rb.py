@@ -129,6 +129,7 @@ _sig("rb_apply_batch", [_P, _P, C.c_int, _D, _P, _P])
 _sig("rb_precond_batch", [_P, _P, _P, C.POINTER(SolveOpts), C.c_int, _D, _I, _P, _P])
 _sig("rb_project_batch", [_P, _P, _P, C.c_int, C.c_int, _P, _D])
 _sig("rb_reduced_factor_batch", [_P, _P, C.c_int, _D, _D, _I])
+_sig("rb_reduced_factor_batch_noalloc", [_P, _P, C.c_int, _D, _D, _I])
 _F = C.POINTER(C.c_float)
 _sig("rb_mlp_forward", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F])
 _sig("rb_mlp_loss_grad", [_P, C.c_int, C.c_int, C.c_int, _F, C.c_int, _F, _F, _F, _F])
@@ -152,6 +153,7 @@ EXPORTED = [
     "rb_solve_opts_default", "rb_solve_batch", "rb_solve_multi",
     "rb_apply_batch",
     "rb_precond_batch", "rb_project_batch", "rb_reduced_factor_batch",
+    "rb_reduced_factor_batch_noalloc",
     "rb_greedy_opts_default", "rb_offline_build", "rb_basis_from_parameters",
     "rb_mlp_forward", "rb_mlp_loss_grad", "rb_mlp_train", "rb_topk", "rb_surrogate_step",
 ]
@@ -441,6 +443,17 @@ def reduced_factor_batch(ctx, basis, theta):
     st = np.empty(B, dtype=np.int32)
     _check(_lib.rb_reduced_factor_batch(ctx.h, basis.h, B, _dptr(theta), _dptr(L),
                                         st.ctypes.data_as(_I)))
+    return L, st
+
+
+def reduced_factor_batch_noalloc(ctx, basis, theta):
+    """reduced_factor_batch through the entry point that allocates no device memory."""
+    theta = _f64(np.atleast_2d(theta))
+    B, n = theta.shape[0], basis.n
+    L = np.empty((B, n, n))
+    st = np.empty(B, dtype=np.int32)
+    _check(_lib.rb_reduced_factor_batch_noalloc(ctx.h, basis.h, B, _dptr(theta), _dptr(L),
+                                                st.ctypes.data_as(_I)))
     return L, st
 
 
