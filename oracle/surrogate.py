@@ -54,6 +54,7 @@ class SurrogateOptions:
     seed: int = 1234
     hidden: int = 128
     minibatch: int = 256
+    bf16: bool = False      # products with BF16 operands (mlp.forward / loss_and_grads)
 
 
 def init_draws(P: int, H: int) -> int:
@@ -162,8 +163,8 @@ def surrogate_step(state: SurrogateState, k: int, U, excluded, true_indicator,
     res = StepResult(None, 0.0, full, False)
     evaluated: list = []
     if not full:
-        pred = np.asarray(predict() if predict is not None else mlp.forward(state.params, U),
-                          dtype=np.float64)
+        pred = np.asarray(predict() if predict is not None
+                          else mlp.forward(state.params, U, bf16=o.bf16), dtype=np.float64)
         tk = top_k(pred, excluded, o.topk)
         listed = set(tk)
         expl = []
@@ -226,7 +227,7 @@ def train(state: SurrogateState, U):
         pick = [min(S - 1, int(state.draw() * S)) for _ in range(mb)]
         X = U[[buf[e][0] for e in pick]]
         y = np.array([(buf[e][1] - mean) / sd for e in pick])
-        loss, g = mlp.loss_and_grads(state.params, X, y)
+        loss, g = mlp.loss_and_grads(state.params, X, y, bf16=state.opts.bf16)
         state.adam.step(state.params, g)
         state.last_loss = loss
 

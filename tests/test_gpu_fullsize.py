@@ -1,9 +1,10 @@
 """Parity at the benchmark's full size and launch configuration (3D 127^3, N = 2,048,383,
-n = 40, B = 256, FP32 preconditioner, literal beta): every query reaches a true relative
-residual <= 1e-10 in FP64, and sampled queries are checked one by one against the
-oracle's RBCG with the same basis (same iteration count within one; solutions within
-2 kappa(A) 1e-10 of each other, with kappa bounded by Gershgorin and the smallest
-Dirichlet eigenvalue scaled by min(mu))."""
+n = 40, B = 256, FP32 or BF16 preconditioner, literal beta), with the 40 smoothest sine
+modes as the basis: every query reaches a true relative residual <= 1e-10 in FP64, and
+sampled queries are checked one by one against the oracle's RBCG with the same basis
+(iteration counts within 3%, 15% for BF16; solutions within 2 kappa(A) 1e-10 of each
+other, with kappa bounded by Gershgorin and the smallest Dirichlet eigenvalue scaled by
+min(mu)); the measured differences are printed."""
 import math
 
 import numpy as np
@@ -11,7 +12,7 @@ import pytest
 
 from oracle import rb as orb
 from oracle.operator import BlockDiffusion
-from workloads import WORKLOADS
+from workloads import WORKLOADS, sine_basis
 
 pytestmark = pytest.mark.gpu
 
@@ -26,30 +27,48 @@ def _kappa_bound(w, theta):
     return lmax / lmin
 
 
-def test_bench_configuration_parity(lib):
-    import torch
+@pytest.fixture(scope="module")
+def setup(lib):
     w = WORKLOADS["3d127"]
     ctx = lib.Context(0)
     prob = lib.Problem(ctx, w.dims, w.blocks)
-    train = w.train_mu()
-    basis, rep = lib.offline_build(ctx, prob, train, mu=train, n_max=w.n, indicator="residual")
-    assert basis.n == w.n
+    # a basis no solver produced (the 40 smoothest sine modes), the same on both sides;
+    # the oracle forms its own reduced operators of it (eq. 12c)
+    Wn = sine_basis(w.dims, w.n)
+    basis = lib.Basis.from_host(ctx, prob, Wn)
+    op = BlockDiffusion(w.dims, w.blocks)
+    W = np.ascontiguousarray(Wn.T)
+    del Wn
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    return w, ctx, prob, basis, op, W, AN
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_bench_configuration_parity(lib, setup, prec):
+    """The full batch with an FP32 (the benchmark's) or BF16 preconditioner; the measured
+    difference of the sampled solutions from the FP64 oracle's is printed."""
+    import torch
+    w, ctx, prob, basis, op, W, AN = setup
     test = w.test_mu(w.B)
-    x, st = lib.solve_batch(ctx, prob, basis, test, prec="fp32")
+    x, st = lib.solve_batch(ctx, prob, basis, test, prec=prec)
     assert (st.status == lib.RB_OK).all()
     assert st.rel_res_true.max() <= 1e-10
-    op = BlockDiffusion(w.dims, w.blocks)
-    Wn, AN, fN = basis.info()
-    W = np.ascontiguousarray(Wn.T)
+    errs = []
     for b in (0, 137):
         ref = orb.solve_rbcg(op, test[b], W, AN, rtol=1e-10)
         xb = x[b].cpu().numpy()
         assert ref.converged
-        assert abs(int(st.iters[b]) - ref.iters) <= max(2, 0.03 * ref.iters), (st.iters[b], ref.iters)
+        # the FP32 preconditioner is the oracle's to 1e-7; the BF16 one uses a basis rounded
+        # by 4e-3, a different operator, whose iteration counts differ more
+        slack = 0.03 if prec == "fp32" else 0.15
+        assert abs(int(st.iters[b]) - ref.iters) <= max(2, slack * ref.iters), (st.iters[b], ref.iters)
         err = np.linalg.norm(xb - ref.x) / np.linalg.norm(ref.x)
+        errs.append(err)
         assert err <= 2 * _kappa_bound(w, test[b]) * 1e-10, err
         # the GPU iterate satisfies the FP64 residual check independently of the library
         r = op.rhs() - op.assemble(test[b]) @ xb
         assert np.linalg.norm(r) / np.linalg.norm(op.rhs()) <= 1.01e-10
+    print(f"127^3 B=256 {prec}: iterations mean {st.iters.mean():.1f}; difference from the "
+          f"FP64 oracle {errs[0]:.2e}, {errs[1]:.2e}")
     del x
     torch.cuda.empty_cache()

@@ -6,10 +6,12 @@ What must agree: the top-K set (exactly, unless two predictions tie at the K-th 
 within the FP32/FP64 rounding of the network, in which case the differing candidates
 must be such near-ties), the exploration draws, the ranking-check outcome, the pick
 (the argmax of the FP64 true indicator), the evaluation count and the counter; the
-weights after the step's training within 1e-3 of the oracle's change (FP32 products)
-or 1e-2 (BF16 products).  With the GPU's own predictions fed to the oracle's protocol
-(rb_mlp_forward on the same weights and features) every list, flag and the pick agree
-exactly, in both precisions."""
+weights after the step's training within 1e-3 of the oracle's change (FP32 products;
+the oracle trains in FP64) or 3e-3 (BF16 products, against the oracle's BF16 mode).
+With the GPU's own predictions fed to the oracle's protocol (rb_mlp_forward on the same
+weights and features) every list, flag and the pick agree exactly, in both precisions."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -76,8 +78,11 @@ def _gpu_step(lib, c, params, prec, counter, k=5):
                               lr=o.lr, mu_lo=LO, mu_hi=HI, seed=o.seed, surrogate_prec=prec)
 
 
-def _oracle_step(c, params, predict=None, k=5):
-    st = sg.SurrogateState(c["op"].Q, c["opts"], params=params)
+def _oracle_step(c, params, predict=None, k=5, bf16=False):
+    opts = c["opts"]
+    if bf16:
+        opts = dataclasses.replace(opts, bf16=True)
+    st = sg.SurrogateState(c["op"].Q, opts, params=params)
     st.buffer = list(c["buf"])
     counter0 = st.counter
     eta = c["eta"]
@@ -108,7 +113,8 @@ def test_step_matches_oracle_fp32(lib, case, net):
             assert abs(pred[m] - kth) <= 1e-5 * max(1.0, abs(kth)), (m, pred[m], kth)
         pytest.skip("top-K boundary tie between FP32 and FP64 predictions")
     assert gpu["explore"] == res.explore
-    assert not gpu["full_sweep"] and gpu["fallback"] == res.fallback
+    # the untrained network ranks poorly: the check may fail, and a fallback is a full sweep
+    assert gpu["fallback"] == res.fallback and gpu["full_sweep"] == res.full
     assert _same_pick(c, gpu["pick"], res.pick), (gpu["pick"], res.pick)
     assert gpu["true_evals"] == res.true_evals
     assert gpu["counter"] == st.counter
@@ -125,7 +131,7 @@ def test_protocol_on_gpu_predictions(lib, case, prec, net):
     params = c["nets"][net]
     X = np.asarray(c["U"], dtype=np.float32)
     gp = lib.mlp_forward(c["ctx"], c["op"].Q, H, pack(params), X, prec=prec).astype(np.float64)
-    st, res, counter0 = _oracle_step(c, params, predict=lambda: gp)
+    st, res, counter0 = _oracle_step(c, params, predict=lambda: gp, bf16=prec == "bf16")
     gpu = _gpu_step(lib, c, params, prec, counter0)
     assert gpu["topk"] == res.topk
     assert gpu["explore"] == res.explore
@@ -133,9 +139,9 @@ def test_protocol_on_gpu_predictions(lib, case, prec, net):
     assert _same_pick(c, gpu["pick"], res.pick)
     assert gpu["true_evals"] == res.true_evals and gpu["counter"] == st.counter
     p0 = pack(params)
-    tol = 1e-3 if prec == "fp32" else 1e-2
-    # the oracle trains in FP64: its change of the weights against the GPU's
-    assert _rel(gpu["params"] - p0, pack(st.params) - p0) <= tol
+    # the oracle trains in FP64 (FP32 products on the GPU) or with the GPU's BF16 operand
+    # rounding: its change of the weights against the GPU's
+    assert _rel(gpu["params"] - p0, pack(st.params) - p0) <= (1e-3 if prec == "fp32" else 3e-3)
 
 
 def test_full_sweep_steps(lib, case):

@@ -40,6 +40,32 @@ def random_orthonormal(seed: int, N: int, n: int) -> np.ndarray:
     return q
 
 
+def sine_basis(dims, n):
+    """The n discrete sine modes prod_a sqrt(2/(m_a+1)) sin(i_a pi j_a / (m_a+1)) with the
+    smallest sum of squared mode numbers (ties by mode numbers), as rows of length N in
+    natural order (x fastest); orthonormal on the grid.  A basis that no solver produced,
+    for tests at sizes where the reference solver cannot build one."""
+    import math
+    d = len(dims)
+    rng = range(1, 9)
+    if d == 2:
+        modes = sorted((i * i + j * j, i, j, 1) for i in rng for j in rng)[:n]
+    else:
+        modes = sorted((i * i + j * j + k * k, i, j, k) for i in rng for j in rng
+                       for k in rng)[:n]
+
+    def s(m, i):
+        return math.sqrt(2.0 / (m + 1)) * np.sin(i * math.pi * np.arange(1, m + 1) / (m + 1))
+
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if d == 3 else 1
+    W = np.empty((n, nx * ny * nz))
+    for c, (_, i, j, k) in enumerate(modes):
+        sz = s(nz, k) if d == 3 else np.ones(1)
+        W[c] = np.multiply.outer(sz, np.multiply.outer(s(ny, j), s(nx, i))).ravel()
+    return W
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
