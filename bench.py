@@ -112,6 +112,14 @@ def main():
                     help="also run the paper's two P1 cases (Table 1) through the sparse path")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also fill and sum a buffer of this many MiB (profiler calibration)")
+    ap.add_argument("--cpu-sample", type=int, default=2,
+                    help="test queries the CPU oracle solves (timed, and compared with the GPU)")
+    ap.add_argument("--mixed-error", type=int, default=1,
+                    help="also solve the batch with the BF16 preconditioner and report every "
+                         "precision's difference from the oracle on the CPU sample")
+    ap.add_argument("--smoother-study", type=int, default=0,
+                    help="also time the batch with each smoother variant (sweeps, symmetric, "
+                         "Jacobi)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the "
@@ -214,6 +222,21 @@ def main():
                     "bytes_per_launch": round(bytes_b / max(n_b, 1)),
                     "avg_launch_us": round(ms_b / max(n_b, 1) * 1e3, 1)}
 
+    # whole solve against the HBM roofline: the fused three-pass model of the iteration,
+    # N (64 + 2 s_y + 1.5 s_W n / B) bytes per query-iteration (x, r, p in FP64, y in
+    # s_y bytes, W in s_W bytes shared by the B queries), plus 24 N per query for the
+    # start and the final true residual, over the wall time of a step
+    s_y = 8 if args.prec == "fp64" else 4
+    s_w = {"fp64": 8, "fp32": 4, "bf16": 2}[args.prec]
+    path_bytes = sum(float(N) * (64 + 2 * s_y + 1.5 * s_w * basis.n / B) * float(ss.iters.sum())
+                     + 24.0 * N * B for ss in stats)
+    path_gbs = path_bytes / elapsed / 1e9
+    roofline["path_model_bytes_per_step"] = round(path_bytes / args.steps)
+    roofline["path_achieved"] = round(path_gbs, 1)
+    roofline["path_frac"] = round(path_gbs / HBM_PEAK_GBS, 4)
+    log(f"whole solve: {path_bytes / args.steps / 1e9:.1f} GB of model traffic per step, "
+        f"{path_gbs:.0f} GB/s = {path_gbs / HBM_PEAK_GBS:.3f} of the HBM peak")
+
     # the same solves with the iterations replayed from a captured HIP graph
     graph_leg = None
     if args.graph_leg and not args.graph:
@@ -234,6 +257,7 @@ def main():
 
     # plain path: FP64 everywhere, one query per call, sequential
     plain = None
+    x_plain = {}
     if args.plain_sample > 0:
         S = min(args.plain_sample, B)
         popts = rb.solve_opts(prec="fp64")
@@ -243,20 +267,43 @@ def main():
         tp = time.perf_counter()
         pc = 0
         pit = []
+        x_plain = {}
         for b in range(S):
             _, ps = rb.solve_batch(ctx, prob, basis, test[b:b + 1], x=xs, opts=popts)
             pc += int(((ps.status == rb.RB_OK) & (ps.rel_res_true <= 1e-10)).sum())
             pit.append(int(ps.iters[0]))
+            if b < args.cpu_sample:
+                x_plain[b] = xs[0].clone()
         torch.cuda.synchronize()
         pe = time.perf_counter() - tp
         plain = {"value": round(pc / pe, 2), "sample": S, "iters_mean": float(np.mean(pit))}
         log(f"plain FP64 B=1: {plain['value']} mu-solves/s over {S} queries, iters {np.mean(pit):.1f}")
 
     cpu = None
+    oracle_error = None
     if args.cpu_baseline:
-        cpu = cpu_baseline(basis, w, test[:2])
+        S = min(args.cpu_sample, B)
+        cpu, x_orc = cpu_baseline(basis, w, test[:S])
+        # difference of each precision's solutions from the oracle's FP64 RBCG on the same
+        # basis: ||x - x_oracle|| / ||x_oracle|| for the sampled queries
+        def errs(xg):
+            return [float(np.linalg.norm(xg[b] - x_orc[b]) / np.linalg.norm(x_orc[b]))
+                    for b in range(S)]
+        oracle_error = {"sample": f"the first {S} test queries", args.prec: errs(x.cpu().numpy())}
+        if x_plain:
+            oracle_error["fp64_plain"] = errs({b: v.cpu().numpy() for b, v in x_plain.items()})
+        if args.mixed_error and args.prec == "fp32":
+            xb = torch.empty_like(x)
+            _, sb = rb.solve_batch(ctx, prob, basis, test, x=xb,
+                                   opts=rb.solve_opts(prec="bf16", flexible=bool(args.flexible)))
+            oracle_error["bf16"] = errs(xb.cpu().numpy())
+            oracle_error["bf16_iters_mean"] = round(float(sb.iters.mean()), 2)
+            del xb
+        log(f"difference from the oracle: {oracle_error}")
 
     extra = {}
+    if args.smoother_study:
+        extra["smoother_study"] = smoother_study(rb, ctx, prob, basis, test, x, args)
     for flag, name, fn in ((args.uneven, "uneven_batch", lambda: uneven_leg(rb, torch)),
                            (args.learned, "learned_greedy", lambda: learned_leg(rb)),
                            (args.fem, "fem_cases", lambda: fem_leg(rb, torch))):
@@ -286,7 +333,7 @@ def main():
         "max_rel_res": float(st.rel_res_true.max()), "converged": conv,
         "plain_fp64_b1": plain,
         "speedup_vs_plain": round(value / plain["value"], 2) if plain and plain["value"] else None,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "oracle_error": oracle_error,
         "graph_replay": graph_leg,
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
     }
@@ -327,9 +374,11 @@ def uneven_leg(rb, torch):
     st = rb.solve_multi(ctx, probs, bases, queries, opts=opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    good = (st.status == rb.RB_OK) & ((st.rel_res_true <= tol) | (st.at_floor == 1))
+    # a query counts only if its true residual meets its tolerance; queries the rounding-
+    # level test accepted above it are reported apart, not counted
+    good = (st.status == rb.RB_OK) & (st.rel_res_true <= tol)
     ok = int(good.sum())
-    at_floor = int(((st.status == rb.RB_OK) & (st.at_floor == 1)).sum())
+    at_floor = int(((st.status == rb.RB_OK) & (st.rel_res_true > tol)).sum())
     gidx = np.array([g for g, _, _ in qs])
     nidx = np.array([nu for _, nu, _ in qs])
     groups = {}
@@ -344,10 +393,11 @@ def uneven_leg(rb, torch):
                     f"converged, iters mean {st.iters[m].mean():.1f} max {st.iters[m].max()}, "
                     f"status {np.bincount(st.status[m], minlength=6).tolist()}")
     log(f"uneven: {len(qs)} queries in {el:.3f}s -> {ok / el:.1f} mu-solves/s "
-        f"({at_floor} accepted at the FP64 rounding level), iters mean {st.iters.mean():.1f}, "
-        f"max rel res {st.rel_res_true.max():.2e}")
+        f"({at_floor} accepted at the FP64 rounding level above their tolerance, not "
+        f"counted), iters mean {st.iters.mean():.1f}, max rel res {st.rel_res_true.max():.2e}")
     return {"value": round(ok / el, 2), "unit": "mu-solves/s", "queries": len(qs),
-            "converged": ok, "at_rounding_level": at_floor, "seconds": round(el, 4), "iters_mean": round(float(st.iters.mean()), 2),
+            "converged": ok, "accepted_above_tolerance": at_floor, "seconds": round(el, 4),
+            "iters_mean": round(float(st.iters.mean()), 2),
             "max_rel_res_over_rtol": float((st.rel_res_true / tol).max()), "groups": groups}
 
 
@@ -443,6 +493,35 @@ def held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch):
     return worst
 
 
+def smoother_study(rb, ctx, prob, basis, test, x, args):
+    """The same batch with each smoother of the preconditioner (Sec. 3.3 leaves the choice
+    open): one to three forward red-black Gauss-Seidel sweeps, the symmetric sweep (forward
+    then backward), damped Jacobi; mean iterations and converged mu-solves per second
+    (median of three timed solves after a warm-up that autotunes)."""
+    import torch
+    out = {}
+    for name, kw in (("rbgs", dict(smoother="rbgs")), ("rbgs_x2", dict(smoother="rbgs", sweeps=2)),
+                     ("rbgs_x3", dict(smoother="rbgs", sweeps=3)),
+                     ("rbgs_sym", dict(smoother="rbgs_sym")), ("jacobi", dict(smoother="jacobi"))):
+        o = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), **kw)
+        ow = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), autotune=True, **kw)
+        _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=ow)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=o)
+            times.append(time.perf_counter() - t)
+        ok = int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
+        el = float(np.median(times))
+        out[name] = {"iters_mean": round(float(st.iters.mean()), 2), "iters_max": int(st.iters.max()),
+                     "converged": ok, "mu_solves_per_s": round(ok / el, 2),
+                     "ms_per_solve": round(el * 1e3, 2)}
+        log(f"smoother {name}: iters mean {st.iters.mean():.1f}, {ok} converged, "
+            f"{ok / el:.1f} mu-solves/s")
+    return out
+
+
 def cpu_baseline(basis, w, thetas):
     """The oracle's RBCG (NumPy/SciPy FP64) on a few queries of the same workload."""
     from oracle import rb as orb
@@ -452,15 +531,18 @@ def cpu_baseline(basis, w, thetas):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = 1
-    log("cpu baseline: building the oracle operator")
+    log("cpu baseline: building the oracle operator and its reduced operators")
     op = BlockDiffusion(w.dims, w.blocks)
-    Wn, AN, fN = basis.info()
+    Wn, _, _ = basis.info()
     W = np.ascontiguousarray(Wn.T)
+    del Wn
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)   # offline: not timed
     t = time.perf_counter()
-    its, ok = [], 0
+    its, ok, xs = [], 0, []
     for th in thetas:
         res = orb.solve_rbcg(op, th, W, AN, rtol=1e-10)
         its.append(res.iters)
+        xs.append(res.x)
         ok += int(res.converged and res.rel_res_true <= 1e-10)
     el = time.perf_counter() - t
     log(f"cpu baseline: {len(thetas)} solves in {el:.1f}s, iters {its}")
@@ -468,13 +550,18 @@ def cpu_baseline(basis, w, thetas):
     one = None
     try:
         from threadpoolctl import threadpool_limits
+        # the whole sample when the grid is small, else the first query
+        n1 = len(thetas) if w.N < 100000 else 1
         with threadpool_limits(limits=1):
             t1 = time.perf_counter()
-            r1 = orb.solve_rbcg(op, thetas[0], W, AN, rtol=1e-10)
+            ok1 = 0
+            for th in thetas[:n1]:
+                r1 = orb.solve_rbcg(op, th, W, AN, rtol=1e-10)
+                ok1 += int(r1.converged and r1.rel_res_true <= 1e-10)
             el1 = time.perf_counter() - t1
-        ok1 = int(r1.converged and r1.rel_res_true <= 1e-10)
-        one = {"value": round(ok1 / el1, 5), "cores": 1, "sample": "the first test query"}
-        log(f"cpu baseline, one core: 1 solve in {el1:.1f}s")
+        one = {"value": round(ok1 / el1, 5), "cores": 1,
+               "sample": f"the first {n1} test queries"}
+        log(f"cpu baseline, one core: {n1} solves in {el1:.1f}s")
     except ImportError:
         pass
     cpu_model = ""
@@ -491,7 +578,7 @@ def cpu_baseline(basis, w, thetas):
             "sample": f"the first {len(thetas)} test queries of the same workload and basis "
                       "(operator setup excluded; reduced assembly, Cholesky, RBCG iterations "
                       "and true residual timed)",
-            "iters": its, "one_core": one}
+            "iters": its, "one_core": one}, xs
 
 
 if __name__ == "__main__":

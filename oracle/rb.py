@@ -14,6 +14,13 @@ Readings where the paper is silent (each also listed in the design notes):
   - stopping test is relative, ||r|| <= rtol ||b|| (eq. relerr of Sec. 5.1); when the
     recursive CG residual passes, the true residual b - A x is recomputed and must
     pass too, else r is replaced by it and CG restarts with p = y
+  - the iterate is held as x + xc: the updates alpha p accumulate in the correction xc,
+    which is added to x (and reset to 0) just before each true-residual check.  The
+    sum is the iterate of Alg. 3; the split only keeps the rounding of later updates
+    relative to the small correction instead of to x, so that a residual replacement
+    is not undone by the rounding of the next cycle (group-wise updating, van der Vorst
+    and Ye, SIAM J. Sci. Comput. 22, 2000).  Before the first check x = 0 and the
+    iterates are exactly those of x += alpha p.
   - the RBI preconditioner skips its own exit test (the outer test just failed)
   - the reduced matrix is factored once per mu; each application is two triangular
     solves (same result as re-inverting each iteration)
@@ -152,6 +159,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
 
     precond_call = M
     x = np.zeros_like(b)
+    xc = np.zeros_like(b)                   # updates since the last true-residual check
     r = b.copy()                            # x0 = 0, no product needed
     y = precond_call(r)
     p = y.copy()
@@ -174,17 +182,19 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
             status = "breakdown"
             break
         alpha = rho / pq
-        x = x + alpha * p
+        xc = xc + alpha * p
         r_old = r
         r = r - alpha * q
         it += 1
         rel_rec = np.linalg.norm(r) / nb
         hist.append(rel_rec)
         if keep_iterates:
-            iterates.append(x.copy())
+            iterates.append(x + xc)
         if adapt is not None and r_in[0] < adapt[0] * np.linalg.norm(r):
             n = min(n + 1, adapt[2])        # residual fell by less than gamma
         if fixed_iters is None and rel_rec <= rtol:   # stopping test
+            x = x + xc                      # fold the correction into x
+            xc = np.zeros_like(b)
             rt = b - A @ x
             if np.linalg.norm(rt) / nb <= rtol:
                 break
@@ -204,6 +214,7 @@ def rbcg(A, b, precond, rtol=1e-10, maxit=2000, flexible=False, fixed_iters=None
         if keep_vectors:
             vecs["r"].append(r.copy())
             vecs["p"].append(p.copy())
+    x = x + xc
     rel_true = np.linalg.norm(b - A @ x) / nb
     converged = status == "ok" and rel_true <= rtol
     out = SolveResult(x, it, converged, rel_true, rel_rec, status, hist, iterates)
@@ -303,3 +314,25 @@ def solve_rbi(op, theta, W, AN_q=None, m=2000, rtol=1e-10, smoother_kind=RBGS, p
     A, M = make_preconditioner(op, theta, W, AN_q, smoother_kind, sweeps)
     x, k, hist = rbi(A, _rhs(op, phi), W, M.L, M.S, m, rtol)
     return x, k, hist
+
+
+def residual_floor(op, theta, phi=None, refine=4):
+    """Attainable accuracy in FP64 of the solution x = A(theta)^-1 f (the definition the
+    iterations converge to): a sparse direct solve refined with residuals formed in
+    extended precision gives x to working precision; returned are the relative residuals
+    ||f - A x|| / ||f|| of that FP64 vector evaluated exactly (long double) and in FP64.
+    No FP64 iterate can be expected to pass a relative-residual test much below these."""
+    import scipy.sparse.linalg as spla
+    A = op.assemble(theta).tocsc()
+    f = _rhs(op, phi)
+    lu = spla.splu(A, permc_spec="COLAMD")
+    x = lu.solve(f)
+    Al = A.astype(np.longdouble)
+    fl = f.astype(np.longdouble)
+    for _ in range(refine):
+        x = x + lu.solve(np.asarray(fl - Al @ x.astype(np.longdouble), dtype=np.float64))
+    nf = np.linalg.norm(f)
+    exact = float(np.linalg.norm(np.asarray(fl - Al @ x.astype(np.longdouble),
+                                            dtype=np.float64))) / nf
+    fp64 = float(np.linalg.norm(f - A @ x)) / nf
+    return exact, fp64, x

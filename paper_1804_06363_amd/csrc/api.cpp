@@ -668,7 +668,7 @@ static void check_opts(const rb_solve_opts* o) {
              "bad precision");
   RB_REQUIRE(o->smoother >= RB_SMOOTH_RBGS && o->smoother <= RB_SMOOTH_NONE, RB_EINVAL,
              "bad smoother");
-  RB_REQUIRE(o->stencil_kind >= 0 && o->stencil_kind <= 2, RB_EINVAL, "bad stencil kind");
+  RB_REQUIRE(o->stencil_kind >= 0 && o->stencil_kind <= 3, RB_EINVAL, "bad stencil kind");
   RB_REQUIRE(std::isfinite(o->adapt_gamma) && o->adapt_gamma >= 0.0, RB_EINVAL,
              "bad adapt_gamma");
   RB_REQUIRE(o->adapt_gamma == 0.0 || o->solver == RB_SOLVER_RBCG, RB_EINVAL,
@@ -843,6 +843,7 @@ rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
     oo.beta_flexible = 0;
     BatchSolver s(ctx, p, bs, oo, B, theta, nullptr, n_use);
     s.prepare();
+    set_stencil_tiles(s.tc);  // the requested stencil kinds (cached tiles, if any)
     hipStream_t st = ctx->stream;
     launch_to_storage(*p, B, r, p->N, s.r0.as<double>(), p->ld, st);
     s.factor();
@@ -857,6 +858,7 @@ rb_status rb_precond_batch(rb_ctx* ctx, const rb_problem* p, const rb_basis* bs,
     }
     launch_from_storage(*p, B, ysrc, p->ld, y, p->N, st);
     RB_HIP(hipStreamSynchronize(st));
+    set_stencil_tiles(TuneConfig{});
   });
 }
 

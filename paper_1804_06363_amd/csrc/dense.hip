@@ -151,7 +151,9 @@ __device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT>& f,
 // qlist (batched path only, nullable): the active queries in increasing order, their
 // count in qlist[B]; the wave tiles then run over that list (tiles past the count exit)
 // and partial sums still go to the query's own row.
-template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED>
+// WCH = true (wchunk plans): each wave covers all the group's queries (QT tiles) over a
+// DOF range of its own; its partial sums are chunk 4 * blockIdx.x + wave.
+template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED, bool WCH = false>
 __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, int64_t r_ld,
                                                  const TW* __restrict__ W, int64_t w_ld, int n,
                                                  int B, int kend, int steps,
@@ -167,6 +169,9 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
   int q_base, k_begin, k_stop;
   if (WSPLIT) {
     q_base = blockIdx.y * QW;
+    k_begin = (chunk * 4 + wave) * steps * 16;
+  } else if (WCH) {
+    q_base = 0;
     k_begin = (chunk * 4 + wave) * steps * 16;
   } else {
     q_base = (blockIdx.y * 4 + wave) * QW;
@@ -213,6 +218,7 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
 
   const int qi = lane & 15, kg = lane >> 4;
   if (!WSPLIT) {
+    const int pchunk = WCH ? chunk * 4 + wave : chunk;
 #pragma unroll
     for (int t = 0; t < QT; ++t)
 #pragma unroll
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
         for (int i = 0; i < 4; ++i) {
           const int c = q_base + 16 * t + acc_row<TW>(kg, i);
           const int j = 16 * u + qi;
-          if (c < cnt) part[((size_t)chunk * B + (qlist ? qlist[c] : c)) * NJ + j] = acc[t][u][i];
+          if (c < cnt) part[((size_t)pchunk * B + (qlist ? qlist[c] : c)) * NJ + j] = acc[t][u][i];
         }
   } else {
     __shared__ Acc sh[4][QW][NJ];
@@ -272,7 +278,25 @@ ProjPlan plan_projection(int N, int B, int n, int target_blocks) {
     p.chunks = (nsteps + p.steps - 1) / p.steps;
   }
   p.nj = 16 * p.jt;
+  p.blocks = p.chunks;
   return p;
+}
+
+void plan_wave_chunks(ProjPlan& p, int B, int target_waves, rb_prec prec) {
+  // with at most 64 queries the four waves of a batched block hold four 16-query tiles
+  // over the same DOFs and each loads the block's basis rows; with a large basis those
+  // rows outweigh the residual rows, so one wave takes all queries instead (QT = 4; the
+  // FP64 basis would not fit the registers)
+  if (p.wsplit || !p.padded || B <= 16 || B > 64 || p.jt < 4 || prec == RB_PREC_FP64) return;
+  const int nsteps = p.kend / 16;
+  const int waves = std::max(4, target_waves);
+  p.wchunk = true;
+  p.qt = 4;
+  p.qgroups = 1;
+  p.steps = std::max(1, (nsteps + waves - 1) / waves);
+  const int used = (nsteps + p.steps - 1) / p.steps;  // waves with DOFs
+  p.blocks = (used + 3) / 4;
+  p.chunks = 4 * p.blocks;
 }
 
 template <typename TW, int QT, int JT>
@@ -280,7 +304,15 @@ static void launch_proj_t(const ProjPlan& pl, const double* R, int64_t r_ld, con
                           int64_t w_ld, int n, int B, const int* active, const int* qlist,
                           void* part, hipStream_t s) {
   using Acc = typename ProjTraits<TW>::Acc;
-  const dim3 grid(pl.chunks, pl.qgroups);
+  const dim3 grid(pl.blocks, pl.qgroups);
+  if constexpr (QT == 4 && sizeof(TW) < 8) {
+    if (pl.wchunk) {
+      hipLaunchKernelGGL((k_project<TW, QT, JT, false, true, true>), grid, dim3(256), 0, s, R,
+                         r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
+      return;
+    }
+  }
+  RB_REQUIRE(!pl.wchunk, RB_EUNSUPPORTED, "wave-chunk projection plan for an FP64 basis");
   if (pl.wsplit)
     hipLaunchKernelGGL((k_project<TW, QT, JT, true, false>), grid, dim3(256), 0, s, R, r_ld, W,
                        w_ld, n, B, pl.kend, pl.steps, active, nullptr, (Acc*)part);
@@ -1090,6 +1122,29 @@ void launch_fin_sum(const double* part, int stride, int cnt, double* out, const 
 }
 
 // ---- small helpers ---------------------------------------------------------------------
+// Correction folding of the CG iterate: x_b += xc_b, xc_b = 0 for the flagged queries.
+// Rows are ld (a multiple of 64) doubles; padding is zero in both vectors.
+__global__ void k_fold(const int* __restrict__ flag, double2* __restrict__ x,
+                       double2* __restrict__ xc, int64_t ld2) {
+  const int b = blockIdx.y;
+  if (flag && !flag[b]) return;
+  double2* xb = x + (size_t)b * ld2;
+  double2* cb = xc + (size_t)b * ld2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld2;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 a = xb[i], c = cb[i];
+    xb[i] = make_double2(a.x + c.x, a.y + c.y);
+    cb[i] = make_double2(0.0, 0.0);
+  }
+}
+void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s) {
+  if (B <= 0) return;
+  // a few blocks per query: most launches find no flag, and a flagged query is rare
+  const int bx = std::max(1, std::min(64, 2048 / B));
+  hipLaunchKernelGGL(k_fold, dim3(bx, B), dim3(256), 0, s, flag, (double2*)x, (double2*)xc,
+                     ld / 2);
+}
+
 // dst[b][pos] = value for pos < n (fill kernel; graph-safe replacement for memset)
 template <typename T>
 __global__ void k_fill(T* __restrict__ dst, int64_t ld, int64_t n, T value) {

@@ -43,8 +43,12 @@ struct Segs {
 struct ProjPlan {
   bool wsplit = false;
   bool padded = false;  // R rows padded to a multiple of 64*qt (zero), W to round_up(n, 16)
+  // wchunk: every wave covers all (at most 64) queries over a DOF range of its own, so
+  // each basis row is read once per launch; chunks = 4 * blocks partial sums per query
+  bool wchunk = false;
   int qt = 1, jt = 1, nj = 16;
   int qgroups = 1, chunks = 1, steps = 1;
+  int blocks = 1;       // grid width (= chunks except in wchunk mode)
   int kend = 0;
 };
 
@@ -65,6 +69,9 @@ int stencil_chunks_all(int N);
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                   const int* flag, double* part, hipStream_t s, double* part2 = nullptr);
+// x_b += xc_b, xc_b = 0 for the queries with flag[b] != 0 (all of them if flag is null),
+// over the ld entries of each row
+void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s);
 // passes A and B return the number of partial sums per query they wrote (at most
 // stencil_chunks_all(N); row stride stays stencil_chunks_all(N) in the solver's arrays)
 template <typename TY>
@@ -81,6 +88,17 @@ int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, 
                     int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                     double* part1, hipStream_t s);
+// One forward red-black sweep y = S(A, rhs, z) in one launch marching along z, for a start
+// z that is zero on the red nodes, read from the black half of zs (not written; y is
+// written on both colours).  Same y as the two launch_gs_color sweeps.  3D stencil grids
+// with nx <= 255 only (gs_fused_supported); returns the number of partial sums per query
+// (<= cap), 0 if not run.
+bool gs_fused_supported(const StencilGeom& g);
+template <typename TY>
+int launch_gs_fused(const StencilGeom& g, int B, const double* coef, const TY* zs, TY* y,
+                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs2,
+                    int64_t rhs2_ld, const int* active, double* part0, double* part1, int cap,
+                    hipStream_t s);
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,
                    int64_t y_ld, double omega, const double* rhs, int64_t rhs_ld,
@@ -119,6 +137,9 @@ void csr_from_storage(int N, const int* perm, int B, const double* sto, int64_t 
 
 // dense.hip
 ProjPlan plan_projection(int N, int B, int n, int target_blocks);
+// Turns a padded batched plan for 16 < B <= 64 queries and n > 48 basis vectors (FP32 or
+// BF16 basis) into wchunk mode with about target_waves waves; other plans are unchanged.
+void plan_wave_chunks(ProjPlan& p, int B, int target_waves, rb_prec prec);
 // qlist (nullable; the batched path only): active queries in increasing order with their
 // count in qlist[B] (launch_compact_active); rows of other queries are then not read.
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,

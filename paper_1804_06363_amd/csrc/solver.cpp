@@ -73,15 +73,21 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
                std::to_string((int)opt.precond_prec) + "|s" + std::to_string((int)opt.smoother);
     ctx->tuner.load();
     if (const TuneConfig* c = ctx->tuner.find(tune_key)) tc = *c;
-    if (opt.stencil_kind) tc.kind_a = tc.kind_b = tc.kind_gs = opt.stencil_kind;
+    if (opt.stencil_kind) {
+      tc.kind_a = tc.kind_b = std::min(opt.stencil_kind, 2);
+      tc.kind_gs = opt.stencil_kind;
+    }
   }
   // projection plan first: for batches it reads residual rows in whole query tiles
   if (n > 0) {
-    plan = plan_projection(g.N, B, n,
-                           tc.proj_target ? tc.proj_target : 4 * ctx->prop.multiProcessorCount);
+    const int target = tc.proj_target ? tc.proj_target : 4 * ctx->prop.multiProcessorCount;
+    plan = plan_projection(g.N, B, n, target);
     plan.padded = !plan.wsplit;
+    plan_wave_chunks(plan, B, target, opt.precond_prec);
   }
-  rrows = (n > 0 && plan.padded) ? plan.qgroups * 64 * plan.qt : B;
+  // rows of r the batched projection may address: whole query groups (a block of four
+  // 16 * qt query tiles, or one such tile in wchunk mode)
+  rrows = (n > 0 && plan.padded) ? plan.qgroups * (plan.wchunk ? 16 : 64) * plan.qt : B;
 
   // workspace views
   theta_d = get_ws(WS_THETA, sizeof(double) * B * Q);
@@ -100,11 +106,15 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
     r1 = get_ws(WS_R1, vr);
   if (opt.solver != RB_SOLVER_RBI) {
+    xc = get_ws(WS_XC, vb);
     p0 = get_ws(WS_P0, vb);
     p1 = get_ws(WS_P1, vb);
     y = get_ws(WS_Y, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
     if (opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
       z = get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
+    fused_ok = opt.solver == RB_SOLVER_RBCG && opt.smoother == RB_SMOOTH_RBGS &&
+               opt.smooth_sweeps <= 1 && gs_fused_supported(g);
+    if (fused_ok) z = get_ws(WS_Z, (y32 ? sizeof(float) : sizeof(double)) * (size_t)B * L_);
   }
   part_m = get_ws(WS_PM, sizeof(double) * (size_t)B * pstride);
   if (opt.floor_factor > 0.0) part_m2 = get_ws(WS_PM2, sizeof(double) * (size_t)B * pstride);
@@ -212,9 +222,10 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     return;
   }
   const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
+  const bool fz = fused();
   // coarse correction z = W A_N^-1 W^T r (black nodes only for Gauss-Seidel: the red
-  // sweep overwrites every red node and reads only black ones)
-  void* zdst = full ? z.p : y.p;
+  // sweep overwrites every red node and reads only black ones; into z for the fused sweep)
+  void* zdst = (full || fz) ? z.p : y.p;
   if (n > 0) {
     // batched path: the projection and the prolongation visit the active queries only
     const int* ql = nullptr;
@@ -245,6 +256,21 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
   }
   double* pr0 = part_r0.as<double>();
   double* pr1 = flex ? part_r1.as<double>() : nullptr;
+  if (fz) {  // both colours in one launch; one partial-sum segment
+    ProfScope ps(ctx, "gs_fused", st);
+    const int cnt =
+        y32 ? launch_gs_fused<float>(g, B, coef.as<double>(), z.as<float>(), y.as<float>(), L_, r,
+                                     L_, flex ? r_old : nullptr, L_, q.active, pr0, pr1, pstride,
+                                     st)
+            : launch_gs_fused<double>(g, B, coef.as<double>(), z.as<double>(), y.as<double>(), L_,
+                                      r, L_, flex ? r_old : nullptr, L_, q.active, pr0, pr1,
+                                      pstride, st);
+    RB_REQUIRE(cnt > 0, RB_EUNSUPPORTED, "fused red-black sweep: no tile plan for this grid");
+    fsegs.n = 1;
+    fsegs.off[0] = 0;
+    fsegs.cnt[0] = cnt;
+    return;
+  }
   // colour class c from the latest values of the others; its y^T r partials go to
   // segment c (only from the sweep that leaves the class final)
   auto sweep = [&](int color, bool dots) {
@@ -287,6 +313,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
 
 // the partial-sum segments of y^T r for this solve's smoother
 const Segs& BatchSolver::dot_segs() const {
+  if (opt.solver != RB_SOLVER_CG && fused()) return fsegs;
   const bool gs = opt.solver != RB_SOLVER_CG &&
                   (opt.smoother == RB_SMOOTH_RBGS || opt.smoother == RB_SMOOTH_RBGS_SYM);
   return gs ? gsegs : jsegs;
@@ -298,6 +325,7 @@ void BatchSolver::init_cg() {
   const int64_t L_ = ld();
   hipStream_t st = s();
   launch_fill<double>(x.as<double>(), L_, L_, B, 0.0, st);
+  launch_fill<double>(xc.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(p0.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(p1.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(r0.as<double>(), L_, L_, rrows, 0.0, st);  // also zeroes the padding
@@ -335,16 +363,22 @@ void BatchSolver::iterate_cg(int k) {
                                  q.beta, q.active, part_m.as<double>(), st);
   }
   launch_fin_alpha(part_m.as<double>(), cN, ca, q, B, st);
-  // x += alpha p, r -= alpha A p
+  // x += alpha p (into the correction xc), r -= alpha A p
   {
     ProfScope ps(ctx, "pass_b", st);
-    cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, x.as<double>(), rin, rout, q.alpha,
+    cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, xc.as<double>(), rin, rout, q.alpha,
                        q.active, part_m.as<double>(), st);
   }
-  // stopping test: recursive, then the true residual of the flagged queries
+  // stopping test: recursive, then the true residual of the flagged queries, formed from x
+  // after the correction accumulated since the previous check is folded into it.  The
+  // iterate is x + xc either way; keeping the updates apart from x until a check makes
+  // their rounding errors relative to the small correction rather than to x, so a
+  // residual replacement is not undone by the rounding of the next cycle's updates
+  // (group-wise updating, van der Vorst and Ye 2000).
   const bool fixed = opt.fixed_iters > 0;
   launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st);
   if (!fixed) {
+    launch_fold(q.flag, B, x.as<double>(), xc.as<double>(), L_, st);
     ProfScope ps(ctx, "true_residual", st);
     double* p2 = opt.floor_factor > 0.0 ? part_m2.as<double>() : nullptr;
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
@@ -453,6 +487,7 @@ void BatchSolver::final_true_residual() {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
+  if (xc.p) launch_fold(nullptr, B, x.as<double>(), xc.as<double>(), L_, st);
   double* tmp = r0.as<double>();
   launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), tmp, 1, f_base, f_ld,
                scale_d.as<double>(), ones_d.as<int>(), part_m.as<double>(), st);
@@ -543,11 +578,31 @@ void BatchSolver::autotune() {
       if (t3 < tg) { tg = t3; best.qpb_gs = c; best.kind_gs = kind; }
     }
   }
+  if (fused_ok) {  // both colours in one launch, against two single-colour sweeps
+    for (int c : caps) {
+      if (c > B || c > 2) break;
+      cur = best;
+      cur.qpb_gs = c;
+      cur.kind_gs = 3;
+      set_stencil_tiles(cur);
+      int cnt = 0;
+      const float t4 = timed([&] {
+        cnt = y32 ? launch_gs_fused<float>(g, B, coef.as<double>(), z.as<float>(), y.as<float>(),
+                                           L_, r0.as<double>(), L_, nullptr, L_, q.active,
+                                           part_r0.as<double>(), nullptr, pstride, st)
+                  : launch_gs_fused<double>(g, B, coef.as<double>(), z.as<double>(),
+                                            y.as<double>(), L_, r0.as<double>(), L_, nullptr, L_,
+                                            q.active, part_r0.as<double>(), nullptr, pstride, st);
+      });
+      if (cnt > 0 && t4 < 2.f * tg) { tg = 0.5f * t4; best.qpb_gs = c; best.kind_gs = 3; }
+    }
+  }
   if (n > 0 && !plan.wsplit) {
     float tp = 1e30f;
     for (int target : {256, 512, 1024, 2048, 4096}) {
       ProjPlan pl = plan_projection(g.N, B, n, target);
       pl.padded = true;
+      plan_wave_chunks(pl, B, target, opt.precond_prec);
       if (pl.chunks == 0) continue;
       const float t = timed([&] {
         launch_projection(pl, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
@@ -561,6 +616,7 @@ void BatchSolver::autotune() {
     }
     plan = plan_projection(g.N, B, n, best.proj_target);
     plan.padded = true;
+    plan_wave_chunks(plan, B, best.proj_target, opt.precond_prec);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

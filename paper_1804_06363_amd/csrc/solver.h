@@ -37,6 +37,13 @@ struct BatchSolver {
   std::vector<int> nu_h;
   Buf qlist;  // active queries in increasing order, then their count (batched coarse step)
   Buf x, r0, r1, p0, p1, y, z;
+  Buf xc;  // RBCG / CG: x-updates since the last true-residual check (folded into x there)
+  // fused red-black sweep (3D grids with nx <= 255, one forward sweep): the coarse
+  // correction goes to zs (black half) and one launch writes y from it
+  bool fused_ok = false;
+  Buf zs;
+  Segs fsegs;
+  bool fused() const { return fused_ok && tc.kind_gs == 3; }
   Buf part_m, part_m2, part_r0, part_r1;
   Buf qbuf;  // QState arrays
   QState q{};

@@ -1050,6 +1050,268 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   if (FLEX && part1) store(a1, part1);
 }
 
+// ---- one forward red-black sweep, both colours in one walk along z (3D, nx <= 255) ------
+// y = S(A, rhs, z) for a start z that is zero on the red nodes: red on plane k from z's
+// black values, then black on plane k-1 from the new red values of planes k-2 .. k.  z's
+// black values come from zs (its black half), which nothing writes during the sweep, and
+// each node of y is written once, by the block that owns it: the red values a block's
+// black updates need from outside its tile (the halo rows, and the planes just outside
+// its slab) it recomputes itself.  So no block reads what another block writes.  The
+// update is k_gs_color's, face by face in the same order and precision: y equals the two
+// colour sweeps' y bit for bit.
+// A block owns QPB queries, rows j0 .. j0+zr-1 of every plane (whole rows) and a slab of
+// planes.  LDS holds per query three planes of z's black values (rows j0-2 .. j0+zr+1)
+// and three planes of new red values (rows j0-1 .. j0+zr), one slot per column pair
+// (2u, 2u+1) of a row, which holds the pair's node of the stored colour.  A row's nodes of
+// one colour are consecutive storage positions, so every load of a plane is contiguous.
+// z's values are loaded a step ahead; the right-hand sides at the start of their step.
+// Partial sums of y^T rhs (and y^T rhs2) go to part[b * tiles + tile].
+constexpr int kFusedSlots = 3;  // slots (row, pair) per thread: (zr + 4) * pairs <= 1536
+
+template <int QPB, typename TY, bool FLEX>
+__global__ __launch_bounds__(kZThreads) void k_gs_fused(StencilGeom g, ZTile zt, int B,
+                                                        const double* coef,
+                                                        const TY* __restrict__ zs,
+                                                        TY* __restrict__ y, int64_t y_ld,
+                                                        const double* __restrict__ rhs,
+                                                        int64_t rhs_ld,
+                                                        const double* __restrict__ rhs2,
+                                                        int64_t rhs2_ld,
+                                                        const int* __restrict__ active,
+                                                        double* __restrict__ part0,
+                                                        double* __restrict__ part1) {
+  constexpr int NW = kZThreads / 64;
+  constexpr int NS = kFusedSlots;
+  extern __shared__ double dyn[];
+  __shared__ double red[NW * QPB];
+  const int tiles = zt.rt * zt.slabs;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % tiles;
+  const int q0 = (blk / tiles) * QPB;
+  const int slab = tile / zt.rt, rtile = tile % zt.rt;
+  const int PR = (g.nx + 1) >> 1;  // column pairs per row
+  const int ZR2 = zt.zr + 2, ZR4 = zt.zr + 4;
+  const int zpl = ZR4 * PR, rpl = ZR2 * PR;  // slots of one LDS plane
+  const int qst = 3 * (zpl + rpl);           // LDS per query
+  TY* cfs = reinterpret_cast<TY*>(dyn);
+  TY* lz = cfs + QPB * g.ct_size;  // [QPB][3][ZR4][PR] z's black values
+  TY* lr = lz + 3 * zpl;           // [QPB][3][ZR2][PR] new red values (offset by query)
+  const unsigned mask = load_group<QPB, TY>(g, coef, q0, B, active, cfs);
+  if (!mask) return;
+  const int j0 = rtile * zt.zr;
+  const int k0 = slab * zt.kslab;
+  const int k1 = min(g.nz, k0 + zt.kslab);
+  const int kfirst = max(k0 - 1, 0);
+  const int nzm = g.nz - 1;
+  int* zinfo = reinterpret_cast<int*>(cfs + QPB * g.ct_size + QPB * qst);  // [k - kfirst][3]
+  for (int kk = threadIdx.x; kk <= k1 - kfirst && kfirst + kk <= nzm; kk += kZThreads) {
+    const uint32_t tz = g.tab[2][kfirst + kk];
+    zinfo[3 * kk] = tz & 0xff;
+    zinfo[3 * kk + 1] = g.ct_off[2] + (int)((tz >> 8) & 0xff) * g.ct_s1[2] * g.ct_s2[2];
+    zinfo[3 * kk + 2] = g.ct_off[2] + (int)((tz >> 16) & 0xff) * g.ct_s1[2] * g.ct_s2[2];
+  }
+  auto live = [&](int q) { return ((mask >> q) & 1u) != 0; };
+  // storage position of the node of pair u in row j of plane k with colour c (0 red)
+  auto spos = [&](int j, int k, int u, int c) {
+    const int rb = k * g.nxy + j * g.nx, par = (j + k) & 1;
+    return c ? g.NR + ((rb - par) >> 1) + u : ((rb + par) >> 1) + u;
+  };
+  // the node of colour c in pair u of row j, plane k: column 2u + ((j + k + c) & 1)
+  auto col = [&](int j, int k, int u, int c) { return 2 * u + ((j + k + c) & 1); };
+
+  // slots of this thread: s = threadIdx.x + m * kZThreads is (window row s / PR, pair
+  // s % PR); the window of the red updates starts at row j0 - 1, that of the staged z
+  // values at row j0 - 2
+  int wr[NS], su[NS];
+  int cb[NS][2][4], zxy[NS][2];
+  unsigned inb[NS][2];
+  bool cex[NS][2];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int sl = threadIdx.x + m * kZThreads;
+    wr[m] = sl / PR;
+    su[m] = sl - wr[m] * PR;
+    const int j = j0 - 1 + wr[m];
+    const bool rowok = wr[m] < ZR2 && j >= 0 && j < g.ny;
+    const int jc = rowok ? j : 0;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int i = 2 * su[m] + c2;
+      cex[m][c2] = rowok && i < g.nx;
+      const int ic = cex[m][c2] ? i : 0;
+      const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
+      const int sx = tx & 0xff, sy = ty & 0xff;
+      cb[m][c2][0] = g.ct_off[0] + ((int)((tx >> 8) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+      cb[m][c2][1] = g.ct_off[0] + ((int)((tx >> 16) & 0xff) * g.ct_s1[0] + sy) * g.ct_s2[0];
+      cb[m][c2][2] = g.ct_off[1] + ((int)((ty >> 8) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+      cb[m][c2][3] = g.ct_off[1] + ((int)((ty >> 16) & 0xff) * g.ct_s1[1] + sx) * g.ct_s2[1];
+      zxy[m][c2] = sx * g.ct_s2[2] + sy;
+      inb[m][c2] = (ic > 0 ? 1u : 0u) | (ic < g.nx - 1 ? 2u : 0u) | (jc > 0 ? 4u : 0u) |
+                   (jc < g.ny - 1 ? 8u : 0u);
+    }
+  }
+  size_t rowy[QPB], rowr[QPB], rowr2[QPB];
+#pragma unroll
+  for (int q = 0; q < QPB; ++q) {
+    const int b = min(q0 + q, B - 1);
+    rowy[q] = (size_t)b * y_ld;
+    rowr[q] = (size_t)b * rhs_ld;
+    rowr2[q] = FLEX ? (size_t)b * rhs2_ld : 0;
+  }
+  struct ZV {
+    TY v[NS][QPB];
+  };
+  struct RV {
+    double r[NS][QPB], r2[NS][QPB];
+  };
+  // z's black values of plane k, staging rows j0-2 .. j0+zr+1 (every load unconditional,
+  // from a valid address: position 0 where the node does not exist)
+  auto load_z = [&](ZV& t, int k) __attribute__((always_inline)) {
+    const int kc = min(max(k, 0), nzm);
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int sl = threadIdx.x + m * kZThreads;
+      const int w = sl / PR, u = sl - w * PR, j = j0 - 2 + w;
+      const bool ok = k >= 0 && k <= nzm && w < ZR4 && j >= 0 && j < g.ny &&
+                      col(j, kc, u, 1) < g.nx;
+      const int pos = ok ? spos(j, kc, u, 1) : 0;
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) t.v[m][q] = zs[rowy[q] + pos];
+    }
+  };
+  auto store_z = [&](const ZV& t, int k) __attribute__((always_inline)) {
+    if (k < 0 || k > nzm) return;
+    TY* dst = lz + (k % 3) * zpl;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int sl = threadIdx.x + m * kZThreads;
+      if (sl < zpl)
+#pragma unroll
+        for (int q = 0; q < QPB; ++q) dst[q * qst + sl] = t.v[m][q];
+    }
+  };
+  // right-hand sides at the nodes of colour c of this thread's slots on plane k (red:
+  // every window row; black: the tile rows)
+  auto load_r = [&](RV& t, int k, int c) __attribute__((always_inline)) {
+    const int kc = min(max(k, 0), nzm);
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int j = j0 - 1 + wr[m];
+      const bool rows = c ? (wr[m] >= 1 && wr[m] <= zt.zr) : true;
+      const bool ok = k >= 0 && k <= nzm && rows &&
+                      ((col(j, kc, su[m], c) & 1) ? cex[m][1] : cex[m][0]);
+      const int pos = ok ? spos(j, kc, su[m], c) : 0;
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) {
+        t.r[m][q] = rhs[rowr[q] + pos];
+        if (FLEX) t.r2[m][q] = rhs2[rowr2[q] + pos];
+      }
+    }
+  };
+
+  double a0[QPB], a1[QPB];
+#pragma unroll
+  for (int q = 0; q < QPB; ++q) a0[q] = a1[q] = 0.0;
+
+  // colour c on plane k of the slots whose window rows lie in [wlo, whi]: neighbours from
+  // LDS plane array `nb` (three planes of pitch npl; the slot's row in it is wr + roff),
+  // right-hand sides from t; write y and the dots on the tile rows of the slab
+  auto update = [&](int k, int c, const TY* nb, int npl, int roff,
+                    const RV& t) __attribute__((always_inline)) {
+    const int kk = k - kfirst;
+    const int sz = zinfo[3 * kk], zlo = zinfo[3 * kk + 1], zhi = zinfo[3 * kk + 2];
+    const unsigned zb = (k > 0 ? 16u : 0u) | (k < nzm ? 32u : 0u);
+    const TY* p0 = nb + (k % 3) * npl;
+    const TY* pm = nb + ((k + 2) % 3) * npl;  // plane k - 1
+    const TY* pp = nb + ((k + 1) % 3) * npl;  // plane k + 1
+    const bool inslab = k >= k0 && k < k1;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int j = j0 - 1 + wr[m];
+      const int c2 = col(j, k, su[m], c) & 1;  // (selects below keep the arrays in registers)
+      if (!(c2 ? cex[m][1] : cex[m][0])) continue;
+      const bool tilerow = wr[m] >= 1 && wr[m] <= zt.zr;
+      if (c && !tilerow) continue;  // black: tile rows only
+      const unsigned inner = (c2 ? inb[m][1] : inb[m][0]) | zb;
+      const int zx = c2 ? zxy[m][1] : zxy[m][0];
+      const int ci[6] = {(c2 ? cb[m][1][0] : cb[m][0][0]) + sz,
+                         (c2 ? cb[m][1][1] : cb[m][0][1]) + sz,
+                         (c2 ? cb[m][1][2] : cb[m][0][2]) + sz,
+                         (c2 ? cb[m][1][3] : cb[m][0][3]) + sz, zlo + zx, zhi + zx};
+      const int r0 = (wr[m] + roff) * PR, u = su[m];
+      const int ixl = r0 + max(u - 1 + c2, 0), ixh = r0 + u + c2;
+      const bool out = inslab && tilerow;
+      const int pos = spos(j, k, u, c);
+#pragma unroll
+      for (int q = 0; q < QPB; ++q) {
+        if (!live(q)) continue;
+        const TY* cf = cfs + q * g.ct_size;
+        const int qo = q * qst;
+        const TY nv[6] = {p0[qo + ixl], p0[qo + ixh], p0[qo + r0 - PR + u], p0[qo + r0 + PR + u],
+                          pm[qo + r0 + u], pp[qo + r0 + u]};
+        TY d = TY(0), off = TY(0);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const TY cc = cf[ci[f]];
+          d += cc;
+          off += cc * (((inner >> f) & 1u) ? nv[f] : TY(0));
+        }
+        const double fp = t.r[m][q];
+        const TY v = (TY)(((TY)fp + off) / d);
+        if (!c) lr[qo + (k % 3) * rpl + wr[m] * PR + u] = v;
+        if (out) {
+          y[rowy[q] + pos] = v;
+          a0[q] += (double)v * fp;
+          if (FLEX) a1[q] += (double)v * t.r2[m][q];
+        }
+      }
+    }
+  };
+
+  // z planes kfirst - 1 and kfirst into LDS, plane kfirst + 1 in flight
+  ZV Za, Zb;
+  RV Rk, Bk;
+  load_z(Za, kfirst - 1);
+  store_z(Za, kfirst - 1);
+  load_z(Za, kfirst);
+  store_z(Za, kfirst);
+  load_z(Za, kfirst + 1);
+  auto step = [&](int k, ZV& Zn, ZV& Zn2) __attribute__((always_inline)) {
+    // Zn = z plane k + 1 (loaded a step ahead); this step's right-hand sides are issued
+    // first and arrive while the block waits at the barriers and updates the red plane
+    load_r(Rk, k, 0);
+    load_r(Bk, k - 1, 1);
+    store_z(Zn, k + 1);
+    load_z(Zn2, k + 2);
+    __syncthreads();  // z plane k + 1 (and zinfo) visible; the black updates of k - 2 done
+    if (k <= nzm) update(k, 0, lz, zpl, 1, Rk);
+    __syncthreads();  // red plane k visible
+    if (k - 1 >= k0) update(k - 1, 1, lr, rpl, 0, Bk);
+  };
+  for (int k = kfirst; k <= k1; k += 2) {
+    step(k, Za, Zb);
+    if (k + 1 <= k1) step(k + 1, Zb, Za);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  auto store = [&](const double (&acc)[QPB], double* part) {
+    __syncthreads();  // red is free
+#pragma unroll
+    for (int q = 0; q < QPB; ++q) {
+      const double v = rbk::wave_sum(acc[q]);
+      if (lane == 0) red[q * NW + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < QPB && live(threadIdx.x)) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) t += red[threadIdx.x * NW + i];
+      part[(size_t)(q0 + threadIdx.x) * tiles + tile] = t;
+    }
+  };
+  if (part0) store(a0, part0);
+  if (FLEX && part1) store(a1, part1);
+}
+
 // ---- damped Jacobi: y = z + omega D^-1 (rhs - A z), partial y^T rhs (and y^T rhs2) ------
 template <int DIM, int QPB, typename TY>
 __global__ __launch_bounds__(kThreads) void k_jacobi(StencilGeom g, int B, int chunks,
@@ -1373,6 +1635,73 @@ static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, con
     by_q(std::false_type{});
   return tiles;
 }
+
+// Tile of the fused sweep: whole rows (nx <= 255), zr <= 16 rows such that the staged
+// window of zr + 4 rows fits the threads' slots and the LDS stays within 64 KB; slabs as
+// for the marching passes.  lds = dynamic LDS bytes.
+static bool zf_plan(const StencilGeom& g, int groups, int cap, int qpb, size_t tysz, ZTile& zt,
+                    size_t& lds) {
+  if (!gs_fused_supported(g)) return false;
+  const int PR = (g.nx + 1) / 2;
+  auto lds_of = [&](int zr, int kslab) {
+    return (size_t)qpb * (g.ct_size + 3 * (2 * zr + 6) * PR) * tysz +
+           (size_t)3 * (kslab + 2) * sizeof(int);
+  };
+  int zr = std::min({g.ny, 16, kFusedSlots * kZThreads / PR - 4});
+  while (zr >= 1 && lds_of(zr, g.nz) > 65536) --zr;
+  if (zr < 1) return false;
+  zt.zr = zr;
+  zt.zc = g.nx;
+  zt.ct = 1;
+  zt.rt = (g.ny + zr - 1) / zr;
+  if (zt.rt > cap) return false;
+  int slabs = (2048 + groups * zt.rt - 1) / (groups * zt.rt);
+  slabs = std::max(1, std::min({slabs, g.nz / 8, cap / zt.rt}));
+  zt.kslab = (g.nz + slabs - 1) / slabs;
+  zt.slabs = (g.nz + zt.kslab - 1) / zt.kslab;
+  lds = lds_of(zr, zt.kslab);
+  return true;
+}
+
+bool gs_fused_supported(const StencilGeom& g) {
+  return g.dim == 3 && !g.csr && g.C == 2 && g.nx <= 255;
+}
+
+template <typename TY>
+int launch_gs_fused(const StencilGeom& g, int B, const double* coef, const TY* zs, TY* y,
+                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs2,
+                    int64_t rhs2_ld, const int* active, double* part0, double* part1, int cap,
+                    hipStream_t s) {
+  // 1 or 2 queries per block (4 would spill registers)
+  const int qpb = (t_tiles.qpb_gs ? t_tiles.qpb_gs : 2) >= 2 && B >= 2 ? 2 : 1;
+  ZTile zt;
+  size_t lds = 0;
+  const int groups = (B + qpb - 1) / qpb;
+  if (!zf_plan(g, groups, cap, qpb, sizeof(TY), zt, lds)) return 0;
+  const int tiles = zt.rt * zt.slabs;
+  const dim3 grid((unsigned)(tiles * groups));
+  auto go = [&](auto Q, auto F) {
+    hipLaunchKernelGGL((k_gs_fused<Q.value, TY, F.value>), grid, dim3(kZThreads), lds, s, g, zt, B,
+                       coef, zs, y, y_ld, rhs, rhs_ld, rhs2, rhs2_ld, active, part0, part1);
+  };
+  auto by_q = [&](auto F) {
+    if (qpb == 2)
+      go(std::integral_constant<int, 2>{}, F);
+    else
+      go(std::integral_constant<int, 1>{}, F);
+  };
+  if (rhs2)
+    by_q(std::true_type{});
+  else
+    by_q(std::false_type{});
+  return tiles;
+}
+template int launch_gs_fused<double>(const StencilGeom&, int, const double*, const double*,
+                                     double*, int64_t, const double*, int64_t, const double*,
+                                     int64_t, const int*, double*, double*, int, hipStream_t);
+template int launch_gs_fused<float>(const StencilGeom&, int, const double*, const float*, float*,
+                                    int64_t, const double*, int64_t, const double*, int64_t,
+                                    const int*, double*, double*, int, hipStream_t);
 
 template <typename TY>
 int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,

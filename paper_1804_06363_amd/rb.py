@@ -321,7 +321,7 @@ class Basis:
             pass
 
 
-STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2}
+STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2, "fused": 3}
 
 
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,

@@ -201,7 +201,8 @@ def test_uneven_configuration(lib, ctx):
     2x2x2; mu log-uniform in [0.01, 100]) and basis sizes 10, 20, 40, 60 mixed in one call
     with the benchmark's options (FP32 preconditioner, flexible beta, HIP graphs,
     floor_factor 16, 1e-9 on 1023^2), 256 of its 1024 queries: every query meets its
-    tolerance or is accepted at the rounding level, and sampled queries on the 63^2 and
+    tolerance or is accepted at the rounding level within 2x the residual of its exact
+    solution rounded to doubles, and sampled queries on the 63^2 and
     63^3 grids match the oracle's RBCG with the same leading basis vectors (solutions
     within 2 kappa rtol of each other)."""
     import torch
@@ -222,7 +223,18 @@ def test_uneven_configuration(lib, ctx):
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
     assert (st.status == lib.RB_OK).all()
     assert ((st.rel_res_true <= tol) | (st.at_floor == 1)).all()
-    assert (st.rel_res_true[st.at_floor == 1] <= 1e-7).all()
+    # a query accepted above its tolerance (rounding-level test) must sit at what FP64 can
+    # reach for it: within 2x the FP64-evaluated residual of its exact solution rounded to
+    # doubles (the oracle's refined direct solve)
+    above = np.flatnonzero(st.rel_res_true > tol)
+    assert len(above) <= 4, above
+    for k in above:
+        g = qs[k][0]
+        exact, fp64, _ = orb.residual_floor(BlockDiffusion(UNEVEN_GRIDS[g].dims,
+                                                           UNEVEN_GRIDS[g].blocks), qs[k][2])
+        print(f"query {k} ({UNEVEN_GRIDS[g].name}): true residual {st.rel_res_true[k]:.2e}, "
+              f"tolerance {tol[k]:.0e}, FP64 floor {fp64:.2e} (exact evaluation {exact:.2e})")
+        assert st.rel_res_true[k] <= 2.0 * fp64
     # sampled queries of the small grids against the oracle (same basis, same n_use)
     names = [wk.name for wk in UNEVEN_GRIDS]
     want = [("u2d63", 10), ("u2d63", 60), ("u3d63", 60)]

@@ -357,6 +357,81 @@ def test_rbi_parity(lib, ctx, smoother):
         assert _rel(x[b], xr) <= 1e-10
 
 
+# 3D grids for the fused red-black sweep (whole rows, nx <= 255): one row tile and one
+# slab; two row tiles (the second ragged) and several slabs; 255-column rows (one row
+# tile in FP32, several in FP64, whose LDS budget takes fewer rows); 129 columns with
+# few rows; four row tiles and several slabs
+FGRIDS = [((7, 9, 5), (2, 2, 3)), ((31, 31, 31), (2, 2, 2)), ((255, 7, 9), (2, 2, 2)),
+          ((129, 5, 9), (2, 2, 2)), ((63, 63, 63), (2, 2, 2))]
+
+
+@pytest.mark.parametrize("dims,blocks", FGRIDS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("B", [1, 2, 5])
+def test_fused_sweep_equals_colour_sweeps(lib, ctx, dims, blocks, prec, B):
+    """One RBI application with both colours of the Gauss-Seidel sweep in one marching
+    launch gives the two single-colour sweeps' y bit for bit (the same update per node from
+    the same coarse correction), and the oracle's to rounding (1e-12 FP64)."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 3, seed=70)
+    theta = log_uniform_mu(71, B, op.Q, 0.1, 10.0)
+    r = random_vectors(72, B, op.N)
+    yf = lib.precond_batch(ctx, prob, basis, theta, _t(r), prec=prec, stencil="fused")
+    yc = lib.precond_batch(ctx, prob, basis, theta, _t(r), prec=prec, stencil="chunked")
+    yf, yc = yf.cpu().numpy(), yc.cpu().numpy()
+    assert np.array_equal(yf, yc)
+    if prec == "fp64":
+        for b in range(B):
+            _, M = orb.make_preconditioner(op, theta[b], W)
+            assert _rel(yf[b], M(r[b])) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,blocks", FGRIDS)
+@pytest.mark.parametrize("flexible", [False, True])
+def test_fused_sweep_fixed_iterations(lib, ctx, dims, blocks, flexible):
+    """RBCG with the fused sweep: k fixed iterations against the oracle's iterates (1e-10)
+    and against the single-colour sweeps (only the summation order of y^T r differs:
+    1e-12)."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 4, seed=73)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(74, 5, op.Q, 0.1, 10.0)
+    k = 7
+    xf, sf = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="fused",
+                             flexible=flexible)
+    xc, _ = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="chunked",
+                            flexible=flexible)
+    xf, xc = xf.cpu().numpy(), xc.cpu().numpy()
+    for b in range(5):
+        ref = orb.solve_rbcg(op, theta[b], W, AN, fixed_iters=k, flexible=flexible)
+        assert sf.iters[b] == k
+        assert _rel(xf[b], ref.x) <= 1e-10, (b, _rel(xf[b], ref.x))
+        assert _rel(xf[b], xc[b]) <= 1e-12, (b, _rel(xf[b], xc[b]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_sweep_converged(lib, ctx, prec):
+    """Converged solves with the fused sweep: queries retire at different iterations
+    (masked queries in a block), FP64 and FP32 preconditioners, flexible beta."""
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 6, seed=30)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
+    theta = log_uniform_mu(62, 9, op.Q, 0.01, 100.0)
+    x, st = lib.solve_batch(ctx, prob, basis, theta, prec=prec, flexible=True, stencil="fused")
+    x = x.cpu().numpy()
+    assert len(set(st.iters.tolist())) > 1
+    h = 1.0 / (dims[0] + 1)
+    for b in range(len(theta)):
+        ref = orb.solve_rbcg(op, theta[b], W, AN, flexible=True)
+        assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
+        if prec == "fp64":
+            assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
+        kappa = (theta[b].max() * 12.0 / h**2) / (
+            theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
+        assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
+
+
 @pytest.mark.parametrize("smoother", ["rbgs", "rbgs_sym"])
 def test_rbi_marching_sweep(lib, ctx, smoother):
     """RBI smooths A x = phi f from one shared row f scaled per query: the marching colour

@@ -368,3 +368,17 @@ def test_residual_replacement_restarts_on_the_residual_equation():
         want = xk + e
         got = res.iterates[k - 1 + m]
         assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(e), m
+
+
+def test_residual_floor_small_grid():
+    """On a 15x15 grid the refined direct solution equals the dense solve, and its residual
+    is at the level of the rounding of x (relative eps times the conditioning of the
+    residual evaluation), far below any tolerance used by the solvers."""
+    op = BlockDiffusion((15, 15), (2, 2))
+    th = np.array([0.01, 100.0, 3.0, 0.5])
+    exact, fp64, x = rb.residual_floor(op, th)
+    xd = np.linalg.solve(op.assemble(th).toarray(), op.rhs())
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+    assert exact <= 1e-13 and fp64 <= 1e-13
+    # the FP64 evaluation equals the residual formed directly
+    assert fp64 == np.linalg.norm(op.rhs() - op.assemble(th).tocsc() @ x) / np.linalg.norm(op.rhs())
