@@ -6,13 +6,15 @@ Workload (synthetic, seeded): 3D 7-point diffusion on a 127^3 interior grid
 (P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, residual
 indicator) over 256 training parameters; 256 test parameters per call.  A step is
 one rb_solve_batch of the 256 queries to relative residual 1e-10 (RBCG of Alg. 3,
-FP32 preconditioner, FP64 CG), its kernels timed one by one with HIP events.  value =
-converged mu-solves per second.  Also: the same solves replayed from a captured HIP graph
-(two iterations per launch, no per-kernel events) as `graph_replay`.
+FP32 preconditioner with four red-black Gauss-Seidel sweeps per application, FP64 CG),
+its kernels timed one by one with HIP events.  value = converged mu-solves per second.
+Also: the same solves replayed from a captured HIP graph (two iterations per launch, no
+per-kernel events) as `graph_replay`.
 
-Also reported: the plain path (same library, FP64 everywhere, one query per call),
-the roofline of the dominant kernel (pass B of the iteration: x += alpha p,
-r -= alpha A p), and the CPU oracle on a bounded sample.
+Also reported: the plain path (same library and smoother, FP64 everywhere, one query per
+call), the roofline of the dominant kernel (pass B of the iteration: x += alpha p,
+r -= alpha A p) and of the whole solve, the differences from the FP64 oracle per
+precision, and the CPU oracle on a bounded sample.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -92,6 +94,12 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--B", type=int, default=0, help="queries per call (default: workload's)")
     ap.add_argument("--flexible", type=int, default=0)
+    ap.add_argument("--sweeps", type=int, default=4,
+                    help="red-black Gauss-Seidel sweeps per preconditioner application (the "
+                         "smoother study on this workload: 1 -> 133.6, 2 -> 157.3, 3 -> 174.5, "
+                         "4 -> 178.2, 6 -> 177.3 mu-solves/s)")
+    ap.add_argument("--uneven-sweeps", type=int, default=1,
+                    help="Gauss-Seidel sweeps per preconditioner application in the uneven batch")
     ap.add_argument("--graph", type=int, default=0,
                     help="time the main steps with the iterations replayed from a captured HIP "
                          "graph (the per-kernel events then see no launches: roofline null)")
@@ -117,9 +125,9 @@ def main():
     ap.add_argument("--mixed-error", type=int, default=1,
                     help="also solve the batch with the BF16 preconditioner and report every "
                          "precision's difference from the oracle on the CPU sample")
-    ap.add_argument("--smoother-study", type=int, default=0,
-                    help="also time the batch with each smoother variant (sweeps, symmetric, "
-                         "Jacobi)")
+    ap.add_argument("--smoother-study", default="",
+                    help="also time the batch with each smoother variant of this list "
+                         "(e.g. rbgs:1,rbgs:2,rbgs_sym:1,jacobi:1; 'all' for a default set)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the "
@@ -131,7 +139,7 @@ def main():
     from workloads import WORKLOADS
 
     if args.uneven_only:
-        print(json.dumps({"uneven_batch": uneven_leg(rb, torch)}), flush=True)
+        print(json.dumps({"uneven_batch": uneven_leg(rb, torch, args.uneven_sweeps)}), flush=True)
         return
 
     if args.copy_calib > 0:
@@ -170,11 +178,12 @@ def main():
             basis.save(args.basis)
     test = w.test_mu(B)
     x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
-    opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph))
+    opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
+                         sweeps=args.sweeps)
 
     # warm-up solves autotune the batched kernels' tiles (kept in the context)
     wopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
-                          autotune=True)
+                          autotune=True, sweeps=args.sweeps)
     for i in range(args.warmup):
         _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=wopts)
         log(f"warmup {i}: iters mean {st.iters.mean():.1f} max {st.iters.max()} "
@@ -228,8 +237,9 @@ def main():
     # start and the final true residual, over the wall time of a step
     s_y = 8 if args.prec == "fp64" else 4
     s_w = {"fp64": 8, "fp32": 4, "bf16": 2}[args.prec]
-    path_bytes = sum(float(N) * (64 + 2 * s_y + 1.5 * s_w * basis.n / B) * float(ss.iters.sum())
-                     + 24.0 * N * B for ss in stats)
+    # each sweep beyond the first reads r and y and writes y: N (8 + 2 s_y) more
+    per_it = 64 + 2 * s_y + 1.5 * s_w * basis.n / B + (args.sweeps - 1) * (8 + 2 * s_y)
+    path_bytes = sum(float(N) * per_it * float(ss.iters.sum()) + 24.0 * N * B for ss in stats)
     path_gbs = path_bytes / elapsed / 1e9
     roofline["path_model_bytes_per_step"] = round(path_bytes / args.steps)
     roofline["path_achieved"] = round(path_gbs, 1)
@@ -240,7 +250,8 @@ def main():
     # the same solves with the iterations replayed from a captured HIP graph
     graph_leg = None
     if args.graph_leg and not args.graph:
-        gopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=True)
+        gopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=True,
+                              sweeps=args.sweeps)
         rb.solve_batch(ctx, prob, basis, test, x=x, opts=gopts)  # capture
         torch.cuda.synchronize()
         tg = time.perf_counter()
@@ -260,7 +271,7 @@ def main():
     x_plain = {}
     if args.plain_sample > 0:
         S = min(args.plain_sample, B)
-        popts = rb.solve_opts(prec="fp64")
+        popts = rb.solve_opts(prec="fp64", sweeps=args.sweeps)
         xs = torch.empty((1, N), dtype=torch.float64, device="cuda:0")
         rb.solve_batch(ctx, prob, basis, test[:1], x=xs, opts=popts)  # warm-up
         torch.cuda.synchronize()
@@ -283,7 +294,7 @@ def main():
     oracle_error = None
     if args.cpu_baseline:
         S = min(args.cpu_sample, B)
-        cpu, x_orc = cpu_baseline(basis, w, test[:S])
+        cpu, x_orc = cpu_baseline(basis, w, test[:S], args.sweeps)
         # difference of each precision's solutions from the oracle's FP64 RBCG on the same
         # basis: ||x - x_oracle|| / ||x_oracle|| for the sampled queries
         def errs(xg):
@@ -295,7 +306,8 @@ def main():
         if args.mixed_error and args.prec == "fp32":
             xb = torch.empty_like(x)
             _, sb = rb.solve_batch(ctx, prob, basis, test, x=xb,
-                                   opts=rb.solve_opts(prec="bf16", flexible=bool(args.flexible)))
+                                   opts=rb.solve_opts(prec="bf16", flexible=bool(args.flexible),
+                                                      sweeps=args.sweeps))
             oracle_error["bf16"] = errs(xb.cpu().numpy())
             oracle_error["bf16_iters_mean"] = round(float(sb.iters.mean()), 2)
             del xb
@@ -304,7 +316,8 @@ def main():
     extra = {}
     if args.smoother_study:
         extra["smoother_study"] = smoother_study(rb, ctx, prob, basis, test, x, args)
-    for flag, name, fn in ((args.uneven, "uneven_batch", lambda: uneven_leg(rb, torch)),
+    for flag, name, fn in ((args.uneven, "uneven_batch",
+                            lambda: uneven_leg(rb, torch, args.uneven_sweeps)),
                            (args.learned, "learned_greedy", lambda: learned_leg(rb)),
                            (args.fem, "fem_cases", lambda: fem_leg(rb, torch))):
         if flag:
@@ -326,6 +339,7 @@ def main():
                                f"n={basis.n}, B={B}, {args.prec} preconditioner",
                    "N": N, "B": B, "n": basis.n, "Q": Q, "prec": args.prec,
                    "beta": "flexible" if args.flexible else "literal",
+                   "smoother": f"red-black Gauss-Seidel x{args.sweeps}",
                    "graph": bool(args.graph), "parallelism": "single-gpu"},
         "step_ms": [round(v * 1e3, 2) for v in step_s],
         "median_step_ms": round(float(np.median(step_s)) * 1e3, 2),
@@ -341,7 +355,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def uneven_leg(rb, torch):
+def uneven_leg(rb, torch, sweeps=1):
     """1024 queries mixing 2D 63^2, 255^2, 1023^2 (4x4 kappa blocks) and 3D 63^3 (2x2x2),
     mu log-uniform in [0.01, 100], per-query basis sizes n in {10, 20, 40, 60} (leading
     columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call.
@@ -367,7 +381,8 @@ def uneven_leg(rb, torch):
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
     # small bases on the 1023^2 grid need up to ~7500 iterations; a query whose FP64
     # rounding level lies above its tolerance is accepted there (at_floor, counted apart)
-    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0)
+    opts = rb.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0,
+                         sweeps=sweeps)
     rb.solve_multi(ctx, probs, bases, queries, opts=opts)  # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -396,6 +411,7 @@ def uneven_leg(rb, torch):
         f"({at_floor} accepted at the FP64 rounding level above their tolerance, not "
         f"counted), iters mean {st.iters.mean():.1f}, max rel res {st.rel_res_true.max():.2e}")
     return {"value": round(ok / el, 2), "unit": "mu-solves/s", "queries": len(qs),
+            "sweeps": sweeps,
             "converged": ok, "accepted_above_tolerance": at_floor, "seconds": round(el, 4),
             "iters_mean": round(float(st.iters.mean()), 2),
             "max_rel_res_over_rtol": float((st.rel_res_true / tol).max()), "groups": groups}
@@ -495,14 +511,18 @@ def held_out_eta(rb, ctx, prob, Wn, AN, fN, held, torch):
 
 def smoother_study(rb, ctx, prob, basis, test, x, args):
     """The same batch with each smoother of the preconditioner (Sec. 3.3 leaves the choice
-    open): one to three forward red-black Gauss-Seidel sweeps, the symmetric sweep (forward
-    then backward), damped Jacobi; mean iterations and converged mu-solves per second
-    (median of three timed solves after a warm-up that autotunes)."""
+    open): forward red-black Gauss-Seidel with several sweeps per application, the
+    symmetric sweep (forward then backward), damped Jacobi; mean iterations and converged
+    mu-solves per second (median of three timed solves after a warm-up that autotunes)."""
     import torch
+    spec = args.smoother_study
+    if spec == "all":
+        spec = "rbgs:1,rbgs:2,rbgs:3,rbgs:4,rbgs:6,rbgs_sym:1,rbgs_sym:2,jacobi:1"
     out = {}
-    for name, kw in (("rbgs", dict(smoother="rbgs")), ("rbgs_x2", dict(smoother="rbgs", sweeps=2)),
-                     ("rbgs_x3", dict(smoother="rbgs", sweeps=3)),
-                     ("rbgs_sym", dict(smoother="rbgs_sym")), ("jacobi", dict(smoother="jacobi"))):
+    for item in spec.split(","):
+        kind, m = item.split(":")
+        name = f"{kind}_x{m}"
+        kw = dict(smoother=kind, sweeps=int(m))
         o = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), **kw)
         ow = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), autotune=True, **kw)
         _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=ow)
@@ -522,7 +542,7 @@ def smoother_study(rb, ctx, prob, basis, test, x, args):
     return out
 
 
-def cpu_baseline(basis, w, thetas):
+def cpu_baseline(basis, w, thetas, sweeps=1):
     """The oracle's RBCG (NumPy/SciPy FP64) on a few queries of the same workload."""
     from oracle import rb as orb
     from oracle.operator import BlockDiffusion
@@ -540,7 +560,7 @@ def cpu_baseline(basis, w, thetas):
     t = time.perf_counter()
     its, ok, xs = [], 0, []
     for th in thetas:
-        res = orb.solve_rbcg(op, th, W, AN, rtol=1e-10)
+        res = orb.solve_rbcg(op, th, W, AN, rtol=1e-10, sweeps=sweeps)
         its.append(res.iters)
         xs.append(res.x)
         ok += int(res.converged and res.rel_res_true <= 1e-10)
@@ -556,7 +576,7 @@ def cpu_baseline(basis, w, thetas):
             t1 = time.perf_counter()
             ok1 = 0
             for th in thetas[:n1]:
-                r1 = orb.solve_rbcg(op, th, W, AN, rtol=1e-10)
+                r1 = orb.solve_rbcg(op, th, W, AN, rtol=1e-10, sweeps=sweeps)
                 ok1 += int(r1.converged and r1.rel_res_true <= 1e-10)
             el1 = time.perf_counter() - t1
         one = {"value": round(ok1 / el1, 5), "cores": 1,

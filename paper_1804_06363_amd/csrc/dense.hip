@@ -282,14 +282,16 @@ ProjPlan plan_projection(int N, int B, int n, int target_blocks) {
   return p;
 }
 
-void plan_wave_chunks(ProjPlan& p, int B, int target_waves, rb_prec prec) {
+void plan_wave_chunks(ProjPlan& p, int B, int target_blocks, rb_prec prec) {
   // with at most 64 queries the four waves of a batched block hold four 16-query tiles
   // over the same DOFs and each loads the block's basis rows; with a large basis those
   // rows outweigh the residual rows, so one wave takes all queries instead (QT = 4; the
   // FP64 basis would not fit the registers)
   if (p.wsplit || !p.padded || B <= 16 || B > 64 || p.jt < 4 || prec == RB_PREC_FP64) return;
   const int nsteps = p.kend / 16;
-  const int waves = std::max(4, target_waves);
+  // two waves per block-target unit: the default target (four blocks per CU) then gives
+  // two of these register-heavy waves per SIMD
+  const int waves = std::max(4, 2 * target_blocks);
   p.wchunk = true;
   p.qt = 4;
   p.qgroups = 1;

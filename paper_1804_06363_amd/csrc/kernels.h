@@ -138,8 +138,9 @@ void csr_from_storage(int N, const int* perm, int B, const double* sto, int64_t 
 // dense.hip
 ProjPlan plan_projection(int N, int B, int n, int target_blocks);
 // Turns a padded batched plan for 16 < B <= 64 queries and n > 48 basis vectors (FP32 or
-// BF16 basis) into wchunk mode with about target_waves waves; other plans are unchanged.
-void plan_wave_chunks(ProjPlan& p, int B, int target_waves, rb_prec prec);
+// BF16 basis) into wchunk mode with about 2 * target_blocks waves; other plans are
+// unchanged.
+void plan_wave_chunks(ProjPlan& p, int B, int target_blocks, rb_prec prec);
 // qlist (nullable; the batched path only): active queries in increasing order with their
 // count in qlist[B] (launch_compact_active); rows of other queries are then not read.
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,

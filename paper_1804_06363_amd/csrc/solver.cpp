@@ -123,7 +123,9 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   if (n > 0) {
     const size_t accb = opt.precond_prec == RB_PREC_FP64 ? sizeof(double) : sizeof(float);
     // room for the largest candidate plan of the autotuner
-    const ProjPlan big = plan_projection(g.N, B, n, 4096);
+    ProjPlan big = plan_projection(g.N, B, n, 4096);
+    big.padded = !big.wsplit;
+    plan_wave_chunks(big, B, 4096, opt.precond_prec);
     projpart = get_ws(WS_PROJ, accb * (size_t)std::max(plan.chunks, big.chunks) * B * plan.nj);
     L = get_ws(WS_L, sizeof(double) * (size_t)B * n * n);
     // the prolongations read e in groups of up to 256 queries: padded rows

@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
 // and three planes of new red values (rows j0-1 .. j0+zr), one slot per column pair
 // (2u, 2u+1) of a row, which holds the pair's node of the stored colour.  A row's nodes of
 // one colour are consecutive storage positions, so every load of a plane is contiguous.
-// z's values are loaded a step ahead; the right-hand sides at the start of their step.
+// Loads run one step ahead (z's next-but-one plane, the right-hand sides of the next step).
 // Partial sums of y^T rhs (and y^T rhs2) go to part[b * tiles + tile].
 constexpr int kFusedSlots = 3;  // slots (row, pair) per thread: (zr + 4) * pairs <= 1536
 
@@ -1268,29 +1268,33 @@ __global__ __launch_bounds__(kZThreads) void k_gs_fused(StencilGeom g, ZTile zt,
     }
   };
 
-  // z planes kfirst - 1 and kfirst into LDS, plane kfirst + 1 in flight
+  // z planes kfirst - 1 and kfirst into LDS; plane kfirst + 1 and the right-hand sides of
+  // the first step in flight
   ZV Za, Zb;
-  RV Rk, Bk;
+  RV Ra, Rb, Ba, Bb;
   load_z(Za, kfirst - 1);
   store_z(Za, kfirst - 1);
   load_z(Za, kfirst);
   store_z(Za, kfirst);
   load_z(Za, kfirst + 1);
-  auto step = [&](int k, ZV& Zn, ZV& Zn2) __attribute__((always_inline)) {
-    // Zn = z plane k + 1 (loaded a step ahead); this step's right-hand sides are issued
-    // first and arrive while the block waits at the barriers and updates the red plane
-    load_r(Rk, k, 0);
-    load_r(Bk, k - 1, 1);
+  load_r(Ra, kfirst, 0);
+  load_r(Ba, kfirst - 1, 1);
+  auto step = [&](int k, ZV& Zn, ZV& Zn2, RV& Rn, RV& Rn2, RV& Bn,
+                  RV& Bn2) __attribute__((always_inline)) {
+    // Zn = z plane k + 1, Rn = red right-hand sides of plane k, Bn = black ones of plane
+    // k - 1, all loaded a step ahead; the next step's are issued before the barriers
     store_z(Zn, k + 1);
     load_z(Zn2, k + 2);
+    load_r(Rn2, k + 1, 0);
+    load_r(Bn2, k, 1);
     __syncthreads();  // z plane k + 1 (and zinfo) visible; the black updates of k - 2 done
-    if (k <= nzm) update(k, 0, lz, zpl, 1, Rk);
+    if (k <= nzm) update(k, 0, lz, zpl, 1, Rn);
     __syncthreads();  // red plane k visible
-    if (k - 1 >= k0) update(k - 1, 1, lr, rpl, 0, Bk);
+    if (k - 1 >= k0) update(k - 1, 1, lr, rpl, 0, Bn);
   };
   for (int k = kfirst; k <= k1; k += 2) {
-    step(k, Za, Zb);
-    if (k + 1 <= k1) step(k + 1, Zb, Za);
+    step(k, Za, Zb, Ra, Rb, Ba, Bb);
+    if (k + 1 <= k1) step(k + 1, Zb, Za, Rb, Ra, Bb, Ba);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   auto store = [&](const double (&acc)[QPB], double* part) {

@@ -2,13 +2,15 @@
 
     python -m paper_1804_06363_amd.profsum stats DIR            # *kernel_stats.csv
     python -m paper_1804_06363_amd.profsum counters DIR NAME    # *counter_collection.csv
-    python -m paper_1804_06363_amd.profsum gaps DIR NAME COUNT  # *kernel_trace.csv
+    python -m paper_1804_06363_amd.profsum gaps DIR NAME COUNT [LAST]  # *kernel_trace.csv
 
 `counters` aggregates one counter per kernel name: dispatches, mean and total value.
 `gaps` splits a kernel trace by stream, from the earliest of the last COUNT dispatches of
 kernels whose name contains NAME on: per stream the span from its first kernel start to
-its last kernel end, the time covered by its kernels, and the share of the span when
-none of its kernels ran (launch gaps and host waits), with its most frequent kernel.
+its last kernel end (or to the end of its last kernel whose name contains LAST), the time
+covered by its kernels, the share of the span when none of its kernels ran (launch gaps
+and host waits) and the median gap between consecutive kernels, with its most frequent
+kernel.
 """
 from __future__ import annotations
 
@@ -61,7 +63,7 @@ def counters(d, name):
         print(f"{n:10d} {tot / n:16.1f} {tot:16.1f}  {_short(k)}")
 
 
-def gaps(d, name, count):
+def gaps(d, name, count, last=None):
     rows = []
     for path in _find(d, "*kernel_trace.csv"):
         with open(path, newline="") as f:
@@ -78,9 +80,14 @@ def gaps(d, name, count):
             streams[r[key]].append((a, b, r["Kernel_Name"]))
     print(f"window from the last {count} dispatches of {name}; per {key}")
     print(f"{'stream':>8} {'kernels':>8} {'span ms':>10} {'busy ms':>10} {'gap share':>10}"
-          f"  most frequent kernel (mean us)")
+          f" {'median gap us':>14}  most frequent kernel (mean us)")
     for sid, ks in sorted(streams.items(), key=lambda kv: -len(kv[1])):
         ks.sort()
+        if last:
+            ends = [i for i, (_, _, n) in enumerate(ks) if last in n]
+            if ends:
+                ks = ks[:ends[-1] + 1]
+        gl = sorted(max(0, ks[i + 1][0] - ks[i][1]) for i in range(len(ks) - 1)) or [0]
         busy, cur_a, cur_b = 0, None, None
         for a, b, _ in ks:  # union of the kernel intervals
             if cur_b is None or a > cur_b:
@@ -96,7 +103,8 @@ def gaps(d, name, count):
             freq[n].append(b - a)
         top, durs = max(freq.items(), key=lambda kv: len(kv[1]))
         print(f"{sid:>8} {len(ks):8d} {span / 1e6:10.2f} {busy / 1e6:10.2f} "
-              f"{1 - busy / max(span, 1):10.3f}  {_short(top, 60)} ({sum(durs) / len(durs) / 1e3:.1f})")
+              f"{1 - busy / max(span, 1):10.3f} {gl[len(gl) // 2] / 1e3:14.1f}  "
+              f"{_short(top, 60)} ({sum(durs) / len(durs) / 1e3:.1f})")
 
 
 if __name__ == "__main__":
@@ -105,6 +113,6 @@ if __name__ == "__main__":
     elif len(sys.argv) >= 4 and sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 5 and sys.argv[1] == "gaps":
-        gaps(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        gaps(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5] if len(sys.argv) > 5 else None)
     else:
         raise SystemExit(__doc__)

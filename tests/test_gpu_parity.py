@@ -206,8 +206,11 @@ def test_rbcg_converged(lib, ctx, dims, blocks, n, graph):
         assert st.status[b] == lib.RB_OK
         assert st.rel_res_true[b] <= 1e-10
         assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
-        if st.iters[b] == ref.iters:
-            assert _rel(x[b], ref.x) <= 1e-9
+        # the FP64 solution gate: 1e-10 against the oracle's solution, or against its
+        # iterate after the GPU's iteration count when the two stopped one apart
+        xo = ref.x if st.iters[b] == ref.iters else orb.solve_rbcg(
+            op, theta[b], W, AN, fixed_iters=int(st.iters[b])).x
+        assert _rel(x[b], xo) <= 1e-10, (b, _rel(x[b], xo))
 
 
 # 3D grids for the z-marching passes.  Tiles span whole grid rows while nx <= 256 (no
@@ -258,6 +261,9 @@ def test_zmarch_converged(lib, ctx, prec):
         assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
         if prec == "fp64":
             assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
+            xo = ref.x if st.iters[b] == ref.iters else orb.solve_rbcg(
+                op, theta[b], W, AN, flexible=True, fixed_iters=int(st.iters[b])).x
+            assert _rel(x[b], xo) <= 1e-10, (b, _rel(x[b], xo))
         kappa = (theta[b].max() * 12.0 / h**2) / (
             theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
         assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
@@ -427,6 +433,9 @@ def test_fused_sweep_converged(lib, ctx, prec):
         assert st.status[b] == lib.RB_OK and st.rel_res_true[b] <= 1e-10
         if prec == "fp64":
             assert abs(st.iters[b] - ref.iters) <= 1, (st.iters[b], ref.iters)
+            xo = ref.x if st.iters[b] == ref.iters else orb.solve_rbcg(
+                op, theta[b], W, AN, flexible=True, fixed_iters=int(st.iters[b])).x
+            assert _rel(x[b], xo) <= 1e-10, (b, _rel(x[b], xo))
         kappa = (theta[b].max() * 12.0 / h**2) / (
             theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
         assert _rel(x[b], ref.x) <= 2 * kappa * 1e-10
