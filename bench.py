@@ -98,7 +98,7 @@ def main():
                     help="red-black Gauss-Seidel sweeps per preconditioner application (the "
                          "smoother study on this workload: 1 -> 133.6, 2 -> 157.3, 3 -> 174.5, "
                          "4 -> 178.2, 6 -> 177.3 mu-solves/s)")
-    ap.add_argument("--uneven-sweeps", type=int, default=1,
+    ap.add_argument("--uneven-sweeps", type=int, default=4,
                     help="Gauss-Seidel sweeps per preconditioner application in the uneven batch")
     ap.add_argument("--graph", type=int, default=0,
                     help="time the main steps with the iterations replayed from a captured HIP "
@@ -355,7 +355,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def uneven_leg(rb, torch, sweeps=1):
+def uneven_leg(rb, torch, sweeps=4):
     """1024 queries mixing 2D 63^2, 255^2, 1023^2 (4x4 kappa blocks) and 3D 63^3 (2x2x2),
     mu log-uniform in [0.01, 100], per-query basis sizes n in {10, 20, 40, 60} (leading
     columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call.

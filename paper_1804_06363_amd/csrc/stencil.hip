@@ -160,6 +160,33 @@ __device__ __forceinline__ T apply_at(const Node<DIM>& n, const T* __restrict__ 
   return d * vp - off;
 }
 
+// y = num / d in the smoother's precision.  FP32: the hardware reciprocal refined by one
+// Newton step on the quotient (q = num r, q += r (num - d q)), within an ulp of the
+// rounded quotient in a third of the instructions of the IEEE sequence (d > 0 is a sum of
+// face coefficients); FP64: IEEE division.  Every stencil sweep kernel uses it, so they
+// agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T gs_div(T num, T d) {
+  if constexpr (sizeof(T) == 4) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = num * r;
+    return __builtin_fmaf(__builtin_fmaf(-d, q, num), r, q);
+  } else {
+    return num / d;
+  }
+}
+
+// the element `byte_off` bytes past a block-uniform base: a scalar base plus a 32-bit
+// vector offset per load (rows are far below 4 GiB)
+template <typename T>
+__device__ __forceinline__ const T& at_byte(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ T& at_byte(T* base, uint32_t byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 // ---- batched pass kernels -------------------------------------------------------------
 // Every pass below runs on a 1D grid of (query group) x (node chunk) blocks.  A block
 // owns QPB consecutive queries and kPT*256 consecutive storage positions: each thread
@@ -370,18 +397,25 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(StencilGeom g, int64_t ld, 
     if (pos >= 0) {
       Node<DIM> n;
       node_at<DIM>(g, pos, n);
+      const uint32_t up = (uint32_t)pos;
 #pragma unroll
       for (int k = 0; k < QPB; ++k) {
         if (!((mask >> k) & 1u)) continue;
         const double* cf = dyn + k * g.ct_size;
+        // block-uniform row bases, 32-bit byte offsets
         const TY* yb = y + (size_t)(q0 + k) * y_ld;
         const double* po = p_old + (size_t)(q0 + k) * ld;
         const double b_ = be[k];
-        const double pp = (double)yb[pos] + b_ * po[pos];
+        const double pp = (double)at_byte(yb, up * (uint32_t)sizeof(TY)) + b_ * at_byte(po, up * 8u);
         double d;
         const double q = apply_at<DIM, double>(
-            n, cf, pp, [&](int s) { return (double)yb[s] + b_ * po[s]; }, d);
-        p_new[(size_t)(q0 + k) * ld + pos] = pp;
+            n, cf, pp,
+            [&](int s) {
+              return (double)at_byte(yb, (uint32_t)s * (uint32_t)sizeof(TY)) +
+                     b_ * at_byte(po, (uint32_t)s * 8u);
+            },
+            d);
+        at_byte(p_new + (size_t)(q0 + k) * ld, up * 8u) = pp;
         acc[k] += pp * q;
       }
     }
@@ -417,18 +451,21 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
     if (pos >= 0) {
       Node<DIM> n;
       node_at<DIM>(g, pos, n);
+      const uint32_t bp = (uint32_t)pos * 8u;
 #pragma unroll
       for (int k = 0; k < QPB; ++k) {
         if (!((mask >> k) & 1u)) continue;
         const double* cf = dyn + k * g.ct_size;
+        // block-uniform row bases, 32-bit byte offsets
         const size_t o = (size_t)(q0 + k) * ld;
         const double* pb = p + o;
-        const double pp = pb[pos];
+        const double pp = at_byte(pb, bp);
         double d;
-        const double q = apply_at<DIM, double>(n, cf, pp, [&](int s) { return pb[s]; }, d);
-        x[o + pos] += al[k] * pp;
-        const double r = r_in[o + pos] - al[k] * q;
-        r_out[o + pos] = r;
+        const double q = apply_at<DIM, double>(
+            n, cf, pp, [&](int s) { return at_byte(pb, (uint32_t)s * 8u); }, d);
+        at_byte(x + o, bp) += al[k] * pp;
+        const double r = at_byte(r_in + o, bp) - al[k] * q;
+        at_byte(r_out + o, bp) = r;
         acc[k] += r * r;
       }
     }
@@ -538,12 +575,20 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   // for nodes outside the tile or the grid, position m = 0); values of such lanes are
   // never read (compute skips them and the boundary bits mask absent neighbours).
   // Loads under a branch would each wait for their data before the next one issued.
-  size_t rowp[QPB], rowy[QPB];
+  // per-query rows as block-uniform bases, read and written at 32-bit byte offsets
+  const double* pq[QPB];
+  const TY* yq[QPB];
+  double* xq[QPB];
+  const double* rq[QPB];
+  double* oq[QPB];   // p_out (pass A) or r_out (pass B)
 #pragma unroll
   for (int q = 0; q < QPB; ++q) {
-    const int b = min(q0 + q, B - 1);
-    rowp[q] = (size_t)b * ld;
-    rowy[q] = (size_t)b * y_ld;
+    const size_t b = (size_t)min(q0 + q, B - 1);
+    pq[q] = p_in + b * ld;
+    yq[q] = MODE == 0 ? y + b * y_ld : nullptr;
+    xq[q] = MODE == 1 ? x + b * ld : nullptr;
+    rq[q] = MODE == 1 ? r_in + b * ld : nullptr;
+    oq[q] = (MODE == 0 ? p_out : r_out) + b * ld;
   }
   // Pipelining: every load is issued a full step before its use.  At the top of step k
   // the block issues plane k+3 (raw: y and p apart for pass A, combined two steps later),
@@ -564,11 +609,11 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   auto load_raw = [&](Raw& r, int k) {
 #pragma unroll
     for (int s = 0; s < kZNodes; ++s) {
-      const int pos = spos(k * P + m_[s]);
+      const uint32_t pos = (uint32_t)spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
-        r.p[s][q] = p_in[rowp[q] + pos];
-        if (MODE == 0) r.y[s][q] = y[rowy[q] + pos];
+        r.p[s][q] = at_byte(pq[q], pos * 8u);
+        if (MODE == 0) r.y[s][q] = at_byte(yq[q], pos * (uint32_t)sizeof(TY));
       }
     }
   };
@@ -580,22 +625,22 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
         v[s][q] = MODE == 0 ? (double)r.y[s][q] + sc[q] * r.p[s][q] : r.p[s][q];
   };
   auto load_halo = [&](Halo& h, int k) {
-    const int pos = spos(k * P + hm);
+    const uint32_t pos = (uint32_t)spos(k * P + hm);
 #pragma unroll
     for (int q = 0; q < QPB; ++q) {
-      h.p[q] = p_in[rowp[q] + pos];
-      if (MODE == 0) h.y[q] = y[rowy[q] + pos];
+      h.p[q] = at_byte(pq[q], pos * 8u);
+      if (MODE == 0) h.y[q] = at_byte(yq[q], pos * (uint32_t)sizeof(TY));
     }
   };
   auto load_xr = [&](XR& t, int k) {
     if (MODE != 1) return;
 #pragma unroll
     for (int s = 0; s < kZNodes; ++s) {
-      const int pos = spos(k * P + m_[s]);
+      const uint32_t pos = (uint32_t)spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
-        t.x[s][q] = x[rowp[q] + pos];
-        t.r[s][q] = r_in[rowp[q] + pos];
+        t.x[s][q] = at_byte(xq[q], pos * 8u);
+        t.r[s][q] = at_byte(rq[q], pos * 8u);
       }
     }
   };
@@ -676,14 +721,14 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
         }
         const double vp = vc[s][q];
         const double Av = d * vp - off;
-        const size_t o = (size_t)(q0 + q) * ld + pos;
+        const uint32_t o = (uint32_t)pos * 8u;  // the query is live: its row is q0 + q
         if (MODE == 0) {
-          __builtin_nontemporal_store(vp, p_out + o);
+          __builtin_nontemporal_store(vp, &at_byte(oq[q], o));
           acc[q] += vp * Av;
         } else {
-          x[o] = Xk.x[s][q] + sc[q] * vp;
+          at_byte(xq[q], o) = Xk.x[s][q] + sc[q] * vp;
           const double r = Xk.r[s][q] - sc[q] * Av;
-          r_out[o] = r;
+          at_byte(oq[q], o) = r;
           acc[q] += r * r;
         }
       }
@@ -721,7 +766,10 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
 // For every node of colour `color`: y_p = (rhs_p - sum_nb A_p,nb y_nb) / A_pp with
 // A_p,nb = -c_f (the neighbours all have the other colour).  rhs_b = rhs_scale[b] *
 // rhs[b*rhs_ld + p].  Partial sums over the updated nodes: y_p rhs_p (part0) and
-// y_p rhs2_p (part1).  Arithmetic in TY (the smoother's precision).
+// y_p rhs2_p (part1).  Arithmetic in TY (the smoother's precision).  The block's QPB
+// coefficient tables sit in LDS interleaved by query (entry e of query k at e QPB + k), so
+// one wide LDS read gives a face's coefficient for every query; each thread loads all its
+// queries' neighbour values before updating them.
 template <int DIM, int QPB, typename TY, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color, int B, int chunks,
                                                        const double* coef,
@@ -735,19 +783,35 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
                                                        double* __restrict__ part0,
                                                        double* __restrict__ part1) {
   extern __shared__ double dyn[];
-  TY* cfs = reinterpret_cast<TY*>(dyn);
+  TY* cfi = reinterpret_cast<TY*>(dyn);  // [ct_size][QPB]
   __shared__ double red[4 * QPB];
   const Tile tl = tile_of(chunks);
   const int q0 = tl.q0 * QPB;
-  const unsigned mask = load_group<QPB>(g, coef, q0, B, active, cfs);
-  if (!mask) return;
+  unsigned mask = 0;
+#pragma unroll
+  for (int k = 0; k < QPB; ++k)
+    if (q0 + k < B && (!active || active[q0 + k])) mask |= 1u << k;
+  if (!mask) return;  // uniform: the whole block leaves
+  for (int e = threadIdx.x; e < QPB * g.ct_size; e += blockDim.x) {
+    const int k = e % QPB, i = e / QPB;
+    cfi[e] = (q0 + k < B) ? (TY)coef[(size_t)(q0 + k) * g.ct_size + i] : TY(0);
+  }
+  __syncthreads();
   const int lo = color ? g.NR : 0;
   const int hi = color ? g.N : g.NR;
   double a0[QPB], a1[QPB], fsc[QPB];
+  // per-query rows: block-uniform bases (clamped to an existing query)
+  TY* yq[QPB];
+  const double* rq[QPB];
+  const double* r2q[QPB];
 #pragma unroll
   for (int k = 0; k < QPB; ++k) {
     a0[k] = a1[k] = 0.0;
     fsc[k] = (rhs_scale && ((mask >> k) & 1u)) ? rhs_scale[q0 + k] : 1.0;
+    const size_t b = (size_t)min(q0 + k, B - 1);
+    yq[k] = y + b * y_ld;
+    rq[k] = rhs + b * rhs_ld;
+    r2q[k] = rhs2 ? rhs2 + b * rhs2_ld : rhs;
   }
   const int base = lo + tl.chunk * kThreads * kPT;
 #pragma unroll
@@ -756,33 +820,56 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
     if (pos < hi) {
       Node<DIM> n;
       node_at<DIM>(g, pos, n);
+      const uint32_t by = (uint32_t)pos * (uint32_t)sizeof(TY), br = (uint32_t)pos * 8u;
+      uint32_t bn[2 * DIM];
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) bn[f] = (uint32_t)n.nb[f] * (uint32_t)sizeof(TY);
+      // every query's loads first (a retired query's values are not loaded and its
+      // update is discarded)
+      TY nv[QPB][2 * DIM];
+      double fr[QPB];
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) {
+        if ((mask >> k) & 1u) {
+#pragma unroll
+          for (int f = 0; f < 2 * DIM; ++f) nv[k][f] = at_byte(yq[k], bn[f]);
+          // NT (a right-hand side per query): rhs is read once and y not again in this
+          // sweep, so both bypass L2, leaving it to the neighbour values; a right-hand
+          // side shared by the queries stays cached
+          fr[k] = NT ? __builtin_nontemporal_load(&at_byte(rq[k], br)) : at_byte(rq[k], br);
+        } else {
+#pragma unroll
+          for (int f = 0; f < 2 * DIM; ++f) nv[k][f] = TY(0);
+          fr[k] = 0.0;
+        }
+      }
+      TY d[QPB], off[QPB];
+#pragma unroll
+      for (int k = 0; k < QPB; ++k) d[k] = off[k] = TY(0);
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) {
+        const TY* cp = cfi + n.ci[f] * QPB;
+        const bool in = (n.inner >> f) & 1u;
+#pragma unroll
+        for (int k = 0; k < QPB; ++k) {
+          const TY c = cp[k];
+          d[k] += c;
+          off[k] += c * (in ? nv[k][f] : TY(0));
+        }
+      }
 #pragma unroll
       for (int k = 0; k < QPB; ++k) {
         if (!((mask >> k) & 1u)) continue;
-        const TY* cf = cfs + k * g.ct_size;
-        TY* yb = y + (size_t)(q0 + k) * y_ld;
-        TY nv[2 * DIM];
-#pragma unroll
-        for (int f = 0; f < 2 * DIM; ++f) nv[f] = yb[n.nb[f]];
-        TY d = TY(0), off = TY(0);
-#pragma unroll
-        for (int f = 0; f < 2 * DIM; ++f) {
-          const TY c = cf[n.ci[f]];
-          d += c;
-          off += c * (((n.inner >> f) & 1u) ? nv[f] : TY(0));
-        }
-        // NT (a right-hand side per query): rhs is read once and y not again in this sweep,
-        // so both bypass L2, leaving it to the neighbour values (127^3, B = 256: 1.03 ->
-        // 1.00 ms per sweep); a right-hand side shared by the queries stays cached
-        const double* rp = rhs + (size_t)(q0 + k) * rhs_ld + pos;
-        const double fp = fsc[k] * (NT ? __builtin_nontemporal_load(rp) : *rp);
-        const TY v = (TY)(((TY)fp + off) / d);
+        const double fp = fsc[k] * fr[k];
+        const TY v = gs_div<TY>((TY)fp + off[k], d[k]);
         if (NT)
-          __builtin_nontemporal_store(v, yb + pos);
+          __builtin_nontemporal_store(v, &at_byte(yq[k], by));
         else
-          yb[pos] = v;
-        a0[k] += (double)v * fp;
-        if (rhs2) a1[k] += (double)v * rhs2[(size_t)(q0 + k) * rhs2_ld + pos];
+          at_byte(yq[k], by) = v;
+        if (part0) {  // sweeps that leave the class final only (a uniform branch)
+          a0[k] += (double)v * fp;
+          if (rhs2) a1[k] += (double)v * at_byte(r2q[k], br);
+        }
       }
     }
   }
@@ -1015,7 +1102,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
           off += c * (((inner >> f) & 1u) ? nv[f] : TY(0));
         }
         const double fp = fsc[q] * Xk.r[a][q];
-        const TY v = (TY)(((TY)fp + off) / d);
+        const TY v = gs_div<TY>((TY)fp + off, d);
         y[(size_t)(q0 + q) * y_ld + pos] = v;
         a0[q] += (double)v * fp;
         if (FLEX) a1[q] += (double)v * Xk.r2[a][q];
@@ -1257,7 +1344,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_fused(StencilGeom g, ZTile zt,
           off += cc * (((inner >> f) & 1u) ? nv[f] : TY(0));
         }
         const double fp = t.r[m][q];
-        const TY v = (TY)(((TY)fp + off) / d);
+        const TY v = gs_div<TY>((TY)fp + off, d);
         if (!c) lr[qo + (k % 3) * rpl + wr[m] * PR + u] = v;
         if (out) {
           y[rowy[q] + pos] = v;

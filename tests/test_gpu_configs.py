@@ -199,10 +199,10 @@ def test_large_configuration_paths_on_a_thin_grid(lib, ctx):
 def test_uneven_configuration(lib, ctx):
     """The uneven batch's four grids (63^2, 255^2, 1023^2 with 4x4 kappa blocks, 63^3 with
     2x2x2; mu log-uniform in [0.01, 100]) and basis sizes 10, 20, 40, 60 mixed in one call
-    with the benchmark's options (FP32 preconditioner, flexible beta, HIP graphs,
-    floor_factor 16, 1e-9 on 1023^2), 256 of its 1024 queries: every query meets its
-    tolerance or is accepted at the rounding level within 2x the residual of its exact
-    solution rounded to doubles, and sampled queries on the 63^2 and
+    with the benchmark's options (FP32 preconditioner with four Gauss-Seidel sweeps,
+    flexible beta, HIP graphs, floor_factor 16, 1e-9 on 1023^2), 256 of its 1024 queries:
+    every query meets its tolerance or is accepted at the rounding level within 2x the
+    residual of its exact solution rounded to doubles, and sampled queries on the 63^2 and
     63^3 grids match the oracle's RBCG with the same leading basis vectors (solutions
     within 2 kappa rtol of each other)."""
     import torch
@@ -218,7 +218,8 @@ def test_uneven_configuration(lib, ctx):
     qs = uneven_batch(count=256)
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda") for g, _, _ in qs]
     queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
-    opts = lib.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0)
+    opts = lib.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0,
+                          sweeps=4)
     st = lib.solve_multi(ctx, probs, bases, queries, opts=opts)
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
     assert (st.status == lib.RB_OK).all()
@@ -246,6 +247,6 @@ def test_uneven_configuration(lib, ctx):
         Wn, AN, fN = bases[g].info()
         W = np.ascontiguousarray(Wn[:nu].T)
         ref = orb.solve_rbcg(op, qs[k][2], W, AN[:, :nu, :nu], flexible=True, rtol=wk.rtol,
-                             maxit=10000)
+                             maxit=10000, sweeps=4)
         assert ref.converged
         assert _rel(xs[k].cpu().numpy(), ref.x) <= 2 * _kappa_bound(wk.dims, qs[k][2]) * wk.rtol
