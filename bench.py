@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--greedy", default="residual", choices=["l1", "residual"])
+    ap.add_argument("--snapshot-sweeps", type=int, default=1,
+                    help="Gauss-Seidel sweeps per preconditioner application in the greedy's "
+                         "snapshot solves")
     ap.add_argument("--uneven", type=int, default=0,
                     help="also time the uneven batch (1024 queries over four grids)")
     ap.add_argument("--uneven-only", type=int, default=0,
@@ -171,8 +174,10 @@ def main():
         log(f"basis n={basis.n} loaded from {args.basis}")
     else:
         basis, rep = rb.offline_build(ctx, prob, train, mu=train, n_max=w.n,
-                                      indicator=args.greedy)
-        log(f"offline greedy: n={basis.n} in {time.time() - t0:.1f}s, snapshot iters "
+                                      indicator=args.greedy,
+                                      snapshot_sweeps=args.snapshot_sweeps)
+        log(f"offline greedy ({args.snapshot_sweeps} sweeps per snapshot preconditioner): "
+            f"n={basis.n} in {time.time() - t0:.1f}s, snapshot iters "
             f"{rep['snapshot_iters'][:5]}..{rep['snapshot_iters'][-3:]}")
         if args.basis:
             basis.save(args.basis)

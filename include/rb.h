@@ -293,6 +293,8 @@ typedef struct {
   rb_prec surrogate_prec; /* the network's products: RB_PREC_BF16 (default; BF16 operands,
                            * FP32 accumulation) or RB_PREC_FP32; master weights and Adam
                            * moments are FP32 either way */
+  int snapshot_sweeps;   /* Gauss-Seidel sweeps per preconditioner application in the
+                          * snapshot solves (default 1) */
 } rb_greedy_opts;
 void rb_greedy_opts_default(rb_greedy_opts* opts);
 

@@ -97,7 +97,7 @@ def _append(op, W, AN_q, fN, w):
 
 def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
                     snapshot_rtol=1e-10, snapshot_maxit=5000, keep_indicators=False,
-                    snapshot_flexible=True, phis=None):
+                    snapshot_flexible=True, phis=None, snapshot_sweeps=1):
     """phis (M x R, optional): Phi_r of every training parameter (eq. 12)."""
     N = op.N
     W = np.zeros((N, 0))
@@ -113,7 +113,7 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
     while W.shape[1] < n_max:
         res = solve_rbcg(op, thetas[mu_next], W, AN_q if W.shape[1] else None,
                          rtol=snapshot_rtol, maxit=snapshot_maxit,
-                         flexible=snapshot_flexible,
+                         flexible=snapshot_flexible, sweeps=snapshot_sweeps,
                          phi=None if phis is None else phis[mu_next])   # snapshot
         try:
             w = mgs(W, res.x)                                            # orthonormalise
@@ -140,7 +140,7 @@ def adaptive_greedy(op, thetas, n_max, indicator="residual", seed_index=0,
 
 
 def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
-                          snapshot_flexible=True, phis=None):
+                          snapshot_flexible=True, phis=None, snapshot_sweeps=1):
     """The snapshot solve and basis update of Alg. 4 for a given sequence of parameters: each snapshot is solved
     by RBCG with the basis built so far and orthonormalised into it (degenerate
     snapshots are skipped).  With the parameters picked by a greedy on a coarse grid
@@ -153,6 +153,7 @@ def basis_from_parameters(op, thetas, snapshot_rtol=1e-10, snapshot_maxit=5000,
     for i, th in enumerate(thetas):
         res = solve_rbcg(op, th, W, AN_q if W.shape[1] else None, rtol=snapshot_rtol,
                          maxit=snapshot_maxit, flexible=snapshot_flexible,
+                         sweeps=snapshot_sweeps,
                          phi=None if phis is None else phis[i])           # snapshot
         try:
             w = mgs(W, res.x)                                               # orthonormalise

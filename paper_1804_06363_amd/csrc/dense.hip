@@ -1125,26 +1125,32 @@ void launch_fin_sum(const double* part, int stride, int cnt, double* out, const 
 
 // ---- small helpers ---------------------------------------------------------------------
 // Correction folding of the CG iterate: x_b += xc_b, xc_b = 0 for the flagged queries.
-// Rows are ld (a multiple of 64) doubles; padding is zero in both vectors.
-__global__ void k_fold(const int* __restrict__ flag, double2* __restrict__ x,
-                       double2* __restrict__ xc, int64_t ld2) {
-  const int b = blockIdx.y;
-  if (flag && !flag[b]) return;
-  double2* xb = x + (size_t)b * ld2;
-  double2* cb = xc + (size_t)b * ld2;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld2;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 a = xb[i], c = cb[i];
-    xb[i] = make_double2(a.x + c.x, a.y + c.y);
-    cb[i] = make_double2(0.0, 0.0);
+// Rows are ld (a multiple of 64) doubles; padding is zero in both vectors.  Every block
+// takes a slice of every flagged row (few rows are flagged at a time: each query reaches
+// its true-residual check once or twice), so a flagged row is folded by the whole grid.
+__global__ __launch_bounds__(256) void k_fold(const int* __restrict__ flag, int B,
+                                              double2* __restrict__ x, double2* __restrict__ xc,
+                                              int64_t ld2, int64_t slice) {
+  const int64_t i0 = (int64_t)blockIdx.x * slice;
+  const int64_t i1 = i0 + slice < ld2 ? i0 + slice : ld2;
+  for (int b = 0; b < B; ++b) {
+    if (flag && !flag[b]) continue;  // uniform across the block
+    double2* xb = x + (size_t)b * ld2;
+    double2* cb = xc + (size_t)b * ld2;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const double2 a = xb[i], c = cb[i];
+      xb[i] = make_double2(a.x + c.x, a.y + c.y);
+      cb[i] = make_double2(0.0, 0.0);
+    }
   }
 }
 void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s) {
   if (B <= 0) return;
-  // a few blocks per query: most launches find no flag, and a flagged query is rare
-  const int bx = std::max(1, std::min(64, 2048 / B));
-  hipLaunchKernelGGL(k_fold, dim3(bx, B), dim3(256), 0, s, flag, (double2*)x, (double2*)xc,
-                     ld / 2);
+  const int64_t ld2 = ld / 2;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (ld2 + 255) / 256));
+  const int64_t slice = (ld2 + blocks - 1) / blocks;
+  hipLaunchKernelGGL(k_fold, dim3(blocks), dim3(256), 0, s, flag, B, (double2*)x, (double2*)xc,
+                     ld2, slice);
 }
 
 // dst[b][pos] = value for pos < n (fill kernel; graph-safe replacement for memset)

@@ -113,6 +113,7 @@ int GreedyState::snapshot(int mu) {
   so.maxit = opt.snapshot_maxit;
   so.beta_flexible = opt.snapshot_flexible;
   so.precond_prec = opt.snapshot_prec;
+  so.smooth_sweeps = opt.snapshot_sweeps;
   const double* th = theta_h.data() + (size_t)mu * prob->g.Q;
   const double* ph = phi_h.empty() ? nullptr : phi_h.data() + (size_t)mu * prob->R;
   BatchSolver s(ctx, prob, bs.get(), so, 1, th, ph, nullptr);
@@ -285,6 +286,7 @@ extern "C" void rb_greedy_opts_default(rb_greedy_opts* o) {
   o->seed = 1234;
   o->snapshot_prec = RB_PREC_FP64;
   o->surrogate_prec = RB_PREC_BF16;
+  o->snapshot_sweeps = 1;
 }
 
 extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
@@ -297,6 +299,8 @@ extern "C" rb_status rb_offline_build(rb_ctx* ctx, const rb_problem* prob,
                "rb_greedy_opts.struct_size mismatch");
     RB_REQUIRE(opts->snapshot_prec == RB_PREC_FP64 || opts->snapshot_prec == RB_PREC_FP32,
                RB_EINVAL, "snapshot_prec must be FP64 or FP32");
+    RB_REQUIRE(opts->snapshot_sweeps >= 1 && opts->snapshot_sweeps <= 64, RB_EINVAL,
+               "snapshot_sweeps must be in 1..64");
     RB_REQUIRE(M >= 1 && M < (1 << 30), RB_EINVAL, "bad training-set size");
     RB_REQUIRE(opts->n_max >= 1 && opts->n_max <= 80, RB_EINVAL, "n_max must be 1..80");
     RB_REQUIRE(opts->seed_index >= 0 && opts->seed_index < M, RB_EINVAL, "bad seed_index");
@@ -385,6 +389,8 @@ extern "C" rb_status rb_basis_from_parameters(rb_ctx* ctx, const rb_problem* pro
                "rb_greedy_opts.struct_size mismatch");
     RB_REQUIRE(opts->snapshot_prec == RB_PREC_FP64 || opts->snapshot_prec == RB_PREC_FP32,
                RB_EINVAL, "snapshot_prec must be FP64 or FP32");
+    RB_REQUIRE(opts->snapshot_sweeps >= 1 && opts->snapshot_sweeps <= 64, RB_EINVAL,
+               "snapshot_sweeps must be in 1..64");
     RB_REQUIRE(K >= 1 && K <= 80, RB_EINVAL, "K must be 1..80");
     for (int64_t i = 0; i < (int64_t)K * prob->g.Q; ++i)
       RB_REQUIRE(std::isfinite(theta[i]), RB_EINVAL, "theta contains NaN or Inf");

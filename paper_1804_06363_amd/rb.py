@@ -72,7 +72,7 @@ class GreedyOpts(C.Structure):
                 ("full_sweep_every", C.c_int), ("warmup_full_sweeps", C.c_int),
                 ("train_steps", C.c_int), ("lr", C.c_double), ("mu_lo", C.c_double),
                 ("mu_hi", C.c_double), ("seed", C.c_uint64), ("snapshot_prec", C.c_int),
-                ("surrogate_prec", C.c_int)]
+                ("surrogate_prec", C.c_int), ("snapshot_sweeps", C.c_int)]
 
 
 class SurrogateIO(C.Structure):

@@ -37,6 +37,27 @@ def test_greedy_matches_oracle(lib, ctx, indicator, dims, blocks):
 
 
 @pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3))])
+def test_greedy_snapshot_sweeps(lib, ctx, dims, blocks):
+    """Snapshot solves with four Gauss-Seidel sweeps per preconditioner application, on
+    the GPU and in the oracle: the same picks and the basis within 1e-7 (the snapshots
+    are solved to 1e-12 either way; fewer iterations than with one sweep)."""
+    op = BlockDiffusion(dims, blocks)
+    mus = log_uniform_mu(80, 24, op.Q, 0.1, 10.0)
+    n_max = 5
+    ref = og.adaptive_greedy(op, mus, n_max, indicator="residual", snapshot_rtol=1e-12,
+                             snapshot_sweeps=4)
+    ref1 = og.adaptive_greedy(op, mus, n_max, indicator="residual", snapshot_rtol=1e-12)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis, rep = lib.offline_build(ctx, prob, mus, mu=mus, n_max=n_max, indicator="residual",
+                                   snapshot_rtol=1e-12, snapshot_sweeps=4)
+    assert rep["picks"] == ref.picks
+    W, AN, fN = basis.info()
+    for j in range(n_max):
+        assert np.linalg.norm(W[j] - ref.W[:, j]) <= 1e-7
+    assert sum(rep["snapshot_iters"]) < sum(ref1.snapshot_iters)
+
+
+@pytest.mark.parametrize("dims,blocks", [((15, 15), (2, 2)), ((7, 9, 5), (2, 2, 3))])
 def test_greedy_fp32_snapshots(lib, ctx, dims, blocks):
     """Snapshot solves preconditioned in FP32 (the basis's FP32 copy grows a column per
     step; CG, stopping test and Gram-Schmidt in FP64): the oracle's picks, the basis
