@@ -98,6 +98,9 @@ def main():
                     help="red-black Gauss-Seidel sweeps per preconditioner application (the "
                          "smoother study on this workload: 1 -> 133.6, 2 -> 157.3, 3 -> 174.5, "
                          "4 -> 178.2, 6 -> 177.3 mu-solves/s)")
+    ap.add_argument("--residual-copy", type=int, default=1,
+                    help="keep an FP32 copy of r for the projection and the sweeps without dot "
+                         "products (FP32 / BF16 preconditioner; same results, fewer bytes)")
     ap.add_argument("--uneven-sweeps", type=int, default=4,
                     help="Gauss-Seidel sweeps per preconditioner application in the uneven batch")
     ap.add_argument("--graph", type=int, default=0,
@@ -184,11 +187,12 @@ def main():
     test = w.test_mu(B)
     x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
     opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
-                         sweeps=args.sweeps)
+                         sweeps=args.sweeps, residual_copy=bool(args.residual_copy))
 
     # warm-up solves autotune the batched kernels' tiles (kept in the context)
     wopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
-                          autotune=True, sweeps=args.sweeps)
+                          autotune=True, sweeps=args.sweeps,
+                          residual_copy=bool(args.residual_copy))
     for i in range(args.warmup):
         _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=wopts)
         log(f"warmup {i}: iters mean {st.iters.mean():.1f} max {st.iters.max()} "
@@ -220,9 +224,11 @@ def main():
         log(f"  {k:14s} {ms:9.2f} ms  {n:6d} launches  {ms / max(n, 1) * 1e3:9.1f} us/launch")
 
     # roofline of the dominant kernel: pass B reads x, p, r and writes x, r (FP64) for
-    # every active query: 40 algorithmic bytes per DOF per active query-iteration
+    # every active query, and the FP32 copy of r with an FP32 / BF16 preconditioner: 40
+    # (44) algorithmic bytes per DOF per active query-iteration
+    copy = bool(args.residual_copy) and args.prec != "fp64"
     ms_b, n_b = prof.get("pass_b", (0.0, 0))
-    bytes_b = 40.0 * N * iters_total
+    bytes_b = (44.0 if copy else 40.0) * N * iters_total
     kernel_b = pass_b_kernel(tune_cache, len(w.dims), N, B, basis.n, args.prec)
     if args.graph:  # graph replays record no per-kernel events
         roofline = {"kernel": kernel_b, "bound": "hbm", "achieved": None,
@@ -242,8 +248,10 @@ def main():
     # start and the final true residual, over the wall time of a step
     s_y = 8 if args.prec == "fp64" else 4
     s_w = {"fp64": 8, "fp32": 4, "bf16": 2}[args.prec]
-    # each sweep beyond the first reads r and y and writes y: N (8 + 2 s_y) more
-    per_it = 64 + 2 * s_y + 1.5 * s_w * basis.n / B + (args.sweeps - 1) * (8 + 2 * s_y)
+    # each sweep beyond the first reads r (its FP32 copy if kept) and y and writes y:
+    # N (s_r + 2 s_y) more
+    s_r = 4 if copy else 8
+    per_it = 64 + 2 * s_y + 1.5 * s_w * basis.n / B + (args.sweeps - 1) * (s_r + 2 * s_y)
     path_bytes = sum(float(N) * per_it * float(ss.iters.sum()) + 24.0 * N * B for ss in stats)
     path_gbs = path_bytes / elapsed / 1e9
     roofline["path_model_bytes_per_step"] = round(path_bytes / args.steps)
@@ -256,7 +264,7 @@ def main():
     graph_leg = None
     if args.graph_leg and not args.graph:
         gopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=True,
-                              sweeps=args.sweeps)
+                              sweeps=args.sweeps, residual_copy=bool(args.residual_copy))
         rb.solve_batch(ctx, prob, basis, test, x=x, opts=gopts)  # capture
         torch.cuda.synchronize()
         tg = time.perf_counter()
@@ -345,6 +353,7 @@ def main():
                    "N": N, "B": B, "n": basis.n, "Q": Q, "prec": args.prec,
                    "beta": "flexible" if args.flexible else "literal",
                    "smoother": f"red-black Gauss-Seidel x{args.sweeps}",
+                   "residual_copy": copy,
                    "graph": bool(args.graph), "parallelism": "single-gpu"},
         "step_ms": [round(v * 1e3, 2) for v in step_s],
         "median_step_ms": round(float(np.median(step_s)) * 1e3, 2),

@@ -184,6 +184,12 @@ typedef struct {
   int smooth_sweeps;  /* Gauss-Seidel sweeps per smoother application (RBGS: forward sweeps,
                          RBGS_SYM: forward + backward pairs); 0 or 1 = one.  Jacobi and
                          none take one only (RB_EUNSUPPORTED otherwise). */
+  int residual_copy;  /* RBCG with an FP32 / BF16 preconditioner on a stencil problem:
+                         1 (default) = the CG updates also keep an FP32 copy of r, which the
+                         projection W^T r and the Gauss-Seidel sweeps that form no dot
+                         product read instead of r.  Both round r to FP32 before using it,
+                         so the results are the same, from fewer bytes read; 0 = read r.
+                         Ignored elsewhere. */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 

@@ -57,30 +57,37 @@ __device__ __forceinline__ int acc_row(int g, int i) {
 // n, so the loads need no bounds checks (no branches between them).
 // One step = 16 DOFs: lane (qi, kg) holds R[q_base + 16 t + qi][k0 + 4 kg .. +3] of every
 // query tile t and W[16 u + qi][same DOFs] of every basis tile u.
-template <typename TW, int QT, int JT>
+// RT: type of the residual rows (double, or float for an FP32 copy with an FP32 / BF16
+// basis: the products round the residual to FP32 first, so the result is the same)
+template <typename TW, int QT, int JT, typename RT = double>
 struct ProjFrag {
-  double a[QT][4];
+  RT a[QT][4];
   TW w[JT][4];
 };
 
 // row[t] / ok[t]: the residual row of this lane in query tile t and whether it is loaded
 // (PADDED: always; rows are valid addresses either way).
-template <typename TW, int QT, int JT, bool PADDED>
-__device__ __forceinline__ void proj_load(const double* __restrict__ R, int64_t r_ld,
+template <typename TW, int QT, int JT, bool PADDED, typename RT>
+__device__ __forceinline__ void proj_load(const RT* __restrict__ R, int64_t r_ld,
                                           const TW* __restrict__ W, int64_t w_ld, int n,
                                           const int (&row)[QT], const bool (&ok)[QT], int k0,
-                                          ProjFrag<TW, QT, JT>& f) {
+                                          ProjFrag<TW, QT, JT, RT>& f) {
   const int lane = threadIdx.x & 63;
   const int qi = lane & 15, kg = lane >> 4;
   const int kk = k0 + 4 * kg;
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     if (PADDED || ok[t]) {
-      const double2* src = reinterpret_cast<const double2*>(R + (size_t)row[t] * r_ld + kk);
-      const double2 v0 = src[0], v1 = src[1];
-      f.a[t][0] = v0.x; f.a[t][1] = v0.y; f.a[t][2] = v1.x; f.a[t][3] = v1.y;
+      if constexpr (sizeof(RT) == 8) {
+        const double2* src = reinterpret_cast<const double2*>(R + (size_t)row[t] * r_ld + kk);
+        const double2 v0 = src[0], v1 = src[1];
+        f.a[t][0] = v0.x; f.a[t][1] = v0.y; f.a[t][2] = v1.x; f.a[t][3] = v1.y;
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(R + (size_t)row[t] * r_ld + kk);
+        f.a[t][0] = v.x; f.a[t][1] = v.y; f.a[t][2] = v.z; f.a[t][3] = v.w;
+      }
     } else {
-      f.a[t][0] = f.a[t][1] = f.a[t][2] = f.a[t][3] = 0.0;
+      f.a[t][0] = f.a[t][1] = f.a[t][2] = f.a[t][3] = RT(0);
     }
   }
 #pragma unroll
@@ -106,8 +113,8 @@ __device__ __forceinline__ void proj_load(const double* __restrict__ R, int64_t 
   }
 }
 
-template <typename TW, int QT, int JT>
-__device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT>& f,
+template <typename TW, int QT, int JT, typename RT>
+__device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT, RT>& f,
                                          typename ProjTraits<TW>::Vec (&acc)[QT][JT]) {
   if constexpr (sizeof(TW) == 8) {  // FP64
 #pragma unroll
@@ -153,8 +160,9 @@ __device__ __forceinline__ void proj_mma(const ProjFrag<TW, QT, JT>& f,
 // and partial sums still go to the query's own row.
 // WCH = true (wchunk plans): each wave covers all the group's queries (QT tiles) over a
 // DOF range of its own; its partial sums are chunk 4 * blockIdx.x + wave.
-template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED, bool WCH = false>
-__global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, int64_t r_ld,
+template <typename TW, int QT, int JT, bool WSPLIT, bool PADDED, bool WCH = false,
+          typename RT = double>
+__global__ __launch_bounds__(256) void k_project(const RT* __restrict__ R, int64_t r_ld,
                                                  const TW* __restrict__ W, int64_t w_ld, int n,
                                                  int B, int kend, int steps,
                                                  const int* __restrict__ active,
@@ -204,7 +212,7 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ R, i
   // loop runs two steps per trip; a prefetch past the range reloads the last step)
   if (k_begin < k_stop) {
     const int klast = k_stop - 16;
-    ProjFrag<TW, QT, JT> f0, f1;
+    ProjFrag<TW, QT, JT, RT> f0, f1;
     proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, row, ok, k_begin, f0);
     for (int k0 = k_begin; k0 < k_stop; k0 += 32) {
       proj_load<TW, QT, JT, PADDED>(R, r_ld, W, w_ld, n, row, ok, min(k0 + 16, klast), f1);
@@ -301,33 +309,33 @@ void plan_wave_chunks(ProjPlan& p, int B, int target_blocks, rb_prec prec) {
   p.chunks = 4 * p.blocks;
 }
 
-template <typename TW, int QT, int JT>
-static void launch_proj_t(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
+template <typename TW, int QT, int JT, typename RT>
+static void launch_proj_t(const ProjPlan& pl, const RT* R, int64_t r_ld, const TW* W,
                           int64_t w_ld, int n, int B, const int* active, const int* qlist,
                           void* part, hipStream_t s) {
   using Acc = typename ProjTraits<TW>::Acc;
   const dim3 grid(pl.blocks, pl.qgroups);
   if constexpr (QT == 4 && sizeof(TW) < 8) {
     if (pl.wchunk) {
-      hipLaunchKernelGGL((k_project<TW, QT, JT, false, true, true>), grid, dim3(256), 0, s, R,
-                         r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
+      hipLaunchKernelGGL((k_project<TW, QT, JT, false, true, true, RT>), grid, dim3(256), 0, s,
+                         R, r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
       return;
     }
   }
   RB_REQUIRE(!pl.wchunk, RB_EUNSUPPORTED, "wave-chunk projection plan for an FP64 basis");
   if (pl.wsplit)
-    hipLaunchKernelGGL((k_project<TW, QT, JT, true, false>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, nullptr, (Acc*)part);
+    hipLaunchKernelGGL((k_project<TW, QT, JT, true, false, false, RT>), grid, dim3(256), 0, s, R,
+                       r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, nullptr, (Acc*)part);
   else if (pl.padded)
-    hipLaunchKernelGGL((k_project<TW, QT, JT, false, true>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
+    hipLaunchKernelGGL((k_project<TW, QT, JT, false, true, false, RT>), grid, dim3(256), 0, s, R,
+                       r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
   else
-    hipLaunchKernelGGL((k_project<TW, QT, JT, false, false>), grid, dim3(256), 0, s, R, r_ld, W,
-                       w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
+    hipLaunchKernelGGL((k_project<TW, QT, JT, false, false, false, RT>), grid, dim3(256), 0, s, R,
+                       r_ld, W, w_ld, n, B, pl.kend, pl.steps, active, qlist, (Acc*)part);
 }
 
-template <typename TW, int QT>
-static void launch_proj_q(const ProjPlan& pl, const double* R, int64_t r_ld, const TW* W,
+template <typename TW, int QT, typename RT>
+static void launch_proj_q(const ProjPlan& pl, const RT* R, int64_t r_ld, const TW* W,
                           int64_t w_ld, int n, int B, const int* active, const int* ql,
                           void* part, hipStream_t s) {
   switch (pl.jt) {
@@ -339,31 +347,31 @@ static void launch_proj_q(const ProjPlan& pl, const double* R, int64_t r_ld, con
   }
 }
 
+template <typename TW, typename RT>
+static void launch_proj_w(const ProjPlan& pl, const RT* R, int64_t r_ld, const void* W,
+                          int64_t w_ld, int n, int B, const int* active, const int* ql,
+                          void* part, hipStream_t s) {
+  const TW* w = (const TW*)W;
+  switch (pl.qt) {
+    case 1: launch_proj_q<TW, 1>(pl, R, r_ld, w, w_ld, n, B, active, ql, part, s); break;
+    case 2: launch_proj_q<TW, 2>(pl, R, r_ld, w, w_ld, n, B, active, ql, part, s); break;
+    default: launch_proj_q<TW, 4>(pl, R, r_ld, w, w_ld, n, B, active, ql, part, s); break;
+  }
+}
+
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
                        const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
-                       hipStream_t s, const int* qlist) {
-  if (prec == RB_PREC_FP64) {
-    const double* w = (const double*)W;
-    switch (pl.qt) {
-      case 1: launch_proj_q<double, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      case 2: launch_proj_q<double, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      default: launch_proj_q<double, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-    }
-  } else if (prec == RB_PREC_FP32) {
-    const float* w = (const float*)W;
-    switch (pl.qt) {
-      case 1: launch_proj_q<float, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      case 2: launch_proj_q<float, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      default: launch_proj_q<float, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-    }
-  } else {
-    const uint16_t* w = (const uint16_t*)W;
-    switch (pl.qt) {
-      case 1: launch_proj_q<uint16_t, 1>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      case 2: launch_proj_q<uint16_t, 2>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-      default: launch_proj_q<uint16_t, 4>(pl, R, r_ld, w, w_ld, n, B, active, qlist, part, s); break;
-    }
-  }
+                       hipStream_t s, const int* qlist, const float* R32) {
+  if (prec == RB_PREC_FP64)
+    launch_proj_w<double>(pl, R, r_ld, W, w_ld, n, B, active, qlist, part, s);
+  else if (prec == RB_PREC_FP32 && R32)
+    launch_proj_w<float>(pl, R32, r_ld, W, w_ld, n, B, active, qlist, part, s);
+  else if (prec == RB_PREC_FP32)
+    launch_proj_w<float>(pl, R, r_ld, W, w_ld, n, B, active, qlist, part, s);
+  else if (R32)
+    launch_proj_w<uint16_t>(pl, R32, r_ld, W, w_ld, n, B, active, qlist, part, s);
+  else
+    launch_proj_w<uint16_t>(pl, R, r_ld, W, w_ld, n, B, active, qlist, part, s);
 }
 
 // ---- prolongation -----------------------------------------------------------------
@@ -1176,7 +1184,8 @@ template void launch_fill<int>(int*, int64_t, int64_t, int, int, hipStream_t);
 __global__ __launch_bounds__(256) void k_init_rhs(const double* __restrict__ f, int64_t f_ld,
                                                   const double* __restrict__ scale, int N,
                                                   double* __restrict__ r, int64_t ld,
-                                                  double* __restrict__ part, int per_thread) {
+                                                  double* __restrict__ part, int per_thread,
+                                                  float* __restrict__ r32) {
   __shared__ double sh[4];
   const int b = blockIdx.y;
   const double sc = scale[b];
@@ -1188,16 +1197,17 @@ __global__ __launch_bounds__(256) void k_init_rhs(const double* __restrict__ f, 
     if (pos >= N) break;
     const double v = sc * fb[pos];
     r[(size_t)b * ld + pos] = v;
+    if (r32) r32[(size_t)b * ld + pos] = (float)v;
     acc += v * v;
   }
   const double s = rbk::block_sum_256(acc, sh);
   if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
 int launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
-                    int64_t ld, int B, double* part, int per_thread, hipStream_t s) {
+                    int64_t ld, int B, double* part, int per_thread, hipStream_t s, float* r32) {
   const int chunks = (N + 256 * per_thread - 1) / (256 * per_thread);
   hipLaunchKernelGGL(k_init_rhs, dim3(chunks, B), dim3(256), 0, s, f, f_ld, scale, N, r, ld, part,
-                     per_thread);
+                     per_thread, r32);
   return chunks;
 }
 

@@ -188,7 +188,7 @@ TuneConfig stencil_tiles();
 enum WsSlot {
   WS_THETA, WS_SCALE, WS_NUSE, WS_COEF, WS_L, WS_E64, WS_E32, WS_PROJ, WS_X, WS_R0, WS_R1,
   WS_P0, WS_P1, WS_Y, WS_Z, WS_PM, WS_PM2, WS_PR0, WS_PR1, WS_Q, WS_QLIST, WS_FB, WS_PHI,
-  WS_GATHER, WS_ONES, WS_XC, WS_COUNT
+  WS_GATHER, WS_ONES, WS_XC, WS_R32, WS_COUNT
 };
 }  // namespace rb
 

@@ -65,10 +65,12 @@ inline int padded_queries(int B) { return (B + 255) / 256 * 256; }
 int stencil_chunks(int count);
 // partial-sum chunks of an all-node stencil pass (apply, pass A/B, Jacobi)
 int stencil_chunks_all(int N);
-// mode 1 with part2: partial sums of (|A| |u|)^2 as well (rounding level of the residual)
+// mode 1 with part2: partial sums of (|A| |u|)^2 as well (rounding level of the residual);
+// y32 (mode 1, stencil grids): also an FP32 copy of y, rows of ld
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, hipStream_t s, double* part2 = nullptr);
+                  const int* flag, double* part, hipStream_t s, double* part2 = nullptr,
+                  float* y32 = nullptr);
 // x_b += xc_b, xc_b = 0 for the queries with flag[b] != 0 (all of them if flag is null),
 // over the ld entries of each row
 void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s);
@@ -78,14 +80,17 @@ template <typename TY>
 int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                   const int* active, double* part, hipStream_t s);
+// r32 (nullable, stencil grids): pass B also writes an FP32 copy of r_out (rows of ld)
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
-                  const int* active, double* part, hipStream_t s);
+                  const int* active, double* part, hipStream_t s, float* r32 = nullptr);
 // returns the number of partial sums per query it wrote (row stride of part0 / part1;
-// at most stencil_chunks of the colour's node count)
-template <typename TY>
+// at most stencil_chunks of the colour's node count).  RT = float (TY = float, stencil
+// grids): rhs is an FP32 copy of the right-hand side; the same y, since the update rounds
+// rhs to FP32 first.
+template <typename TY, typename RT = double>
 int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
-                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                    int64_t y_ld, const RT* rhs, int64_t rhs_ld, const double* rhs_scale,
                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                     double* part1, hipStream_t s);
 // One forward red-black sweep y = S(A, rhs, z) in one launch marching along z, for a start
@@ -143,9 +148,11 @@ ProjPlan plan_projection(int N, int B, int n, int target_blocks);
 void plan_wave_chunks(ProjPlan& p, int B, int target_blocks, rb_prec prec);
 // qlist (nullable; the batched path only): active queries in increasing order with their
 // count in qlist[B] (launch_compact_active); rows of other queries are then not read.
+// R32 (nullable; FP32 / BF16 basis): an FP32 copy of R with the same layout, read instead
+// of R (the same partial sums: the products round R to FP32 first).
 void launch_projection(const ProjPlan& pl, rb_prec prec, const double* R, int64_t r_ld,
                        const void* W, int64_t w_ld, int n, int B, const int* active, void* part,
-                       hipStream_t s, const int* qlist = nullptr);
+                       hipStream_t s, const int* qlist = nullptr, const float* R32 = nullptr);
 // MFMA path (FP32/BF16, B >= 16): e must have round_up(B, 64) rows, zero beyond B, and
 // W basis_rows(n) rows plus kBasisTail elements, zero beyond n.
 // qlist as for launch_projection (MFMA path only)
@@ -181,9 +188,10 @@ void launch_fin_sum(const double* part, int stride, int cnt, double* out, const 
                     int B, hipStream_t s);
 template <typename T>
 void launch_fill(T* dst, int64_t ld, int64_t n, int B, T value, hipStream_t s);
-// returns the number of partial sums per query
+// returns the number of partial sums per query; r32 (nullable): also an FP32 copy of r
 int launch_init_rhs(const double* f, int64_t f_ld, const double* scale, int N, double* r,
-                    int64_t ld, int B, double* part, int per_thread, hipStream_t s);
+                    int64_t ld, int B, double* part, int per_thread, hipStream_t s,
+                    float* r32 = nullptr);
 void launch_cast(const double* src, void* dst, int64_t n, rb_prec prec, hipStream_t s);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
 void compute_reduced(rb_basis* bs, int j0);

@@ -103,6 +103,8 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   const size_t vr = sizeof(double) * (size_t)rrows * L_;
   x = get_ws(WS_X, vb);
   r0 = get_ws(WS_R0, vr);
+  use_r32 = y32 && opt.residual_copy && opt.solver == RB_SOLVER_RBCG && !g.csr;
+  if (use_r32) r32 = get_ws(WS_R32, sizeof(float) * (size_t)rrows * L_);
   if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
     r1 = get_ws(WS_R1, vr);
   if (opt.solver != RB_SOLVER_RBI) {
@@ -212,7 +214,7 @@ void BatchSolver::factor() {
 // One application y = RBI(A, r, W, 1) from x = 0, the preconditioner of Alg. 3: one
 // iteration of Alg. 2 (coarse correction and smoothing) whose residual is r itself, plus
 // the partial sums of y^T r (and y^T r_old).
-void BatchSolver::precondition(const double* r, const double* r_old) {
+void BatchSolver::precondition(const double* r, const double* r_old, const float* rc) {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
@@ -238,7 +240,7 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     {
       ProfScope ps(ctx, "project", st);
       launch_projection(plan, opt.precond_prec, r, L_, Wsh, L_, n, B, q.active, projpart.p, st,
-                        ql);
+                        ql, rc);
     }
     {
       ProfScope ps(ctx, "reduced_solve", st);
@@ -274,9 +276,15 @@ void BatchSolver::precondition(const double* r, const double* r_old) {
     return;
   }
   // colour class c from the latest values of the others; its y^T r partials go to
-  // segment c (only from the sweep that leaves the class final)
+  // segment c (only from the sweep that leaves the class final).  Sweeps without dot
+  // products read the FP32 copy of r when there is one (y is FP32 then).
   auto sweep = [&](int color, bool dots) {
     ProfScope ps(ctx, color == 0 ? "gs_red" : "gs_black", st);
+    if (!dots && rc && y32) {
+      launch_gs_color<float, float>(g, color, B, coef.as<double>(), y.as<float>(), L_, rc, L_,
+                                    nullptr, nullptr, 0, q.active, nullptr, nullptr, st);
+      return;
+    }
     double* d0 = dots ? pr0 + gsegs.off[color] : nullptr;
     double* d1 = dots && pr1 ? pr1 + gsegs.off[color] : nullptr;
     // the sweep reports how many partial sums per query it wrote (chunked or marching)
@@ -332,14 +340,16 @@ void BatchSolver::init_cg() {
   launch_fill<double>(p1.as<double>(), L_, L_, B, 0.0, st);
   launch_fill<double>(r0.as<double>(), L_, L_, rrows, 0.0, st);  // also zeroes the padding
   if (r1.p) launch_fill<double>(r1.as<double>(), L_, L_, rrows, 0.0, st);
+  float* rc = use_r32 ? r32.as<float>() : nullptr;
+  if (rc) launch_fill<float>(rc, L_, L_, rrows, 0.f, st);
   const int ci = launch_init_rhs(f_base, f_ld, scale_d.as<double>(), g.N, r0.as<double>(), L_,
-                                 B, part_m.as<double>(), pt, st);
+                                 B, part_m.as<double>(), pt, st, rc);
   launch_fin_sum(part_m.as<double>(), ci, ci, q.fnorm2, nullptr, B, st);
   if (adaptive)  // r_0 = f is preconditioned first
     RB_HIP(hipMemcpyAsync(q.rr_in, q.fnorm2, sizeof(double) * B, hipMemcpyDeviceToDevice, st));
   factor();
   launch_fill<int>(q.restart, 0, B, 1, 1, st);
-  precondition(r0.as<double>(), nullptr);
+  precondition(r0.as<double>(), nullptr, rc);
   launch_fin_beta(part_r0.as<double>(), nullptr, dot_segs(), q, B, false, st);
 }
 
@@ -353,6 +363,7 @@ void BatchSolver::iterate_cg(int k) {
   const bool flex = opt.beta_flexible != 0;
   double* rin = (flex && (k & 1)) ? r1.as<double>() : r0.as<double>();
   double* rout = flex ? ((k & 1) ? r0.as<double>() : r1.as<double>()) : rin;
+  float* rc = use_r32 ? r32.as<float>() : nullptr;  // FP32 copy of rout
   // the previous iteration's direction update fused with the product: p = y + beta p; A p
   int ca, cb;
   {
@@ -369,7 +380,7 @@ void BatchSolver::iterate_cg(int k) {
   {
     ProfScope ps(ctx, "pass_b", st);
     cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, xc.as<double>(), rin, rout, q.alpha,
-                       q.active, part_m.as<double>(), st);
+                       q.active, part_m.as<double>(), st, rc);
   }
   // stopping test: recursive, then the true residual of the flagged queries, formed from x
   // after the correction accumulated since the previous check is folded into it.  The
@@ -384,12 +395,12 @@ void BatchSolver::iterate_cg(int k) {
     ProfScope ps(ctx, "true_residual", st);
     double* p2 = opt.floor_factor > 0.0 ? part_m2.as<double>() : nullptr;
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
-                 scale_d.as<double>(), q.flag, part_m.as<double>(), st, p2);
+                 scale_d.as<double>(), q.flag, part_m.as<double>(), st, p2, rc);
     launch_fin_true(part_m.as<double>(), cN, cN, q, B, opt.rtol, opt.maxit, st, p2,
                     opt.floor_factor);
   }
   // preconditioning and the new direction coefficient
-  precondition(rout, flex ? rin : nullptr);
+  precondition(rout, flex ? rin : nullptr, rc);
   launch_fin_beta(part_r0.as<double>(), flex ? part_r1.as<double>() : nullptr, dot_segs(), q, B,
                   flex, st);
 }
@@ -527,6 +538,10 @@ void BatchSolver::autotune() {
     return best;
   };
   const int caps[4] = {1, 2, 4, 8};
+  // the kernels as the solve runs them: pass B writing the FP32 copy of r, which the
+  // projection and (with several sweeps, most of) the sweeps read
+  float* rc = use_r32 ? r32.as<float>() : nullptr;
+  const bool gs_copy = rc && y32 && opt.smooth_sweeps > 1;
   TuneConfig best = tc, cur = tc;
   float ta = 1e30f, tb = 1e30f, tg = 1e30f;
   for (int kind : {1, 2}) {  // chunked, z-marching (3D only)
@@ -554,7 +569,7 @@ void BatchSolver::autotune() {
       const float t2 = timed([&] {
         launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
                       r0.as<double>(), r0.as<double>(), q.alpha, q.active, part_m.as<double>(),
-                      st);
+                      st, rc);
       });
       if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; }
     }
@@ -568,7 +583,10 @@ void BatchSolver::autotune() {
       cur.kind_gs = kind;
       set_stencil_tiles(cur);
       const float t3 = timed([&] {
-        if (y32)
+        if (gs_copy)
+          launch_gs_color<float, float>(g, 0, B, coef.as<double>(), y.as<float>(), L_, rc, L_,
+                                        nullptr, nullptr, 0, q.active, nullptr, nullptr, st);
+        else if (y32)
           launch_gs_color<float>(g, 0, B, coef.as<double>(), y.as<float>(), L_, r0.as<double>(),
                                  L_, nullptr, nullptr, L_, q.active, part_r0.as<double>(),
                                  nullptr, st);
@@ -608,7 +626,7 @@ void BatchSolver::autotune() {
       if (pl.chunks == 0) continue;
       const float t = timed([&] {
         launch_projection(pl, opt.precond_prec, r0.as<double>(), L_, Wsh, L_, n, B, q.active,
-                          projpart.p, st);
+                          projpart.p, st, nullptr, rc);
         // the reduction of the chunk partials grows with the number of chunks
         launch_reduce_solve(opt.precond_prec == RB_PREC_FP64, projpart.p, pl.chunks, B, pl.nj,
                             n, nuse_d.as<int>(), L.as<double>(), q.active, nullptr, nullptr,

@@ -38,6 +38,10 @@ struct BatchSolver {
   Buf qlist;  // active queries in increasing order, then their count (batched coarse step)
   Buf x, r0, r1, p0, p1, y, z;
   Buf xc;  // RBCG / CG: x-updates since the last true-residual check (folded into x there)
+  // RBCG with y in FP32 on stencil grids: an FP32 copy of the current r (same rows as r0),
+  // written wherever r is; read by the projection and the sweeps without dot products
+  bool use_r32 = false;
+  Buf r32;
   // fused red-black sweep (3D grids with nx <= 255, one forward sweep): the coarse
   // correction goes to zs (black half) and one launch writes y from it
   bool fused_ok = false;
@@ -73,7 +77,8 @@ struct BatchSolver {
   // RBCG / CG
   void init_cg();
   void iterate_cg(int k);
-  void precondition(const double* r, const double* r_old);
+  // rc (nullable): the FP32 copy of r
+  void precondition(const double* r, const double* r_old, const float* rc = nullptr);
   const Segs& dot_segs() const;
   // RBI
   void init_rbi();

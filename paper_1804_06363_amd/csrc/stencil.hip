@@ -284,7 +284,8 @@ __device__ __forceinline__ T diag_of(const Node<DIM>& n, const T* cf) {
 
 // ---- y = A(theta) u, or y = rhs - A u with partial ||y||^2 ------------------------------
 // mode 0: y = A u for every query.  mode 1: y = rhs_scale[b] * rhs_b - A u for queries
-// with flag[b] != 0 (others untouched) and partial sums of y^2.
+// with flag[b] != 0 (others untouched) and partial sums of y^2; y32 (nullable, mode 1):
+// an FP32 copy of y, rows of ld.
 // group bitmap of the apply kernel: at most kApplyMaxGroupWords * 32 = 16384 groups per
 // block (the launcher adds slots beyond that; batches hold at most 65535 queries)
 constexpr int kApplyMaxGroupWords = 512;
@@ -299,7 +300,8 @@ __global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, i
                                                     const double* __restrict__ rhs_scale,
                                                     const int* __restrict__ flag,
                                                     double* __restrict__ part,
-                                                    double* __restrict__ part2) {
+                                                    double* __restrict__ part2,
+                                                    float* __restrict__ y32) {
   extern __shared__ double dyn[];
   __shared__ double red[4 * QPB];
   // A block owns one chunk and the query groups slot, slot + slots, ...: with few slots
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(StencilGeom g, int64_t ld, i
           } else {
             const double r = rhs_scale[q0 + k] * rhs[(size_t)(q0 + k) * rhs_ld + pos] - Au;
             y[(size_t)(q0 + k) * ld + pos] = r;
+            if (y32) y32[(size_t)(q0 + k) * ld + pos] = (float)r;
             acc[k] += r * r;
             if (part2) {  // (|A| |u|)_pos: the face coefficients are non-negative
               double a = d * fabs(ub[pos]);
@@ -424,6 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(StencilGeom g, int64_t ld, 
 }
 
 // ---- pass B: x += alpha p; r_out = r_in - alpha A p; partial ||r_out||^2 ----------------
+// r32 (nullable): an FP32 copy of r_out, rows of ld.
 template <int DIM, int QPB>
 __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, int B, int chunks,
                                                      const double* coef,
@@ -432,7 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
                                                      const double* r_in, double* r_out,
                                                      const double* __restrict__ alpha,
                                                      const int* __restrict__ active,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part,
+                                                     float* __restrict__ r32) {
   extern __shared__ double dyn[];
   __shared__ double red[4 * QPB];
   const Tile tl = tile_of(chunks);
@@ -466,6 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
         at_byte(x + o, bp) += al[k] * pp;
         const double r = at_byte(r_in + o, bp) - al[k] * q;
         at_byte(r_out + o, bp) = r;
+        if (r32) at_byte(r32 + o, (uint32_t)pos * 4u) = (float)r;
         acc[k] += r * r;
       }
     }
@@ -502,9 +508,11 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
                                                       const double* r_in, double* r_out,
                                                       const double* __restrict__ scal,
                                                       const int* __restrict__ active,
-                                                      double* __restrict__ part, int pstride) {
+                                                      double* __restrict__ part, int pstride,
+                                                      float* __restrict__ r32) {
   // MODE 0 (pass A): v = y + beta p_in, p_out = v, partial v^T A v.
-  // MODE 1 (pass B): v = p_in, x += alpha v, r_out = r_in - alpha A v, partial ||r_out||^2.
+  // MODE 1 (pass B): v = p_in, x += alpha v, r_out = r_in - alpha A v, partial ||r_out||^2,
+  // and the FP32 copy r32 of r_out (rows of ld) unless r32 is null.
   constexpr int NW = kZThreads / 64;
   extern __shared__ double dyn[];
   __shared__ double red[NW * QPB];
@@ -581,9 +589,11 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   double* xq[QPB];
   const double* rq[QPB];
   double* oq[QPB];   // p_out (pass A) or r_out (pass B)
+  float* sq[QPB];    // r32 (pass B)
 #pragma unroll
   for (int q = 0; q < QPB; ++q) {
     const size_t b = (size_t)min(q0 + q, B - 1);
+    sq[q] = (MODE == 1 && r32) ? r32 + b * ld : nullptr;
     pq[q] = p_in + b * ld;
     yq[q] = MODE == 0 ? y + b * y_ld : nullptr;
     xq[q] = MODE == 1 ? x + b * ld : nullptr;
@@ -729,6 +739,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
           at_byte(xq[q], o) = Xk.x[s][q] + sc[q] * vp;
           const double r = Xk.r[s][q] - sc[q] * Av;
           at_byte(oq[q], o) = r;
+          if (r32) at_byte(sq[q], (uint32_t)pos * 4u) = (float)r;
           acc[q] += r * r;
         }
       }
@@ -769,12 +780,13 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
 // y_p rhs2_p (part1).  Arithmetic in TY (the smoother's precision).  The block's QPB
 // coefficient tables sit in LDS interleaved by query (entry e of query k at e QPB + k), so
 // one wide LDS read gives a face's coefficient for every query; each thread loads all its
-// queries' neighbour values before updating them.
-template <int DIM, int QPB, typename TY, bool NT>
+// queries' neighbour values before updating them.  RT = float: rhs is the FP32 copy of an
+// FP64 right-hand side (the update rounds rhs to TY = float first, so y is the same).
+template <int DIM, int QPB, typename TY, bool NT, typename RT = double>
 __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color, int B, int chunks,
                                                        const double* coef,
                                                        TY* __restrict__ y, int64_t y_ld,
-                                                       const double* __restrict__ rhs,
+                                                       const RT* __restrict__ rhs,
                                                        int64_t rhs_ld,
                                                        const double* __restrict__ rhs_scale,
                                                        const double* __restrict__ rhs2,
@@ -802,7 +814,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
   double a0[QPB], a1[QPB], fsc[QPB];
   // per-query rows: block-uniform bases (clamped to an existing query)
   TY* yq[QPB];
-  const double* rq[QPB];
+  const RT* rq[QPB];
   const double* r2q[QPB];
 #pragma unroll
   for (int k = 0; k < QPB; ++k) {
@@ -811,7 +823,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
     const size_t b = (size_t)min(q0 + k, B - 1);
     yq[k] = y + b * y_ld;
     rq[k] = rhs + b * rhs_ld;
-    r2q[k] = rhs2 ? rhs2 + b * rhs2_ld : rhs;
+    r2q[k] = rhs2 ? rhs2 + b * rhs2_ld : nullptr;
   }
   const int base = lo + tl.chunk * kThreads * kPT;
 #pragma unroll
@@ -821,6 +833,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
       Node<DIM> n;
       node_at<DIM>(g, pos, n);
       const uint32_t by = (uint32_t)pos * (uint32_t)sizeof(TY), br = (uint32_t)pos * 8u;
+      const uint32_t brt = (uint32_t)pos * (uint32_t)sizeof(RT);
       uint32_t bn[2 * DIM];
 #pragma unroll
       for (int f = 0; f < 2 * DIM; ++f) bn[f] = (uint32_t)n.nb[f] * (uint32_t)sizeof(TY);
@@ -836,7 +849,8 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
           // NT (a right-hand side per query): rhs is read once and y not again in this
           // sweep, so both bypass L2, leaving it to the neighbour values; a right-hand
           // side shared by the queries stays cached
-          fr[k] = NT ? __builtin_nontemporal_load(&at_byte(rq[k], br)) : at_byte(rq[k], br);
+          fr[k] = NT ? (double)__builtin_nontemporal_load(&at_byte(rq[k], brt))
+                     : (double)at_byte(rq[k], brt);
         } else {
 #pragma unroll
           for (int f = 0; f < 2 * DIM; ++f) nv[k][f] = TY(0);
@@ -893,11 +907,11 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
 // as in the marching passes: the neighbour values of plane k+3 (two steps ahead), the
 // halo, rhs (and rhs2) of plane k+1.  Partial sums go to part[b * tiles + tile].
 constexpr int kGsPairs = 2;  // pairs per thread: tiles of up to 2 * 512 / (zc / 2) rows
-template <int QPB, typename TY, bool FLEX>
+template <int QPB, typename TY, bool FLEX, typename RT = double>
 __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt, int color,
                                                          int B, const double* coef,
                                                          TY* __restrict__ y, int64_t y_ld,
-                                                         const double* __restrict__ rhs,
+                                                         const RT* __restrict__ rhs,
                                                          int64_t rhs_ld,
                                                          const double* __restrict__ rhs_scale,
                                                          const double* __restrict__ rhs2,
@@ -1002,7 +1016,8 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     TY v[QPB];
   };
   struct Rhs {
-    double r[NP][QPB], r2[NP][QPB];
+    RT r[NP][QPB];
+    double r2[NP][QPB];
   };
   // neighbour values of this thread's column pairs on plane k
   auto load_raw = [&](Raw& t, int k) {
@@ -1101,7 +1116,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
           d += c;
           off += c * (((inner >> f) & 1u) ? nv[f] : TY(0));
         }
-        const double fp = fsc[q] * Xk.r[a][q];
+        const double fp = fsc[q] * (double)Xk.r[a][q];
         const TY v = gs_div<TY>((TY)fp + off, d);
         y[(size_t)(q0 + q) * y_ld + pos] = v;
         a0[q] += (double)v * fp;
@@ -1538,7 +1553,9 @@ static dim3 grid_for(int chunks, int B, int qpb) {
 
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,
                   double* y, int mode, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
-                  const int* flag, double* part, hipStream_t s, double* part2) {
+                  const int* flag, double* part, hipStream_t s, double* part2, float* y32) {
+  RB_REQUIRE(!y32 || (mode == 1 && !g.csr), RB_EINVAL,
+             "FP32 residual copy: mode 1 on stencil grids only");
   if (g.csr)
     return csr_apply(g, ld, B, coef, u, y, mode, rhs, rhs_ld, rhs_scale, flag, part, s, part2);
   const int chunks = stencil_chunks_all(g.N);
@@ -1554,7 +1571,7 @@ void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, c
                                 : groups;
     hipLaunchKernelGGL((k_apply<D.value, Q.value>), dim3((unsigned)((long)chunks * slots)),
                        dim3(kThreads), Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, u, y,
-                       mode, rhs, rhs_ld, rhs_scale, flag, part, part2);
+                       mode, rhs, rhs_ld, rhs_scale, flag, part, part2, y32);
   });
 }
 
@@ -1596,7 +1613,8 @@ template <int MODE, typename TY>
 static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const double* coef,
                          const TY* y, int64_t y_ld, const double* p_in, double* p_out, double* x,
                          const double* r_in, double* r_out, const double* scal,
-                         const int* active, double* part, hipStream_t s, int kind) {
+                         const int* active, double* part, hipStream_t s, int kind,
+                         float* r32 = nullptr) {
   if (kind == 1) return 0;
   qpb = std::min(qpb, 4);
   ZTile zt;
@@ -1610,15 +1628,18 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   switch (qpb) {
     case 4:
       hipLaunchKernelGGL((k_zmarch<4, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride);
+                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
+                         r32);
       break;
     case 2:
       hipLaunchKernelGGL((k_zmarch<2, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride);
+                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
+                         r32);
       break;
     default:
       hipLaunchKernelGGL((k_zmarch<1, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride);
+                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
+                         r32);
       break;
   }
   return tiles;
@@ -1653,17 +1674,18 @@ template int launch_pass_a<float>(const StencilGeom&, int64_t, int, const double
 
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
-                  const int* active, double* part, hipStream_t s) {
+                  const int* active, double* part, hipStream_t s, float* r32) {
+  RB_REQUIRE(!r32 || !g.csr, RB_EINVAL, "FP32 residual copy: stencil grids only");
   if (g.csr) return csr_pass_b(g, ld, B, coef, p, x, r_in, r_out, alpha, active, part, s);
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 2);
   if (const int t = launch_zmarch<1, double>(g, qpb, ld, B, coef, nullptr, 0, p, nullptr, x, r_in,
-                                             r_out, alpha, active, part, s, t_tiles.kind_b))
+                                             r_out, alpha, active, part, s, t_tiles.kind_b, r32))
     return t;
   const int chunks = stencil_chunks_all(g.N);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     hipLaunchKernelGGL((k_pass_b<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
                        Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, p, x, r_in, r_out,
-                       alpha, active, part);
+                       alpha, active, part, r32);
   });
   return chunks;
 }
@@ -1692,9 +1714,9 @@ static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
 // marching with 2, 1 or 4 (1.05-1.09 ms with one column pair per thread): a sweep moves
 // only 8 B per node per barrier pair of each plane, against pass B's 40.  The autotuner
 // tries both.  Returns the number of partial sums per query (0: not run).
-template <typename TY>
+template <typename TY, typename RT>
 static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, const double* coef,
-                            TY* y, int64_t y_ld, const double* rhs, int64_t rhs_ld,
+                            TY* y, int64_t y_ld, const RT* rhs, int64_t rhs_ld,
                             const double* rhs_scale, const double* rhs2, int64_t rhs2_ld,
                             const int* active, double* part0, double* part1, hipStream_t s,
                             int kind) {
@@ -1709,7 +1731,7 @@ static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, con
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const dim3 grid((unsigned)(tiles * groups));
   auto go = [&](auto Q, auto F) {
-    hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value>), grid, dim3(kZThreads), lds, s, g, zt,
+    hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value, RT>), grid, dim3(kZThreads), lds, s, g, zt,
                        color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
                        part0, part1);
   };
@@ -1794,42 +1816,53 @@ template int launch_gs_fused<float>(const StencilGeom&, int, const double*, cons
                                     int64_t, const double*, int64_t, const double*, int64_t,
                                     const int*, double*, double*, int, hipStream_t);
 
-template <typename TY>
+template <typename TY, typename RT>
 int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, TY* y,
-                    int64_t y_ld, const double* rhs, int64_t rhs_ld, const double* rhs_scale,
+                    int64_t y_ld, const RT* rhs, int64_t rhs_ld, const double* rhs_scale,
                     const double* rhs2, int64_t rhs2_ld, const int* active, double* part0,
                     double* part1, hipStream_t s) {
   if (g.csr) {
-    csr_gs_color<TY>(g, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
-                     part0, part1, s);
-    return stencil_chunks(g.coff[color + 1] - g.coff[color]);
+    if constexpr (std::is_same<RT, double>::value) {
+      csr_gs_color<TY>(g, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                       part0, part1, s);
+      return stencil_chunks(g.coff[color + 1] - g.coff[color]);
+    } else {
+      RB_REQUIRE(false, RB_EINVAL, "FP32 right-hand side: stencil grids only");
+    }
   }
   const int qpb = pick_qpb(g, B, (int)sizeof(TY), t_tiles.qpb_gs ? t_tiles.qpb_gs : 4);
-  if (const int t = launch_gs_zmarch<TY>(g, color, qpb, B, coef, y, y_ld, rhs, rhs_ld,
-                                         rhs_scale, rhs2, rhs2_ld, active, part0, part1, s,
-                                         t_tiles.kind_gs))
+  if (const int t = launch_gs_zmarch<TY, RT>(g, color, qpb, B, coef, y, y_ld, rhs, rhs_ld,
+                                             rhs_scale, rhs2, rhs2_ld, active, part0, part1, s,
+                                             t_tiles.kind_gs))
     return t;
   const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     const size_t lds = Q.value * g.ct_size * sizeof(TY);
     if (rhs_ld)
-      hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY, true>), grid_for(chunks, B, Q.value),
-                         dim3(kThreads), lds, s, g, color, B, chunks, coef, y, y_ld, rhs, rhs_ld,
-                         rhs_scale, rhs2, rhs2_ld, active, part0, part1);
+      hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY, true, RT>),
+                         grid_for(chunks, B, Q.value), dim3(kThreads), lds, s, g, color, B,
+                         chunks, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                         part0, part1);
     else
-      hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY, false>), grid_for(chunks, B, Q.value),
-                         dim3(kThreads), lds, s, g, color, B, chunks, coef, y, y_ld, rhs, rhs_ld,
-                         rhs_scale, rhs2, rhs2_ld, active, part0, part1);
+      hipLaunchKernelGGL((k_gs_color<D.value, Q.value, TY, false, RT>),
+                         grid_for(chunks, B, Q.value), dim3(kThreads), lds, s, g, color, B,
+                         chunks, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
+                         part0, part1);
   });
   return chunks;
 }
-template int launch_gs_color<double>(const StencilGeom&, int, int, const double*, double*,
-                                     int64_t, const double*, int64_t, const double*,
-                                     const double*, int64_t, const int*, double*, double*,
-                                     hipStream_t);
-template int launch_gs_color<float>(const StencilGeom&, int, int, const double*, float*, int64_t,
-                                    const double*, int64_t, const double*, const double*,
-                                    int64_t, const int*, double*, double*, hipStream_t);
+template int launch_gs_color<double, double>(const StencilGeom&, int, int, const double*, double*,
+                                             int64_t, const double*, int64_t, const double*,
+                                             const double*, int64_t, const int*, double*,
+                                             double*, hipStream_t);
+template int launch_gs_color<float, double>(const StencilGeom&, int, int, const double*, float*,
+                                            int64_t, const double*, int64_t, const double*,
+                                            const double*, int64_t, const int*, double*, double*,
+                                            hipStream_t);
+template int launch_gs_color<float, float>(const StencilGeom&, int, int, const double*, float*,
+                                           int64_t, const float*, int64_t, const double*,
+                                           const double*, int64_t, const int*, double*, double*,
+                                           hipStream_t);
 
 template <typename TY>
 void launch_jacobi(const StencilGeom& g, int B, const double* coef, const TY* z, TY* y,

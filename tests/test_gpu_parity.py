@@ -241,6 +241,37 @@ def test_zmarch_fixed_iterations(lib, ctx, dims, blocks, B):
         assert _rel(xz[b], xc[b]) <= 1e-12, (b, _rel(xz[b], xc[b]))
 
 
+@pytest.mark.parametrize("dims,blocks,stencil", [((63, 63), (2, 2), "auto"),
+                                                  ((31, 31, 31), (2, 2, 2), "chunked"),
+                                                  ((31, 31, 31), (2, 2, 2), "zmarch"),
+                                                  ((129, 5, 9), (2, 2, 2), "zmarch")])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("B", [5, 20])
+def test_residual_copy_is_bitwise_equal(lib, ctx, dims, blocks, stencil, prec, B):
+    """The FP32 copy of r, which the projection and the sweeps that form no dot product
+    read instead of r, changes no bit: both round r to FP32 before using it.  Fixed-k
+    iterates with one and three sweeps, literal and flexible beta (B = 5 takes the
+    split-wave projection, B = 20 the batched MFMA one), and a converged solve, whose
+    residual replacements refresh the copy too."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 6, seed=70)
+    theta = log_uniform_mu(71, B, op.Q, 0.1, 10.0)
+    for sweeps, flexible in ((1, False), (3, False), (3, True)):
+        kw = dict(prec=prec, fixed_iters=6, sweeps=sweeps, flexible=flexible, stencil=stencil)
+        x0, s0 = lib.solve_batch(ctx, prob, basis, theta, residual_copy=False, **kw)
+        x1, s1 = lib.solve_batch(ctx, prob, basis, theta, residual_copy=True, **kw)
+        assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy()), (sweeps, flexible)
+        assert np.array_equal(s0.rel_res_recursive, s1.rel_res_recursive)
+    Ws = _snapshot_basis(op, 5, seed=72)
+    bs = lib.Basis.from_host(ctx, prob, Ws.T)
+    kw = dict(prec=prec, sweeps=3, stencil=stencil, check_every=2)
+    x0, s0 = lib.solve_batch(ctx, prob, bs, theta, residual_copy=False, **kw)
+    x1, s1 = lib.solve_batch(ctx, prob, bs, theta, residual_copy=True, **kw)
+    assert (s1.status == lib.RB_OK).all() and s1.rel_res_true.max() <= 1e-10
+    assert np.array_equal(s0.iters, s1.iters)
+    assert np.array_equal(s0.rel_res_true, s1.rel_res_true)
+    assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_zmarch_converged(lib, ctx, prec):
     """Converged solves with the z-marching passes: queries retire at different
@@ -579,6 +610,45 @@ def test_solve_multi_uneven(lib, ctx):
         assert abs(st.iters[k] - ref.iters) <= 1
         kappa = _cond(op.assemble(th))
         assert _rel(x.cpu().numpy(), ref.x) <= 2 * kappa * 1e-10
+
+
+def test_solve_multi_query_order(lib, ctx):
+    """The results of rb_solve_multi, query by query, do not depend on the order of the
+    call's query list (each query's place in its problem's batch), bit for bit, with FP64
+    and FP32 preconditioners."""
+    import torch
+    specs = [((31, 31), (2, 2)), ((7, 9, 5), (2, 2, 3))]
+    probs, bases = [], []
+    for i, (dims, blocks) in enumerate(specs):
+        op = BlockDiffusion(dims, blocks)
+        W = _snapshot_basis(op, 6, seed=120 + i)
+        prob = lib.Problem(ctx, dims, blocks)
+        probs.append(prob)
+        bases.append(lib.Basis.from_host(ctx, prob, W.T))
+    rng = np.random.default_rng(121)
+    spec = []
+    for k in range(20):
+        pi = int(rng.integers(0, 2))
+        nu = int(rng.choice([2, 4, 6]))
+        th = log_uniform_mu(300 + k, 1, probs[pi].Q, 0.01, 100.0)[0]
+        spec.append((pi, nu, th))
+    for prec in ("fp64", "fp32"):
+        out = []
+        for perm in (np.arange(20), rng.permutation(20)):
+            qs = [(spec[i][0], spec[i][1], spec[i][2], None,
+                   torch.empty(probs[spec[i][0]].N, dtype=torch.float64, device="cuda"))
+                  for i in perm]
+            st = lib.solve_multi(ctx, probs, bases, qs, flexible=True, prec=prec, sweeps=2)
+            xs = [None] * 20
+            its = np.zeros(20, dtype=np.int64)
+            for j, i in enumerate(perm):
+                xs[i] = qs[j][4].cpu().numpy()
+                its[i] = st.iters[j]
+                assert st.status[j] == lib.RB_OK
+            out.append((xs, its))
+        assert np.array_equal(out[0][1], out[1][1]), prec
+        for i in range(20):
+            assert np.array_equal(out[0][0][i], out[1][0][i]), (prec, i)
 
 
 def test_solve_multi_per_query_tolerance(lib, ctx):
