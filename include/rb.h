@@ -190,6 +190,10 @@ typedef struct {
                          product read instead of r.  Both round r to FP32 before using it,
                          so the results are the same, from fewer bytes read; 0 = read r.
                          Ignored elsewhere. */
+  int prolong_kind;   /* prolongation W e of a batch of at least 16 queries with an FP32 /
+                         BF16 preconditioner: 0 = autotuned / default (MFMA tiles), 1 = MFMA
+                         tiles, 2 = vector units (one node per thread, FP32 FMAs).  Changes
+                         speed and summation order only. */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 

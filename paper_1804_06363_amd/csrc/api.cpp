@@ -677,6 +677,8 @@ static void check_opts(const rb_solve_opts* o) {
   RB_REQUIRE(o->smooth_sweeps >= 0 && o->smooth_sweeps <= 64, RB_EINVAL, "bad smooth_sweeps");
   RB_REQUIRE(o->residual_copy == 0 || o->residual_copy == 1, RB_EINVAL,
              "residual_copy must be 0 or 1");
+  RB_REQUIRE(o->prolong_kind >= 0 && o->prolong_kind <= 2, RB_EINVAL,
+             "prolong_kind must be 0, 1 or 2");
   RB_REQUIRE(std::isfinite(o->floor_factor) && o->floor_factor >= 0.0, RB_EINVAL,
              "bad floor_factor");
   RB_REQUIRE(o->smooth_sweeps <= 1 || o->smoother == RB_SMOOTH_RBGS ||

@@ -514,6 +514,103 @@ __global__ __launch_bounds__(256) void k_prolong_mfma(const TW* __restrict__ W, 
   }
 }
 
+// Batched prolongation on the vector units (FP32 / BF16 basis, FP32 arithmetic, out
+// overwritten): one node per thread.  The thread holds its node's NB = round_up(n, 8) basis
+// entries in registers and forms out_q[pos] = sum_{j<n} W[j][pos] e_q[j], j in increasing
+// order, for the queries of its block's chunk, two at a time.  The e rows are the same for
+// every lane (block-uniform addresses), so they come through the scalar cache into scalar
+// registers and each product is one FMA with a scalar operand; each store writes 256
+// consecutive entries of one query's row.  A run of 256 nodes is read once per query chunk,
+// and the chunks of a run are consecutive block ids on one XCD, so the later ones find its
+// W rows in L2.  Against the MFMA kernel this issues all of a node's W loads at once
+// instead of one four-row step after another.
+constexpr int kVecQChunk = 64;  // queries per block
+template <typename TW, typename TO, int NB>
+__global__ __launch_bounds__(256) void k_prolong_vec(const TW* __restrict__ W, int64_t w_ld, int n,
+                                                     const float* __restrict__ e, int e_ld,
+                                                     int B, const int* __restrict__ active,
+                                                     const int* __restrict__ qlist,
+                                                     TO* __restrict__ out, int64_t o_ld, int lo,
+                                                     int hi, int qchunks) {
+  const int total = gridDim.x;
+  const int qd = total / 8, rd = total % 8;
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int id = xcd < rd ? xcd * (qd + 1) + slot : rd * (qd + 1) + (xcd - rd) * qd + slot;
+  const int run = id / qchunks, qc = id % qchunks;
+  const int cnt = qlist ? qlist[B] : B;
+  const int c0 = qc * kVecQChunk;
+  if (c0 >= cnt) return;
+  const int c1 = min(c0 + kVecQChunk, cnt);
+  const int pos = lo + run * 256 + (int)threadIdx.x;
+  const bool ok = pos < hi;
+  const int pc = ok ? pos : lo;  // a valid address for the loads of lanes past hi
+  // rows below NB - 8 exist (n > NB - 8); the last eight load row min(j, n - 1) and keep
+  // zero past n, so every load is unconditional and in bounds
+  float w[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int jr = (j < NB - 8 || j < n) ? j : n - 1;
+    float v;
+    if constexpr (sizeof(TW) == 2)
+      v = rbk::bf16_to_f32(W[(size_t)jr * w_ld + pc]);
+    else
+      v = (float)W[(size_t)jr * w_ld + pc];
+    w[j] = (j < NB - 8 || j < n) ? v : 0.f;
+  }
+  for (int c = c0; c < c1; c += 2) {
+    const bool two = c + 1 < c1;
+    const int qa = qlist ? qlist[c] : c;
+    const int qb = two ? (qlist ? qlist[c + 1] : c + 1) : qa;
+    const float* ea = e + (size_t)qa * e_ld;
+    const float* eb = e + (size_t)qb * e_ld;
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < NB; j0 += 8) {
+      // eight entries of each e row at a time: the compiler barrier keeps the scalar loads
+      // of later entries from being hoisted here, which would exhaust the scalar registers
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int j = j0 + k;
+        if (j0 + 8 < NB || j < n) {  // only the last group of eight can pass n
+          a = fmaf(w[j], ea[j], a);
+          b = fmaf(w[j], eb[j], b);
+        }
+      }
+    }
+    if (ok && (qlist || active[qa])) out[(size_t)qa * o_ld + pos] = (TO)a;
+    if (two && ok && (qlist || active[qb])) out[(size_t)qb * o_ld + pos] = (TO)b;
+  }
+}
+
+template <typename TW, typename TO>
+static void launch_prolong_vec(const TW* W, int64_t w_ld, int n, const float* e, int e_ld, int B,
+                               const int* active, const int* qlist, TO* out, int64_t o_ld, int lo,
+                               int hi, hipStream_t s) {
+  const int runs = (hi - lo + 255) / 256;
+  const int qchunks = (B + kVecQChunk - 1) / kVecQChunk;
+  const dim3 grid((unsigned)(runs * qchunks));
+  auto go = [&](auto NBc) {
+    hipLaunchKernelGGL((k_prolong_vec<TW, TO, NBc.value>), grid, dim3(256), 0, s, W, w_ld, n, e,
+                       e_ld, B, active, qlist, out, o_ld, lo, hi, qchunks);
+  };
+  switch ((n + 7) / 8) {
+    case 1: go(std::integral_constant<int, 8>{}); break;
+    case 2: go(std::integral_constant<int, 16>{}); break;
+    case 3: go(std::integral_constant<int, 24>{}); break;
+    case 4: go(std::integral_constant<int, 32>{}); break;
+    case 5: go(std::integral_constant<int, 40>{}); break;
+    case 6: go(std::integral_constant<int, 48>{}); break;
+    case 7: go(std::integral_constant<int, 56>{}); break;
+    case 8: go(std::integral_constant<int, 64>{}); break;
+    case 9: go(std::integral_constant<int, 72>{}); break;
+    default:
+      RB_REQUIRE(n <= 80, RB_EUNSUPPORTED, "vector prolongation: basis size above 80");
+      go(std::integral_constant<int, 80>{});
+      break;
+  }
+}
+
 template <typename TW, typename TO, bool ADD>
 static void launch_prolong_mfma(const TW* W, int64_t w_ld, int n, const float* e, int e_ld, int B,
                                 const int* active, const int* qlist, TO* out, int64_t o_ld,
@@ -549,6 +646,24 @@ void launch_prolong(rb_prec prec, const void* W, int64_t w_ld, int n, const doub
     else
       launch_prolong_t<double, double, double, false>((const double*)W, w_ld, n, e64, e_ld, B,
                                                       active, (double*)out, o_ld, lo, hi, s);
+    return;
+  }
+  if (B >= 16 && !add && stencil_tiles().kind_pro == 2) {
+    if (prec == RB_PREC_FP32) {
+      if (out_is_double)
+        launch_prolong_vec<float, double>((const float*)W, w_ld, n, e32, e_ld, B, active, qlist,
+                                          (double*)out, o_ld, lo, hi, s);
+      else
+        launch_prolong_vec<float, float>((const float*)W, w_ld, n, e32, e_ld, B, active, qlist,
+                                         (float*)out, o_ld, lo, hi, s);
+    } else {
+      if (out_is_double)
+        launch_prolong_vec<uint16_t, double>((const uint16_t*)W, w_ld, n, e32, e_ld, B, active,
+                                             qlist, (double*)out, o_ld, lo, hi, s);
+      else
+        launch_prolong_vec<uint16_t, float>((const uint16_t*)W, w_ld, n, e32, e_ld, B, active,
+                                            qlist, (float*)out, o_ld, lo, hi, s);
+    }
     return;
   }
   if (B >= 16) {

@@ -170,6 +170,8 @@ struct TuneConfig {
   int proj_target = 0;                   // projection: target number of blocks
   int kind_a = 0, kind_b = 0;            // pass A / B: 0 default, 1 chunked, 2 z-marching
   int kind_gs = 0;                       // colour sweeps: the same kinds
+  int kind_pro = 0;                      // batched prolongation: 0 default (MFMA), 1 MFMA,
+                                         // 2 vector units
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

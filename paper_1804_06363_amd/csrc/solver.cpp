@@ -77,6 +77,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
       tc.kind_a = tc.kind_b = std::min(opt.stencil_kind, 2);
       tc.kind_gs = opt.stencil_kind;
     }
+    if (opt.prolong_kind) tc.kind_pro = opt.prolong_kind;
   }
   // projection plan first: for batches it reads residual rows in whole query tiles
   if (n > 0) {
@@ -637,6 +638,23 @@ void BatchSolver::autotune() {
     plan = plan_projection(g.N, B, n, best.proj_target);
     plan.padded = true;
     plan_wave_chunks(plan, B, best.proj_target, opt.precond_prec);
+  }
+  if (n > 0 && B >= 16 && y32 && !opt.prolong_kind) {  // batched prolongation: MFMA tiles
+                                                       // or the vector units
+    const bool full = opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE;
+    const int lo = full ? 0 : g.coff[1];
+    launch_fill<float>(e32.as<float>(), e_ld, e_ld, padded_queries(B), 0.f, st);
+    float tk[2] = {1e30f, 1e30f};
+    for (int kp = 1; kp <= 2; ++kp) {
+      cur = best;
+      cur.kind_pro = kp;
+      set_stencil_tiles(cur);
+      tk[kp - 1] = timed([&] {
+        launch_prolong(opt.precond_prec, Wsh, L_, n, e64.as<double>(), e32.as<float>(), e_ld, B,
+                       q.active, y.p, false, L_, lo, g.N, false, st, nullptr);
+      });
+    }
+    best.kind_pro = tk[1] < tk[0] ? 2 : 1;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

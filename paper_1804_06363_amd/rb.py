@@ -50,7 +50,8 @@ class SolveOpts(C.Structure):
                 ("beta_flexible", C.c_int), ("use_graph", C.c_int), ("fixed_iters", C.c_int),
                 ("check_every", C.c_int), ("autotune", C.c_int), ("stencil_kind", C.c_int),
                 ("adapt_gamma", C.c_double), ("floor_factor", C.c_double),
-                ("smooth_sweeps", C.c_int), ("residual_copy", C.c_int)]
+                ("smooth_sweeps", C.c_int), ("residual_copy", C.c_int),
+                ("prolong_kind", C.c_int)]
 
 
 class QueryStats(C.Structure):
@@ -322,11 +323,13 @@ class Basis:
 
 
 STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2, "fused": 3}
+PROLONG_KIND = {"auto": 0, "mfma": 1, "vector": 2}
 
 
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,
                flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False,
-               stencil="auto", adapt_gamma=0.0, sweeps=1, floor_factor=0.0, residual_copy=True):
+               stencil="auto", adapt_gamma=0.0, sweeps=1, floor_factor=0.0, residual_copy=True,
+               prolong="auto"):
     o = SolveOpts()
     _lib.rb_solve_opts_default(C.byref(o))
     o.solver = SOLVER[solver]
@@ -344,6 +347,7 @@ def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=20
     o.smooth_sweeps = sweeps
     o.floor_factor = floor_factor
     o.residual_copy = int(residual_copy)
+    o.prolong_kind = PROLONG_KIND[prolong]
     return o
 
 

@@ -169,6 +169,53 @@ def test_preconditioner_mixed(lib, ctx, prec, tol):
         assert _rel(y[b], M(r[b])) <= tol
 
 
+@pytest.mark.parametrize("prolong", ["mfma", "vector"])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 5e-2)])
+@pytest.mark.parametrize("B,n", [(20, 12), (70, 40), (17, 80)])
+def test_preconditioner_mixed_batched(lib, ctx, prolong, prec, tol, B, n):
+    """One preconditioner application for batches of at least 16 queries (the batched
+    MFMA projection over the active-query list; the prolongation on MFMA tiles or on the
+    vector units, whose register tile covers n rounded up to 8, here partly, fully and at
+    the largest basis) against the oracle's FP64 preconditioner; and the two prolongations
+    against each other (FP32 summation order only)."""
+    dims, blocks = (15, 13, 11), (2, 2, 2)
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, n, seed=16)
+    theta = log_uniform_mu(17, B, op.Q, 0.1, 10.0)
+    r = random_vectors(18, B, op.N)
+    y = lib.precond_batch(ctx, prob, basis, theta, _t(r), prec=prec, prolong=prolong)
+    y = y.cpu().numpy()
+    for b in sorted({0, 1, B // 2, B - 2, B - 1}):
+        A, M = orb.make_preconditioner(op, theta[b], W)
+        assert _rel(y[b], M(r[b])) <= tol, (b, _rel(y[b], M(r[b])))
+    other = "mfma" if prolong == "vector" else "vector"
+    y2 = lib.precond_batch(ctx, prob, basis, theta, _t(r), prec=prec, prolong=other)
+    y2 = y2.cpu().numpy()
+    for b in range(B):
+        assert _rel(y[b], y2[b]) <= 2e-6, (b, _rel(y[b], y2[b]))
+
+
+def test_prolong_kinds_converge(lib, ctx):
+    """Converged FP32 solves with either prolongation: the same iteration counts (within
+    one), true residuals <= 1e-10, solutions within 2 kappa 1e-10 of each other."""
+    dims, blocks = (31, 31, 31), (2, 2, 2)
+    op = BlockDiffusion(dims, blocks)
+    W = _snapshot_basis(op, 6, seed=130)
+    prob = lib.Problem(ctx, dims, blocks)
+    basis = lib.Basis.from_host(ctx, prob, W.T)
+    theta = log_uniform_mu(131, 24, op.Q, 0.1, 10.0)
+    x1, s1 = lib.solve_batch(ctx, prob, basis, theta, prec="fp32", sweeps=2, prolong="mfma")
+    x2, s2 = lib.solve_batch(ctx, prob, basis, theta, prec="fp32", sweeps=2, prolong="vector")
+    assert (s1.status == lib.RB_OK).all() and (s2.status == lib.RB_OK).all()
+    assert max(s1.rel_res_true.max(), s2.rel_res_true.max()) <= 1e-10
+    assert np.abs(s1.iters - s2.iters).max() <= 1
+    a1, a2 = x1.cpu().numpy(), x2.cpu().numpy()
+    h = 1.0 / (dims[0] + 1)
+    for b in range(len(theta)):
+        kappa = (theta[b].max() * 12.0 / h**2) / (
+            theta[b].min() * 12.0 / h**2 * np.sin(np.pi * h / 2) ** 2)
+        assert _rel(a2[b], a1[b]) <= 2 * kappa * 1e-10
+
+
 # ---- RBCG / RBI / CG -------------------------------------------------------------------
 @pytest.mark.parametrize("dims,blocks,n", [((15, 15), (2, 2), 4), ((63, 63), (2, 2), 6),
                                            ((7, 9, 5), (2, 2, 3), 3),
