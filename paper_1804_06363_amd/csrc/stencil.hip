@@ -479,6 +479,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
   store_partials<QPB>(acc, mask, q0, tl.chunk, chunks, part, red);
 }
 
+// A coordinate in [0, hi] with the parity of v (v itself when it is in range), for the
+// loads of lanes whose node lies outside the tile or the grid: a node with the parities of
+// the wanted one has its colour on every plane, so its storage position lies next to those
+// the neighbouring lanes load and costs no extra cache line; its value is never used.
+__device__ __forceinline__ int clamp_same_parity(int v, int hi) {
+  const int c = v < 0 ? (v & 1) : (v > hi ? hi - ((v - hi) & 1) : v);
+  return (c < 0 || c > hi) ? min(max(v, 0), hi) : c;
+}
+
 // ---- 3D passes A and B marching along z --------------------------------------------------
 // A block owns QPB queries, an in-plane tile of zr rows x zc columns (at most 1024 nodes,
 // two per thread) and a slab of planes, which it walks from bottom to top.  The values
@@ -951,7 +960,9 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   const int pairs = zt.zc >> 1;
   const int rstep = kZThreads / pairs;  // rows between a thread's pairs
   const int pu = threadIdx.x % pairs;
-  int j[NP], m_[NP][2], slot[NP][2], cb[NP][2][4], zxy[NP][2];
+  // a node outside the tile or the grid is loaded from one of its colour inside them
+  const int jlast = min(j0 + zt.zr, g.ny) - 1;  // last row of the tile inside the grid
+  int j[NP], lm[NP][2], slot[NP][2], cb[NP][2][4], zxy[NP][2];
   unsigned inb[NP][2];
   bool own[NP][2];
 #pragma unroll
@@ -960,12 +971,13 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     j[a] = j0 + jj;
     const bool rowok = jj < zt.zr && j[a] < g.ny;
     const int jc = rowok ? j[a] : 0;
+    const int jl = rowok ? j[a] : clamp_same_parity(j[a], jlast);
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
       const int i = i0 + 2 * pu + c2;
       own[a][c2] = rowok && i < g.nx;
       const int ic = own[a][c2] ? i : 0;
-      m_[a][c2] = ic + g.nx * jc;
+      lm[a][c2] = clamp_same_parity(i, g.nx - 1) + g.nx * jl;
       slot[a][c2] = (jj + 1) * W2 + 2 * pu + c2 + 1;
       const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
       const int sx = tx & 0xff, sy = ty & 0xff;
@@ -981,21 +993,48 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   // the column of pair a updated on plane k (the colour of node (i, j, k) is the parity
   // of i + j + k, and i0 + 2u is even); the other one holds the neighbour value
   auto ucol = [&](int a, int k) { return (j[a] + k + color) & 1; };
-  // halo cell of this thread (rows j0-1, j0+zr and columns i0-1, i0+zc of the tile)
-  int hm, hslot;
-  bool hv;
+  // Halo (rows j0-1, j0+zr and columns i0-1, i0+zc of the tile): thread h covers two
+  // adjacent cells (two columns of a halo row, or two rows of a halo column), which have
+  // opposite colours; on each plane only the one of the colour opposite to the swept one
+  // is a neighbour value, and the thread loads that one.
+  int hmc[2], hsl[2], hpar;
+  bool hvc[2];
   {
     const int h = threadIdx.x;
-    int hj, hi;
-    if (h < zt.zc) { hj = -1; hi = h; }
-    else if (h < 2 * zt.zc) { hj = zt.zr; hi = h - zt.zc; }
-    else if (h < 2 * zt.zc + zt.zr) { hj = h - 2 * zt.zc; hi = -1; }
-    else { hj = h - 2 * zt.zc - zt.zr; hi = zt.zc; }
-    const int i = i0 + hi, jh = j0 + hj;
-    hv = h < 2 * (zt.zc + zt.zr) && i >= 0 && i < g.nx && jh >= 0 && jh < g.ny;
-    hm = hv ? i + g.nx * jh : 0;
-    hslot = (hj + 1) * W2 + hi + 1;
+    const int hr = zt.zc >> 1, hc = (zt.zr + 1) >> 1;  // cell pairs per halo row / column
+    int hj[2], hi[2];
+    bool col = false, any = true;
+    if (h < hr) {
+      hj[0] = hj[1] = -1;
+      hi[0] = 2 * h;
+    } else if (h < 2 * hr) {
+      hj[0] = hj[1] = zt.zr;
+      hi[0] = 2 * (h - hr);
+    } else if (h < 2 * hr + hc) {
+      col = true;
+      hi[0] = hi[1] = -1;
+      hj[0] = 2 * (h - 2 * hr);
+    } else if (h < 2 * hr + 2 * hc) {
+      col = true;
+      hi[0] = hi[1] = zt.zc;
+      hj[0] = 2 * (h - 2 * hr - hc);
+    } else {
+      any = false;
+      hj[0] = hj[1] = 0;
+      hi[0] = 0;
+    }
+    if (col) hj[1] = hj[0] + 1; else hi[1] = hi[0] + 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int i = i0 + hi[c], jh = j0 + hj[c];
+      hvc[c] = any && i >= 0 && i < g.nx && jh >= 0 && jh < g.ny && (!col || hj[c] < zt.zr);
+      hmc[c] = clamp_same_parity(i, g.nx - 1) + g.nx * clamp_same_parity(jh, g.ny - 1);
+      hsl[c] = (hj[c] + 1) * W2 + hi[c] + 1;
+    }
+    hpar = (i0 + hi[0] + j0 + hj[0]) & 1;  // colour of cell 0 on plane 0
   }
+  // the halo cell of the opposite colour on plane k
+  auto hsel = [&](int k) { return ((hpar + k) & 1) == (color ^ 1) ? 0 : 1; };
 
   auto spos = [&](int L) { return (L & 1) ? g.NR + (L >> 1) : (L >> 1); };
   auto live = [&](int q) { return ((mask >> q) & 1u) != 0; };
@@ -1023,13 +1062,13 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   auto load_raw = [&](Raw& t, int k) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      const int pos = spos(k * P + (ucol(a, k) ? m_[a][0] : m_[a][1]));
+      const int pos = spos(k * P + (ucol(a, k) ? lm[a][0] : lm[a][1]));
 #pragma unroll
       for (int q = 0; q < QPB; ++q) t.v[a][q] = y[rowy[q] + pos];
     }
   };
   auto load_halo = [&](Halo& t, int k) {
-    const int pos = spos(k * P + hm);
+    const int pos = spos(k * P + (hsel(k) ? hmc[1] : hmc[0]));
 #pragma unroll
     for (int q = 0; q < QPB; ++q) t.v[q] = y[rowy[q] + pos];
   };
@@ -1037,7 +1076,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   auto load_rhs = [&](Rhs& t, int k) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      const int pos = spos(k * P + (ucol(a, k) ? m_[a][1] : m_[a][0]));
+      const int pos = spos(k * P + (ucol(a, k) ? lm[a][1] : lm[a][0]));
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
         t.r[a][q] = rhs[rowr[q] + pos];
@@ -1083,9 +1122,12 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
         for (int q = 0; q < QPB; ++q) pl[q * plane + ss] = vc.v[a][q];
       }
     }
-    if (hv)
+    {
+      const int hs = hsel(k);
+      if (hs ? hvc[1] : hvc[0])
 #pragma unroll
-      for (int q = 0; q < QPB; ++q) pl[q * plane + hslot] = Hk.v[q];
+        for (int q = 0; q < QPB; ++q) pl[q * plane + (hs ? hsl[1] : hsl[0])] = Hk.v[q];
+    }
     __syncthreads();
     const int sz = zinfo[3 * (k - k0)];
     const int zlo = zinfo[3 * (k - k0) + 1];
@@ -1095,7 +1137,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     for (int a = 0; a < NP; ++a) {
       const int cu = ucol(a, k);
       if (!(cu ? own[a][1] : own[a][0])) continue;
-      const int pos = spos(k * P + (cu ? m_[a][1] : m_[a][0]));
+      const int pos = spos(k * P + (cu ? lm[a][1] : lm[a][0]));  // an own node
       const unsigned inner = (cu ? inb[a][1] : inb[a][0]) | zb;
       const int su = cu ? slot[a][1] : slot[a][0];
       const int zx = cu ? zxy[a][1] : zxy[a][0];
