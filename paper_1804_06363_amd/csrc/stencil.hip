@@ -969,7 +969,8 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   for (int a = 0; a < NP; ++a) {
     const int jj = threadIdx.x / pairs + a * rstep;
     j[a] = j0 + jj;
-    const bool rowok = jj < zt.zr && j[a] < g.ny;
+    // threads past rstep * pairs own nothing (their rows belong to the next pair set)
+    const bool rowok = (int)threadIdx.x < rstep * pairs && jj < zt.zr && j[a] < g.ny;
     const int jc = rowok ? j[a] : 0;
     const int jl = rowok ? j[a] : clamp_same_parity(j[a], jlast);
 #pragma unroll
@@ -1736,10 +1737,13 @@ int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, c
 // most `cap` tiles per query (the partial sums the solver holds for one colour).
 static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
   if (g.dim != 3) return false;
-  zt.zc = std::min(g.nx + 1, 128);  // nx is odd: the last column of the last tile is outside
+  // whole rows up to 255 columns (nx odd: the last column of the last tile is outside),
+  // so that no halo column is read: a halo column costs one cache line per row
+  zt.zc = std::min(g.nx + 1, 256);
   const int pairs = zt.zc / 2;
   zt.zr = std::min(g.ny, kGsPairs * (kZThreads / pairs));
-  if (zt.zr < 1 || 2 * (zt.zc + zt.zr) > kZThreads) return false;
+  // one thread per pair of halo cells
+  if (zt.zr < 1 || 2 * pairs + 2 * ((zt.zr + 1) / 2) > kZThreads) return false;
   zt.ct = (g.nx + zt.zc - 1) / zt.zc;
   zt.rt = (g.ny + zt.zr - 1) / zt.zr;
   const int tiles2 = zt.rt * zt.ct;

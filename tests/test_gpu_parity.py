@@ -260,13 +260,17 @@ def test_rbcg_converged(lib, ctx, dims, blocks, n, graph):
         assert _rel(x[b], xo) <= 1e-10, (b, _rel(x[b], xo))
 
 
-# 3D grids for the z-marching passes.  Tiles span whole grid rows while nx <= 256 (no
-# halo columns) and are 128 columns wide beyond (halo columns at i0 - 1 and i0 + 128):
-# one tile; several slabs; a whole-row tile of 129 columns; 255-column rows in a full
-# and a ragged row tile; three column tiles (the last one column wide) with halo
-# columns; several row tiles with halo rows
+# 3D grids for the z-marching passes and sweeps.  The passes' tiles span whole grid rows
+# while nx <= 256 (no halo columns) and are 128 columns wide beyond (halo columns at
+# i0 - 1 and i0 + 128); the sweeps' tiles span whole rows while nx <= 255 and are 256
+# columns wide beyond, with 512 / (columns / 2) rows per set of column pairs: one tile;
+# several slabs; a whole-row tile of 129 columns; 255-column rows in a full and a ragged
+# row tile; three (passes) or two (sweeps) column tiles, the last one column wide, with
+# halo columns; several row tiles with halo rows; 130-column sweep tiles whose rows come
+# from two pair sets of 7 rows (512 is not a multiple of 65 pairs)
 ZGRIDS = [((7, 9, 5), (2, 2, 3)), ((31, 31, 31), (2, 2, 2)), ((129, 5, 9), (2, 2, 2)),
-          ((255, 7, 9), (2, 2, 2)), ((257, 3, 5), (2, 2, 2)), ((63, 63, 63), (2, 2, 2))]
+          ((255, 7, 9), (2, 2, 2)), ((257, 3, 5), (2, 2, 2)), ((63, 63, 63), (2, 2, 2)),
+          ((129, 21, 5), (2, 2, 2))]
 
 
 @pytest.mark.parametrize("dims,blocks", ZGRIDS)
