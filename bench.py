@@ -6,7 +6,7 @@ Workload (synthetic, seeded): 3D 7-point diffusion on a 127^3 interior grid
 (P = Q = 8), f = 1; reduced basis n = 40 from the GPU adaptive greedy (Alg. 4, residual
 indicator) over 256 training parameters; 256 test parameters per call.  A step is
 one rb_solve_batch of the 256 queries to relative residual 1e-10 (RBCG of Alg. 3,
-FP32 preconditioner with four red-black Gauss-Seidel sweeps per application, FP64 CG),
+FP32 preconditioner with six red-black Gauss-Seidel sweeps per application, FP64 CG),
 its kernels timed one by one with HIP events.  value = converged mu-solves per second.
 Also: the same solves replayed from a captured HIP graph (two iterations per launch, no
 per-kernel events) as `graph_replay`.
@@ -94,15 +94,16 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--B", type=int, default=0, help="queries per call (default: workload's)")
     ap.add_argument("--flexible", type=int, default=0)
-    ap.add_argument("--sweeps", type=int, default=4,
+    ap.add_argument("--sweeps", type=int, default=6,
                     help="red-black Gauss-Seidel sweeps per preconditioner application (the "
-                         "smoother study on this workload: 1 -> 133.6, 2 -> 157.3, 3 -> 174.5, "
-                         "4 -> 178.2, 6 -> 177.3 mu-solves/s)")
+                         "smoother study on this workload: 1 -> 130.2, 2 -> 160.0, 3 -> 182.9, "
+                         "4 -> 190.6, 5 -> 194.0, 6 -> 195.4, 8 -> 194.1 mu-solves/s)")
     ap.add_argument("--residual-copy", type=int, default=1,
                     help="keep an FP32 copy of r for the projection and the sweeps without dot "
                          "products (FP32 / BF16 preconditioner; same results, fewer bytes)")
-    ap.add_argument("--uneven-sweeps", type=int, default=4,
-                    help="Gauss-Seidel sweeps per preconditioner application in the uneven batch")
+    ap.add_argument("--uneven-sweeps", type=int, default=8,
+                    help="Gauss-Seidel sweeps per preconditioner application in the uneven batch "
+                         "(4 -> 90.7, 6 -> 111.0, 8 -> 113.2, 10 -> 113.9 mu-solves/s)")
     ap.add_argument("--graph", type=int, default=0,
                     help="time the main steps with the iterations replayed from a captured HIP "
                          "graph (the per-kernel events then see no launches: roofline null)")
@@ -369,7 +370,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def uneven_leg(rb, torch, sweeps=4):
+def uneven_leg(rb, torch, sweeps=8):
     """1024 queries mixing 2D 63^2, 255^2, 1023^2 (4x4 kappa blocks) and 3D 63^3 (2x2x2),
     mu log-uniform in [0.01, 100], per-query basis sizes n in {10, 20, 40, 60} (leading
     columns of one n = 60 basis per grid), FP32 preconditioner, one rb_solve_multi call.

@@ -176,9 +176,10 @@ typedef struct {
                          beta_flexible (the preconditioner changes between iterations). */
   double floor_factor; /* > 0: the true-residual test also accepts ||f - A x|| <= floor_factor
                           * eps * || |A| |x| || (eps = 2^-52), the rounding level of an FP64
-                          * residual of x, once the iteration has stalled there (the true
-                          * residual of this check is above half of the previous check's,
-                          * i.e. a residual replacement did not pay); such queries end RB_OK
+                          * residual of x, once the iteration has stalled there (at two
+                          * checks in a row the true residual stayed above half of the
+                          * previous check's: residual replacements did not pay); such
+                          * queries end RB_OK
                           * with at_floor = 1.  0: off.  For problems whose tolerance lies
                           * below what FP64 reaches (strong kappa contrasts on fine grids). */
   int smooth_sweeps;  /* Gauss-Seidel sweeps per smoother application (RBGS: forward sweeps,

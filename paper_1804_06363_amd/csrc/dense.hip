@@ -1162,14 +1162,17 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
     const double rel = sqrt(rr / q.fnorm2[b]);
     const double lvl = floor_factor * 0x1p-52 * sqrt(aa / q.fnorm2[b]);
     // The rounding level is a worst-case bound, often far above what the iteration still
-    // reaches, so it is accepted only once a residual replacement has stopped paying:
-    // this check's true residual is above half of the previous check's (0 before the
-    // first check).
+    // reaches, so it is accepted only once residual replacements have stopped paying: at
+    // two checks in a row the true residual stayed above half of the previous check's (0
+    // before the first check).  One such check can be a query that is still converging
+    // and was checked just above its tolerance.
     const double prev = q.rel_true[b];
     const bool stalled = prev > 0.0 && rel > 0.5 * prev;
+    const int run = stalled ? (q.stalls ? q.stalls[b] + 1 : 2) : 0;
+    if (q.stalls) q.stalls[b] = run;
     q.rel_true[b] = rel;
     q.flag[b] = 0;
-    if (rel <= rtol || (part2 && stalled && rel <= lvl)) {
+    if (rel <= rtol || (part2 && run >= 2 && rel <= lvl)) {
       q.active[b] = 0;
       q.status[b] = RB_OK;
       if (q.at_floor && rel > rtol) q.at_floor[b] = 1;

@@ -31,6 +31,7 @@ struct QState {
   double gamma2 = 0.0;
   int nmax = 0;
   int* at_floor = nullptr;  // accepted at the rounding level (floor test on)
+  int* stalls = nullptr;    // true-residual checks in a row that gained less than half
 };
 
 // Segments of a partial-sum buffer written by successive colour sweeps.

@@ -137,7 +137,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     e32 = get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
     qlist = get_ws(WS_QLIST, sizeof(int) * ((size_t)B + 1));
   }
-  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 6) * (size_t)B);
+  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 7) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
@@ -145,6 +145,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in);
   takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
   takeI(q.at_floor);
+  takeI(q.stalls);
   if (adaptive) {
     q.nuse = nuse_d.as<int>();
     q.gamma2 = opt.adapt_gamma * opt.adapt_gamma;
@@ -186,6 +187,7 @@ void BatchSolver::prepare() {
   }
   launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
   launch_fill<int>(q.at_floor, 0, (int64_t)B, 1, 0, st);
+  launch_fill<int>(q.stalls, 0, (int64_t)B, 1, 0, st);
   launch_fill<int>(q.status, 0, (int64_t)B, 1, (int)RB_OK, st);
   launch_fill<int>(q.active, 0, (int64_t)B, 1, 1, st);
   launch_fill<int>(q.iters, 0, 3 * (int64_t)B, 1, 0, st);  // iters, flag, restart

@@ -196,11 +196,13 @@ def test_large_configuration_paths_on_a_thin_grid(lib, ctx):
               f"{st.iters.max()}, difference from the FP64 oracle {max(errs):.2e}")
 
 
-def test_uneven_configuration(lib, ctx):
+@pytest.mark.parametrize("sweeps", [4, 8])
+def test_uneven_configuration(lib, ctx, sweeps):
     """The uneven batch's four grids (63^2, 255^2, 1023^2 with 4x4 kappa blocks, 63^3 with
     2x2x2; mu log-uniform in [0.01, 100]) and basis sizes 10, 20, 40, 60 mixed in one call
-    with the benchmark's options (FP32 preconditioner with four Gauss-Seidel sweeps,
-    flexible beta, HIP graphs, floor_factor 16, 1e-9 on 1023^2), 256 of its 1024 queries:
+    with the benchmark's options (FP32 preconditioner with four or eight Gauss-Seidel
+    sweeps, flexible beta, HIP graphs, floor_factor 16, 1e-9 on 1023^2), 256 of its 1024
+    queries:
     every query meets its tolerance or is accepted at the rounding level within 2x the
     residual of its exact solution rounded to doubles, and sampled queries on the 63^2 and
     63^3 grids match the oracle's RBCG with the same leading basis vectors (solutions
@@ -219,7 +221,7 @@ def test_uneven_configuration(lib, ctx):
     xs = [torch.empty(UNEVEN_GRIDS[g].N, dtype=torch.float64, device="cuda") for g, _, _ in qs]
     queries = [(g, nu, mu, None, x, UNEVEN_GRIDS[g].rtol) for (g, nu, mu), x in zip(qs, xs)]
     opts = lib.solve_opts(prec="fp32", flexible=True, graph=True, maxit=10000, floor_factor=16.0,
-                          sweeps=4)
+                          sweeps=sweeps)
     st = lib.solve_multi(ctx, probs, bases, queries, opts=opts)
     tol = np.array([UNEVEN_GRIDS[g].rtol for g, _, _ in qs])
     assert (st.status == lib.RB_OK).all()
@@ -247,6 +249,6 @@ def test_uneven_configuration(lib, ctx):
         Wn, AN, fN = bases[g].info()
         W = np.ascontiguousarray(Wn[:nu].T)
         ref = orb.solve_rbcg(op, qs[k][2], W, AN[:, :nu, :nu], flexible=True, rtol=wk.rtol,
-                             maxit=10000, sweeps=4)
+                             maxit=10000, sweeps=sweeps)
         assert ref.converged
         assert _rel(xs[k].cpu().numpy(), ref.x) <= 2 * _kappa_bound(wk.dims, qs[k][2]) * wk.rtol

@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size and launch configuration (3D 127^3, N = 2,048,383,
-n = 40, B = 256, FP32 or BF16 preconditioner, literal beta), with the 40 smoothest sine
+n = 40, B = 256, FP32 or BF16 preconditioner with six red-black Gauss-Seidel sweeps per
+application, literal beta), with the 40 smoothest sine
 modes as the basis: every query reaches a true relative residual <= 1e-10 in FP64, and
 sampled queries are checked one by one against the oracle's RBCG with the same basis
 (iteration counts within 3%, 15% for BF16; solutions within 2 kappa(A) 1e-10 of each
@@ -43,6 +44,9 @@ def setup(lib):
     return w, ctx, prob, basis, op, W, AN
 
 
+SWEEPS = 6  # bench.py's default
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_bench_configuration_parity(lib, setup, prec):
     """The full batch with an FP32 (the benchmark's) or BF16 preconditioner; the measured
@@ -50,12 +54,12 @@ def test_bench_configuration_parity(lib, setup, prec):
     import torch
     w, ctx, prob, basis, op, W, AN = setup
     test = w.test_mu(w.B)
-    x, st = lib.solve_batch(ctx, prob, basis, test, prec=prec)
+    x, st = lib.solve_batch(ctx, prob, basis, test, prec=prec, sweeps=SWEEPS)
     assert (st.status == lib.RB_OK).all()
     assert st.rel_res_true.max() <= 1e-10
     errs = []
     for b in (0, 137):
-        ref = orb.solve_rbcg(op, test[b], W, AN, rtol=1e-10)
+        ref = orb.solve_rbcg(op, test[b], W, AN, rtol=1e-10, sweeps=SWEEPS)
         xb = x[b].cpu().numpy()
         assert ref.converged
         # the FP32 preconditioner is the oracle's to 1e-7; the BF16 one uses a basis rounded
@@ -68,7 +72,7 @@ def test_bench_configuration_parity(lib, setup, prec):
         # the GPU iterate satisfies the FP64 residual check independently of the library
         r = op.rhs() - op.assemble(test[b]) @ xb
         assert np.linalg.norm(r) / np.linalg.norm(op.rhs()) <= 1.01e-10
-    print(f"127^3 B=256 {prec}: iterations mean {st.iters.mean():.1f}; difference from the "
+    print(f"127^3 B=256 {prec} x{SWEEPS}: iterations mean {st.iters.mean():.1f}; difference from the "
           f"FP64 oracle {errs[0]:.2e}, {errs[1]:.2e}")
     del x
     torch.cuda.empty_cache()
