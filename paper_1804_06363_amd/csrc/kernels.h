@@ -66,6 +66,9 @@ inline int padded_queries(int B) { return (B + 255) / 256 * 256; }
 int stencil_chunks(int count);
 // partial-sum chunks of an all-node stencil pass (apply, pass A/B, Jacobi)
 int stencil_chunks_all(int N);
+// partial-sum chunks of a one-colour sweep over storage positions [lo, hi) (its chunks
+// start at lo rounded down to a 128-byte line; at most stencil_chunks(hi - lo) + 1)
+int stencil_sweep_chunks(int lo, int hi);
 // mode 1 with part2: partial sums of (|A| |u|)^2 as well (rounding level of the residual);
 // y32 (mode 1, stencil grids): also an FP32 copy of y, rows of ld
 void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* u,

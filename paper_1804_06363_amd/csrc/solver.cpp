@@ -52,7 +52,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   gsegs.n = g.C;
   int64_t acc = 0;
   for (int c = 0; c < g.C; ++c) {
-    gsegs.cnt[c] = stencil_chunks(g.coff[c + 1] - g.coff[c]);  // at most; each sweep
+    gsegs.cnt[c] = stencil_chunks(g.coff[c + 1] - g.coff[c]) + 1;  // at most; each sweep
                                                                 // records its own count
     gsegs.off[c] = acc;
     acc += (int64_t)B * gsegs.cnt[c];

@@ -210,13 +210,17 @@ constexpr int kPH = RB_KPH;  // positions per thread and colour in the all-node 
 constexpr int kXCD = 8;
 
 // All-node passes: chunk c holds red positions [c*CH, (c+1)*CH) and the black positions
-// NR + [c*CH, (c+1)*CH) (CH = 256*kPH), so the red and black neighbours of a node are
-// loaded by the same block and the plane neighbours by the chunks next to it.
+// NRa + [c*CH, (c+1)*CH) (CH = 256*kPH; NRa = NR rounded down to a multiple of 32, the
+// positions below NR left out), so the red and black neighbours of a node are loaded by
+// the same block and the plane neighbours by the chunks next to it, and every wave's run
+// of black positions starts on a 128-byte line (NR is odd on odd 2D grids).
+constexpr int kAlign = 32;  // positions per 128-byte line of FP32 values
 __device__ __forceinline__ int paired_pos(const StencilGeom& g, int chunk, int t) {
   const int half = t / kPH, u = t % kPH;
   const int off = chunk * kThreads * kPH + u * kThreads + (int)threadIdx.x;
   if (half == 0) return off < g.NR ? off : -1;
-  return g.NR + off < g.N ? g.NR + off : -1;
+  const int b = (g.NR & ~(kAlign - 1)) + off;
+  return (b >= g.NR && b < g.N) ? b : -1;
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int total) {
@@ -821,6 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
   const int lo = color ? g.NR : 0;
   const int hi = color ? g.N : g.NR;
   double a0[QPB], a1[QPB], fsc[QPB];
+  // chunks start at lo rounded down to a line (positions below lo left out)
   // per-query rows: block-uniform bases (clamped to an existing query)
   TY* yq[QPB];
   const RT* rq[QPB];
@@ -834,11 +839,11 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
     rq[k] = rhs + b * rhs_ld;
     r2q[k] = rhs2 ? rhs2 + b * rhs2_ld : nullptr;
   }
-  const int base = lo + tl.chunk * kThreads * kPT;
+  const int base = (lo & ~(kAlign - 1)) + tl.chunk * kThreads * kPT;
 #pragma unroll
   for (int t = 0; t < kPT; ++t) {
     const int pos = base + t * kThreads + threadIdx.x;
-    if (pos < hi) {
+    if (pos >= lo && pos < hi) {
       Node<DIM> n;
       node_at<DIM>(g, pos, n);
       const uint32_t by = (uint32_t)pos * (uint32_t)sizeof(TY), br = (uint32_t)pos * 8u;
@@ -1555,8 +1560,11 @@ void launch_from_storage(const rb_problem& p, int B, const double* sto, int64_t 
 int stencil_chunks(int count) { return (count + kThreads * kPT - 1) / (kThreads * kPT); }
 int stencil_chunks_all(int N) {
   const int NR = (N + 1) / 2;
-  return (NR + kThreads * kPH - 1) / (kThreads * kPH);
+  const int CH = kThreads * kPH;
+  // red [0, NR) and black [NR rounded down to kAlign, N) (paired_pos)
+  return std::max((NR + CH - 1) / CH, (N - (NR & ~(kAlign - 1)) + CH - 1) / CH);
 }
+int stencil_sweep_chunks(int lo, int hi) { return stencil_chunks(hi - (lo & ~(kAlign - 1))); }
 
 static thread_local TuneConfig t_tiles;
 void set_stencil_tiles(const TuneConfig& c) { t_tiles = c; }
@@ -1881,7 +1889,7 @@ int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, 
                                              rhs_scale, rhs2, rhs2_ld, active, part0, part1, s,
                                              t_tiles.kind_gs))
     return t;
-  const int chunks = stencil_chunks(color ? g.N - g.NR : g.NR);
+  const int chunks = color ? stencil_sweep_chunks(g.NR, g.N) : stencil_sweep_chunks(0, g.NR);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
     const size_t lds = Q.value * g.ct_size * sizeof(TY);
     if (rhs_ld)
