@@ -669,7 +669,7 @@ static void check_opts(const rb_solve_opts* o) {
              "bad precision");
   RB_REQUIRE(o->smoother >= RB_SMOOTH_RBGS && o->smoother <= RB_SMOOTH_NONE, RB_EINVAL,
              "bad smoother");
-  RB_REQUIRE(o->stencil_kind >= 0 && o->stencil_kind <= 3, RB_EINVAL, "bad stencil kind");
+  RB_REQUIRE(o->stencil_kind >= 0 && o->stencil_kind <= 4, RB_EINVAL, "bad stencil kind");
   RB_REQUIRE(std::isfinite(o->adapt_gamma) && o->adapt_gamma >= 0.0, RB_EINVAL,
              "bad adapt_gamma");
   RB_REQUIRE(o->adapt_gamma == 0.0 || o->solver == RB_SOLVER_RBCG, RB_EINVAL,

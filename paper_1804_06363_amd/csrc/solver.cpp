@@ -75,7 +75,8 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     if (const TuneConfig* c = ctx->tuner.find(tune_key)) tc = *c;
     if (opt.stencil_kind) {
       tc.kind_a = tc.kind_b = std::min(opt.stencil_kind, 2);
-      tc.kind_gs = opt.stencil_kind;
+      tc.kind_gs = opt.stencil_kind == 4 ? 2 : opt.stencil_kind;
+      tc.zn_a = tc.zn_b = opt.stencil_kind == 4 ? 4 : 0;
     }
     if (opt.prolong_kind) tc.kind_pro = opt.prolong_kind;
   }
@@ -547,13 +548,15 @@ void BatchSolver::autotune() {
   const bool gs_copy = rc && y32 && opt.smooth_sweeps > 1;
   TuneConfig best = tc, cur = tc;
   float ta = 1e30f, tb = 1e30f, tg = 1e30f;
-  for (int kind : {1, 2}) {  // chunked, z-marching (3D only)
+  for (int kz : {1, 2, 4}) {  // chunked, z-marching with 2 or 4 nodes per thread (3D only)
+    const int kind = kz == 1 ? 1 : 2, zn = kz == 1 ? 0 : kz;
     if (kind == 2 && g.dim != 3) break;
     for (int c : caps) {
-      if (c > B || (kind == 2 && c > 4)) break;
+      if (c > B || (kind == 2 && c > 4) || (zn == 4 && c > 2)) break;
       cur = best;
       cur.qpb_a = c;
       cur.kind_a = kind;
+      cur.zn_a = zn;
       set_stencil_tiles(cur);
       const float t1 = timed([&] {
         if (y32)
@@ -564,17 +567,18 @@ void BatchSolver::autotune() {
                                 p0.as<double>(), p1.as<double>(), q.beta, q.active,
                                 part_m.as<double>(), st);
       });
-      if (t1 < ta) { ta = t1; best.qpb_a = c; best.kind_a = kind; }
+      if (t1 < ta) { ta = t1; best.qpb_a = c; best.kind_a = kind; best.zn_a = zn; }
       cur = best;
       cur.qpb_b = c;
       cur.kind_b = kind;
+      cur.zn_b = zn;
       set_stencil_tiles(cur);
       const float t2 = timed([&] {
         launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
                       r0.as<double>(), r0.as<double>(), q.alpha, q.active, part_m.as<double>(),
                       st, rc);
       });
-      if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; }
+      if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; best.zn_b = zn; }
     }
   }
   for (int kind : {1, 2}) {  // chunked, marching (3D only)

@@ -493,8 +493,8 @@ __device__ __forceinline__ int clamp_same_parity(int v, int hi) {
 }
 
 // ---- 3D passes A and B marching along z --------------------------------------------------
-// A block owns QPB queries, an in-plane tile of zr rows x zc columns (at most 1024 nodes,
-// two per thread) and a slab of planes, which it walks from bottom to top.  The values
+// A block owns QPB queries, an in-plane tile of zr rows x zc columns (at most 512 ZN nodes,
+// ZN = 2 or 4 per thread) and a slab of planes, which it walks from bottom to top.  The values
 // of the current plane (the tile plus one halo row / column on each side) sit in LDS,
 // and every thread keeps the values of its own nodes on the planes below and above in
 // registers, so each vector element reaches the block once: the in-plane neighbours
@@ -509,9 +509,9 @@ struct ZTile {
   int slabs, kslab;  // slabs along z and planes per slab
 };
 constexpr int kZThreads = 512;
-constexpr int kZNodes = 2;  // own nodes per thread (zr * zc <= 1024)
+constexpr int kZNodes = 2;  // own nodes per thread by default (zr * zc <= 1024); 4 for taller tiles
 
-template <int QPB, int MODE, typename TY>
+template <int QPB, int MODE, typename TY, int ZN>
 __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, int64_t ld, int B,
                                                       const double* coef,
                                                       const TY* __restrict__ y, int64_t y_ld,
@@ -552,11 +552,11 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   for (int q = 0; q < QPB; ++q) sc[q] = ((mask >> q) & 1u) ? scal[q0 + q] : 0.0;
 
   // own nodes: in-plane offset m, LDS slot, x/y coefficient bases, boundary bits
-  int m_[kZNodes], slot[kZNodes], cb[kZNodes][4], zxy[kZNodes];
-  unsigned inb[kZNodes];
-  bool own[kZNodes];
+  int m_[ZN], slot[ZN], cb[ZN][4], zxy[ZN];
+  unsigned inb[ZN];
+  bool own[ZN];
 #pragma unroll
-  for (int s = 0; s < kZNodes; ++s) {
+  for (int s = 0; s < ZN; ++s) {
     const int u = threadIdx.x + s * kZThreads;
     const int jj = u / zt.zc, ii = u - jj * zt.zc;
     const int i = i0 + ii, j = j0 + jj;
@@ -619,19 +619,19 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   // parity of k - k0 and the loop is unrolled by two, so they stay in fixed registers
   // (a loop-carried copy of a just-loaded register waits for it).
   struct Raw {
-    double p[kZNodes][QPB];
-    TY y[kZNodes][QPB];
+    double p[ZN][QPB];
+    TY y[ZN][QPB];
   };
   struct Halo {
     double p[QPB];
     TY y[QPB];
   };
   struct XR {
-    double x[kZNodes][QPB], r[kZNodes][QPB];
+    double x[ZN][QPB], r[ZN][QPB];
   };
   auto load_raw = [&](Raw& r, int k) {
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s) {
+    for (int s = 0; s < ZN; ++s) {
       const uint32_t pos = (uint32_t)spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
@@ -640,9 +640,9 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       }
     }
   };
-  auto combine = [&](double (&v)[kZNodes][QPB], const Raw& r) {
+  auto combine = [&](double (&v)[ZN][QPB], const Raw& r) {
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s)
+    for (int s = 0; s < ZN; ++s)
 #pragma unroll
       for (int q = 0; q < QPB; ++q)
         v[s][q] = MODE == 0 ? (double)r.y[s][q] + sc[q] * r.p[s][q] : r.p[s][q];
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   auto load_xr = [&](XR& t, int k) {
     if (MODE != 1) return;
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s) {
+    for (int s = 0; s < ZN; ++s) {
       const uint32_t pos = (uint32_t)spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
 
   const int klast = g.nz - 1;
   // planes k-1, k, k+1 combined; later planes in flight (clamped planes are never used)
-  double vb[kZNodes][QPB], vc[kZNodes][QPB], vn[kZNodes][QPB];
+  double vb[ZN][QPB], vc[ZN][QPB], vn[ZN][QPB];
   Raw R0, R1;
   Halo H0, H1;
   XR X0, X1;
@@ -709,7 +709,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     load_xr(Xn, min(k + 1, klast));
     __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s)
+    for (int s = 0; s < ZN; ++s)
       if (own[s])
 #pragma unroll
         for (int q = 0; q < QPB; ++q) pl[q * plane + slot[s]] = vc[s][q];
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     const int zhi = zinfo[3 * (k - k0) + 2];
     const unsigned zb = (k > 0 ? 16u : 0u) | (k < klast ? 32u : 0u);
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s) {
+    for (int s = 0; s < ZN; ++s) {
       if (!own[s]) continue;
       const int pos = spos(k * P + m_[s]);
       const unsigned inner = inb[s] | zb;
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       }
     }
 #pragma unroll
-    for (int s = 0; s < kZNodes; ++s)
+    for (int s = 0; s < ZN; ++s)
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
         vb[s][q] = vc[s][q];
@@ -1628,12 +1628,14 @@ void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, c
 
 // Tile of the z-marching passes for `groups` query groups; false if the grid does not
 // suit them (not 3D, or more partial sums than the chunked passes produce).
-static bool z_plan(const StencilGeom& g, int groups, ZTile& zt) {
+// zn: own nodes per thread (2, or 4 for tiles twice as tall, whose halo rows are a smaller
+// share of the rows read).
+static bool z_plan(const StencilGeom& g, int groups, ZTile& zt, int zn = kZNodes) {
   if (g.dim != 3) return false;
   // full rows while one thread per halo cell suffices: a tile as wide as the grid has no
   // valid halo columns, so only its two halo rows need threads
   zt.zc = 2 * g.nx <= kZThreads ? g.nx : 128;
-  zt.zr = std::min(g.ny, (kZThreads * kZNodes) / zt.zc);
+  zt.zr = std::min(g.ny, (kZThreads * zn) / zt.zc);
   const int halo = zt.zc == g.nx ? 2 * zt.zc : 2 * (zt.zc + zt.zr);
   if (zt.zr < 1 || halo > kZThreads) return false;
   zt.ct = (g.nx + zt.zc - 1) / zt.zc;
@@ -1665,32 +1667,34 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
                          const TY* y, int64_t y_ld, const double* p_in, double* p_out, double* x,
                          const double* r_in, double* r_out, const double* scal,
                          const int* active, double* part, hipStream_t s, int kind,
-                         float* r32 = nullptr) {
+                         float* r32 = nullptr, int zn = kZNodes) {
   if (kind == 1) return 0;
   qpb = std::min(qpb, 4);
+  if (zn != 4 || qpb > 2) zn = kZNodes;  // four nodes per thread: up to two queries per block
   ZTile zt;
   const int groups = (B + qpb - 1) / qpb;
-  if (!z_plan(g, groups, zt) || z_lds(g, zt, qpb) > 65536) return 0;
+  if (!z_plan(g, groups, zt, zn) || z_lds(g, zt, qpb) > 65536) return 0;
   if (kind == 0 && groups * zt.rt * zt.ct < 256) return 0;
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const int pstride = stencil_chunks_all(g.N);  // row stride of the partial sums
   const dim3 grid((unsigned)(tiles * groups));
   const size_t lds = z_lds(g, zt, qpb);
+  auto go = [&](auto Q, auto Z) {
+    hipLaunchKernelGGL((k_zmarch<Q.value, MODE, TY, Z.value>), grid, dim3(kZThreads), lds, s, g,
+                       zt, ld, B, coef, y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part,
+                       pstride, r32);
+  };
+  using Z2 = std::integral_constant<int, kZNodes>;
+  using Z4 = std::integral_constant<int, 4>;
   switch (qpb) {
-    case 4:
-      hipLaunchKernelGGL((k_zmarch<4, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
-                         r32);
-      break;
+    case 4: go(std::integral_constant<int, 4>{}, Z2{}); break;
     case 2:
-      hipLaunchKernelGGL((k_zmarch<2, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
-                         r32);
+      if (zn == 4) go(std::integral_constant<int, 2>{}, Z4{});
+      else go(std::integral_constant<int, 2>{}, Z2{});
       break;
     default:
-      hipLaunchKernelGGL((k_zmarch<1, MODE, TY>), grid, dim3(kZThreads), lds, s, g, zt, ld, B, coef,
-                         y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part, pstride,
-                         r32);
+      if (zn == 4) go(std::integral_constant<int, 1>{}, Z4{});
+      else go(std::integral_constant<int, 1>{}, Z2{});
       break;
   }
   return tiles;
@@ -1706,7 +1710,8 @@ int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, c
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_a ? t_tiles.qpb_a : 2);
   if (const int t = launch_zmarch<0, TY>(g, t_tiles.qpb_a ? qpb : 1, ld, B, coef, y, y_ld, p_old,
                                          p_new, nullptr, nullptr, nullptr, beta, active, part, s,
-                                         t_tiles.kind_a))
+                                         t_tiles.kind_a, nullptr,
+                                         t_tiles.zn_a ? t_tiles.zn_a : kZNodes))
     return t;
   const int chunks = stencil_chunks_all(g.N);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
@@ -1730,7 +1735,8 @@ int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, c
   if (g.csr) return csr_pass_b(g, ld, B, coef, p, x, r_in, r_out, alpha, active, part, s);
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 2);
   if (const int t = launch_zmarch<1, double>(g, qpb, ld, B, coef, nullptr, 0, p, nullptr, x, r_in,
-                                             r_out, alpha, active, part, s, t_tiles.kind_b, r32))
+                                             r_out, alpha, active, part, s, t_tiles.kind_b, r32,
+                                             t_tiles.zn_b ? t_tiles.zn_b : kZNodes))
     return t;
   const int chunks = stencil_chunks_all(g.N);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {

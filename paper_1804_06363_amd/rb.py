@@ -322,7 +322,7 @@ class Basis:
             pass
 
 
-STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2, "fused": 3}
+STENCIL_KIND = {"auto": 0, "chunked": 1, "zmarch": 2, "fused": 3, "zmarch4": 4}
 PROLONG_KIND = {"auto": 0, "mfma": 1, "vector": 2}
 
 

@@ -276,20 +276,24 @@ ZGRIDS = [((7, 9, 5), (2, 2, 3)), ((31, 31, 31), (2, 2, 2)), ((129, 5, 9), (2, 2
 @pytest.mark.parametrize("dims,blocks", ZGRIDS)
 @pytest.mark.parametrize("B", [1, 5])
 def test_zmarch_fixed_iterations(lib, ctx, dims, blocks, B):
-    """Passes A and B marching along z against the oracle's iterates (1e-10) and against
-    the chunked passes (summation order of the dots only: 1e-12)."""
+    """Passes A and B marching along z (tiles of 1024 nodes, and of 2048 with four nodes
+    per thread) against the oracle's iterates (1e-10) and against the chunked passes
+    (summation order of the dots only: 1e-12)."""
     op, prob, W, basis = _setup(lib, ctx, dims, blocks, 4, seed=60)
     AN, _ = orb.reduced_operators(op.A_q, [op.rhs()], W)
     theta = log_uniform_mu(61, B, op.Q, 0.1, 10.0)
     k = 7
     xz, sz = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="zmarch")
+    x4, s4 = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="zmarch4")
     xc, sc = lib.solve_batch(ctx, prob, basis, theta, fixed_iters=k, stencil="chunked")
-    xz, xc = xz.cpu().numpy(), xc.cpu().numpy()
+    xz, x4, xc = xz.cpu().numpy(), x4.cpu().numpy(), xc.cpu().numpy()
     for b in range(B):
         ref = orb.solve_rbcg(op, theta[b], W, AN, fixed_iters=k)
-        assert sz.iters[b] == k
+        assert sz.iters[b] == k and s4.iters[b] == k
         assert _rel(xz[b], ref.x) <= 1e-10, (b, _rel(xz[b], ref.x))
         assert _rel(xz[b], xc[b]) <= 1e-12, (b, _rel(xz[b], xc[b]))
+        # tiles twice as tall: the same products, partial sums over other tiles
+        assert _rel(x4[b], xc[b]) <= 1e-12, (b, _rel(x4[b], xc[b]))
 
 
 @pytest.mark.parametrize("dims,blocks,stencil", [((63, 63), (2, 2), "auto"),
