@@ -167,8 +167,9 @@ typedef struct {
                        plane in LDS (3D only; other grids use 1), 3 = as 2, with both
                        colours of a one-sweep Gauss-Seidel smoother in one launch marching
                        along z (3D grids with n[0] <= 255; else as 2), 4 = as 2, with the
-                       passes' tiles twice as tall (four nodes per thread, at most two
-                       queries per block).  Changes speed and summation order only. */
+                       tiles of the passes and sweeps twice as tall (four nodes or column
+                       pairs per thread, at most two queries per block).  Changes speed and
+                       summation order only. */
   double adapt_gamma; /* RBCG only.  > 0: adaptive basis size (Sec. 4.1, last
                          paragraph): query b starts with n_use[b] vectors (1 if n_use is
                          NULL) and uses one more (up to the basis size) for the next

@@ -173,6 +173,7 @@ struct TuneConfig {
   int kind_pro = 0;                      // batched prolongation: 0 default (MFMA), 1 MFMA,
                                          // 2 vector units
   int zn_a = 0, zn_b = 0;                // marching passes A / B: nodes per thread (0 = 2)
+  int np_gs = 0;                         // marching sweeps: column pairs per thread (0 = 2)
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

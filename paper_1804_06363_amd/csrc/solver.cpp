@@ -76,7 +76,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     if (opt.stencil_kind) {
       tc.kind_a = tc.kind_b = std::min(opt.stencil_kind, 2);
       tc.kind_gs = opt.stencil_kind == 4 ? 2 : opt.stencil_kind;
-      tc.zn_a = tc.zn_b = opt.stencil_kind == 4 ? 4 : 0;
+      tc.zn_a = tc.zn_b = tc.np_gs = opt.stencil_kind == 4 ? 4 : 0;
     }
     if (opt.prolong_kind) tc.kind_pro = opt.prolong_kind;
   }
@@ -581,13 +581,15 @@ void BatchSolver::autotune() {
       if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; best.zn_b = zn; }
     }
   }
-  for (int kind : {1, 2}) {  // chunked, marching (3D only)
+  for (int kp : {1, 2, 4}) {  // chunked, marching with 2 or 4 column pairs per thread (3D)
+    const int kind = kp == 1 ? 1 : 2, np = kp == 1 ? 0 : kp;
     if (kind == 2 && g.dim != 3) break;
     for (int c : caps) {
-      if (c > B || (kind == 2 && c > 4)) break;
+      if (c > B || (kind == 2 && c > 4) || (np == 4 && c > 2)) break;
       cur = best;
       cur.qpb_gs = c;
       cur.kind_gs = kind;
+      cur.np_gs = np;
       set_stencil_tiles(cur);
       const float t3 = timed([&] {
         if (gs_copy)
@@ -602,7 +604,7 @@ void BatchSolver::autotune() {
                                   r0.as<double>(), L_, nullptr, nullptr, L_, q.active,
                                   part_r0.as<double>(), nullptr, st);
       });
-      if (t3 < tg) { tg = t3; best.qpb_gs = c; best.kind_gs = kind; }
+      if (t3 < tg) { tg = t3; best.qpb_gs = c; best.kind_gs = kind; best.np_gs = np; }
     }
   }
   if (fused_ok) {  // both colours in one launch, against two single-colour sweeps

@@ -920,8 +920,9 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(StencilGeom g, int color,
 // the other node of the pair there, so they stay in registers.  Loads are issued ahead
 // as in the marching passes: the neighbour values of plane k+3 (two steps ahead), the
 // halo, rhs (and rhs2) of plane k+1.  Partial sums go to part[b * tiles + tile].
-constexpr int kGsPairs = 2;  // pairs per thread: tiles of up to 2 * 512 / (zc / 2) rows
-template <int QPB, typename TY, bool FLEX, typename RT = double>
+constexpr int kGsPairs = 2;  // pairs per thread by default: tiles of up to 2 * 512 / (zc / 2)
+                             // rows; 4 for tiles twice as tall
+template <int QPB, typename TY, bool FLEX, typename RT = double, int NP = kGsPairs>
 __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt, int color,
                                                          int B, const double* coef,
                                                          TY* __restrict__ y, int64_t y_ld,
@@ -934,7 +935,6 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
                                                          double* __restrict__ part0,
                                                          double* __restrict__ part1) {
   constexpr int NW = kZThreads / 64;
-  constexpr int NP = kGsPairs;
   extern __shared__ double dyn[];
   __shared__ double red[NW * QPB];
   const int tiles2 = zt.rt * zt.ct;
@@ -1749,13 +1749,13 @@ int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, c
 
 // Tile of the marching colour sweeps: an even number of columns (pairs per thread), at
 // most `cap` tiles per query (the partial sums the solver holds for one colour).
-static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt) {
+static bool zg_plan(const StencilGeom& g, int groups, int cap, ZTile& zt, int np = kGsPairs) {
   if (g.dim != 3) return false;
   // whole rows up to 255 columns (nx odd: the last column of the last tile is outside),
   // so that no halo column is read: a halo column costs one cache line per row
   zt.zc = std::min(g.nx + 1, 256);
   const int pairs = zt.zc / 2;
-  zt.zr = std::min(g.ny, kGsPairs * (kZThreads / pairs));
+  zt.zr = std::min(g.ny, np * (kZThreads / pairs));
   // one thread per pair of halo cells
   if (zt.zr < 1 || 2 * pairs + 2 * ((zt.zr + 1) / 2) > kZThreads) return false;
   zt.ct = (g.nx + zt.zc - 1) / zt.zc;
@@ -1779,27 +1779,36 @@ static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, con
                             TY* y, int64_t y_ld, const RT* rhs, int64_t rhs_ld,
                             const double* rhs_scale, const double* rhs2, int64_t rhs2_ld,
                             const int* active, double* part0, double* part1, hipStream_t s,
-                            int kind) {
+                            int kind, int np = kGsPairs) {
   if (kind != 2) return 0;
   qpb = std::min(qpb, 4);
+  if (np != 4 || qpb > 2) np = kGsPairs;  // four pairs per thread: up to two queries
   ZTile zt;
   const int groups = (B + qpb - 1) / qpb;
-  if (!zg_plan(g, groups, stencil_chunks(color ? g.N - g.NR : g.NR), zt)) return 0;
+  if (!zg_plan(g, groups, stencil_chunks(color ? g.N - g.NR : g.NR), zt, np)) return 0;
   const size_t lds = (size_t)qpb * (g.ct_size + (zt.zr + 2) * (zt.zc + 2)) * sizeof(TY) +
                      (size_t)3 * zt.kslab * sizeof(int);
   if (lds > 65536) return 0;
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const dim3 grid((unsigned)(tiles * groups));
-  auto go = [&](auto Q, auto F) {
-    hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value, RT>), grid, dim3(kZThreads), lds, s, g, zt,
-                       color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2, rhs2_ld, active,
-                       part0, part1);
+  auto go = [&](auto Q, auto F, auto NPc) {
+    hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value, RT, NPc.value>), grid, dim3(kZThreads),
+                       lds, s, g, zt, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2,
+                       rhs2_ld, active, part0, part1);
   };
+  using P2 = std::integral_constant<int, kGsPairs>;
+  using P4 = std::integral_constant<int, 4>;
   auto by_q = [&](auto F) {
     switch (qpb) {
-      case 4: go(std::integral_constant<int, 4>{}, F); break;
-      case 2: go(std::integral_constant<int, 2>{}, F); break;
-      default: go(std::integral_constant<int, 1>{}, F); break;
+      case 4: go(std::integral_constant<int, 4>{}, F, P2{}); break;
+      case 2:
+        if (np == 4) go(std::integral_constant<int, 2>{}, F, P4{});
+        else go(std::integral_constant<int, 2>{}, F, P2{});
+        break;
+      default:
+        if (np == 4) go(std::integral_constant<int, 1>{}, F, P4{});
+        else go(std::integral_constant<int, 1>{}, F, P2{});
+        break;
     }
   };
   if (rhs2)
@@ -1893,7 +1902,8 @@ int launch_gs_color(const StencilGeom& g, int color, int B, const double* coef, 
   const int qpb = pick_qpb(g, B, (int)sizeof(TY), t_tiles.qpb_gs ? t_tiles.qpb_gs : 4);
   if (const int t = launch_gs_zmarch<TY, RT>(g, color, qpb, B, coef, y, y_ld, rhs, rhs_ld,
                                              rhs_scale, rhs2, rhs2_ld, active, part0, part1, s,
-                                             t_tiles.kind_gs))
+                                             t_tiles.kind_gs,
+                                             t_tiles.np_gs ? t_tiles.np_gs : kGsPairs))
     return t;
   const int chunks = color ? stencil_sweep_chunks(g.NR, g.N) : stencil_sweep_chunks(0, g.NR);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {

@@ -26,7 +26,7 @@ void Tuner::put(const std::string& key, const TuneConfig& c) {
 
 // File format: one JSON object,
 // {"key": [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs, kind_pro, zn_a,
-// zn_b], ...} (the last six optional)
+// zn_b, np_gs], ...} (the last seven optional)
 void Tuner::load() {
   if (loaded) return;
   loaded = true;
@@ -48,10 +48,10 @@ void Tuner::load() {
     if (b == std::string::npos || l == std::string::npos || r == std::string::npos) break;
     TuneConfig c;
     const int got =
-        std::sscanf(t.c_str() + l + 1, "%d , %d , %d , %d , %d , %d , %d , %d , %d , %d",
+        std::sscanf(t.c_str() + l + 1, "%d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d",
                     &c.qpb_a, &c.qpb_b, &c.qpb_gs, &c.proj_target, &c.kind_a, &c.kind_b,
-                    &c.kind_gs, &c.kind_pro, &c.zn_a, &c.zn_b);
-    if (got == 4 || got == 6 || got == 7 || got == 8 || got == 10)
+                    &c.kind_gs, &c.kind_pro, &c.zn_a, &c.zn_b, &c.np_gs);
+    if (got == 4 || got == 6 || got == 7 || got == 8 || got == 10 || got == 11)
       put(t.substr(a + 1, b - a - 1), c);
     i = r + 1;
   }
@@ -66,7 +66,7 @@ void Tuner::save() const {
     const TuneConfig& c = table[i].second;
     f << "  \"" << table[i].first << "\": [" << c.qpb_a << ", " << c.qpb_b << ", " << c.qpb_gs
       << ", " << c.proj_target << ", " << c.kind_a << ", " << c.kind_b << ", " << c.kind_gs
-      << ", " << c.kind_pro << ", " << c.zn_a << ", " << c.zn_b << "]"
+      << ", " << c.kind_pro << ", " << c.zn_a << ", " << c.zn_b << ", " << c.np_gs << "]"
       << (i + 1 < table.size() ? "," : "") << "\n";
   }
   f << "}\n";

@@ -528,12 +528,14 @@ def test_fused_sweep_converged(lib, ctx, prec):
 
 
 @pytest.mark.parametrize("smoother", ["rbgs", "rbgs_sym"])
-def test_rbi_marching_sweep(lib, ctx, smoother):
+@pytest.mark.parametrize("dims", [(15, 13, 11), (127, 41, 5)])
+def test_rbi_marching_sweep(lib, ctx, smoother, dims):
     """RBI smooths A x = phi f from one shared row f scaled per query: the marching colour
-    sweep gives exactly the chunked sweep's iterates (the same update per node, and RBI
+    sweep (tiles of two or four column pairs per thread; on 127 x 41 rows 16 and 32 rows
+    tall) gives exactly the chunked sweep's iterates (the same update per node, and RBI
     takes no partial sums from its sweeps), and phi times the oracle's unscaled iterates
     (every step is linear in the right-hand side)."""
-    dims, blocks = (15, 13, 11), (2, 2, 2)
+    blocks = (2, 2, 2)
     op = BlockDiffusion(dims, blocks)
     W = _snapshot_basis(op, 4, seed=43)
     prob = lib.Problem(ctx, dims, blocks)
@@ -546,8 +548,11 @@ def test_rbi_marching_sweep(lib, ctx, smoother):
                             smoother=smoother, stencil="zmarch")
     xc, _ = lib.solve_batch(ctx, prob, basis, theta, phi=phi, solver="rbi", fixed_iters=m,
                             smoother=smoother, stencil="chunked")
-    xm, xc = xm.cpu().numpy(), xc.cpu().numpy()
+    x4, _ = lib.solve_batch(ctx, prob, basis, theta, phi=phi, solver="rbi", fixed_iters=m,
+                            smoother=smoother, stencil="zmarch4")
+    xm, xc, x4 = xm.cpu().numpy(), xc.cpu().numpy(), x4.cpu().numpy()
     assert np.array_equal(xm, xc)
+    assert np.array_equal(x4, xc)
     for b in range(5):
         xr, k, _ = orb.solve_rbi(op, theta[b], W, AN, m=m, rtol=0.0, smoother_kind=smoother)
         assert _rel(xm[b], phi[b] * xr) <= 1e-10
