@@ -65,7 +65,9 @@ def measured_traffic(workload, prec, B, kernel):
 def pass_b_kernel(cache_path, dim, N, B, n, prec):
     """Name of the kernel that ran pass B, from the tile choice the autotuner wrote to
     its cache file: {"arch|d<dim>|N<log2 N>|B<log2 B>|n<ceil(n/16)>|p<prec>|s<smoother>":
-    [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b], ...}."""
+    [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs, kind_pro, zn_a, zn_b,
+    np_gs], ...}; the marching pass B takes four nodes per thread (zn_b = 4) with at most
+    two queries per block, else two."""
     suffix = (f"|d{dim}|N{int(N).bit_length() - 1}|B{int(B).bit_length() - 1}"
               f"|n{(n + 15) // 16}|p{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[prec] }|s0")
     try:
@@ -77,7 +79,8 @@ def pass_b_kernel(cache_path, dim, N, B, n, prec):
         return "pass B (tiles unknown)"
     qpb_b, kind_b = tiles[0][1], tiles[0][5]
     if dim == 3 and kind_b == 2:
-        return f"k_zmarch<{qpb_b}, 1, double>"
+        zn = 4 if len(tiles[0]) >= 10 and tiles[0][9] == 4 and qpb_b <= 2 else 2
+        return f"k_zmarch<{qpb_b}, 1, double, {zn}>"
     return f"k_pass_b<{dim}, {qpb_b}>"
 
 
