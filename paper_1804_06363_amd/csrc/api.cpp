@@ -54,9 +54,16 @@ hipEvent_t Profiler::get() {
   return e;
 }
 void Profiler::resolve() {
+  // pairs whose launches are still in flight stay pending (their events are not reused)
+  std::vector<Pending> later;
   for (auto& p : pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    const hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e == hipErrorNotReady) {
+      later.push_back(p);
+      continue;
+    }
+    if (e == hipSuccess) {
       auto it = std::find_if(totals.begin(), totals.end(),
                              [&](const auto& t) { return t.first == p.name; });
       if (it == totals.end()) {
@@ -69,7 +76,7 @@ void Profiler::resolve() {
     pool.push_back(p.a);
     pool.push_back(p.b);
   }
-  pending.clear();
+  pending.swap(later);
 }
 Profiler::~Profiler() {
   for (auto& p : pending) {
@@ -826,10 +833,14 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       g.solver->start();
       g.running = true;
     }
+    // every group keeps one chunk of iterations queued while the host reads the flags of
+    // the chunk before it
+    for (auto& g : gs)
+      if (g.solver->more()) g.solver->issue(g.solver->chunk_);
     bool any = true;
     while (any) {
       for (auto& g : gs)
-        if (g.running) g.solver->issue(g.solver->chunk_);
+        if (g.running && g.solver->more()) g.solver->issue(g.solver->chunk_);
       any = false;
       for (auto& g : gs)
         if (g.running) {

@@ -152,7 +152,7 @@ struct Profiler {
   std::vector<std::pair<std::string, Total>> totals;
   hipEvent_t get();
   void record(const char* name, hipEvent_t a, hipEvent_t b) { pending.push_back({name, a, b}); }
-  void resolve();  // after the stream has been synchronised
+  void resolve();  // completed pairs (the others stay pending)
   ~Profiler();
 };
 }  // namespace rb

@@ -196,6 +196,10 @@ void BatchSolver::prepare() {
 
 BatchSolver::~BatchSolver() {
   if (graph) (void)hipGraphExecDestroy(graph);
+  for (int i = 0; i < 2; ++i) {
+    if (hev_[i]) (void)hipEventDestroy(hev_[i]);
+    if (hflags_[i]) (void)hipHostFree(hflags_[i]);
+  }
 }
 
 // Reduced assembly + Cholesky of every query (eq. 12b, Sec. 2.1).  A query whose
@@ -685,7 +689,11 @@ void BatchSolver::start() {
   k_ = 0;
   chunk_ = opt.check_every > 0 ? opt.check_every : (prob->g.N >= (1 << 18) ? 4 : 16);
   if (opt.use_graph && chunk_ % 2) ++chunk_;
-  act_.assign(B, 1);
+  for (int i = 0; i < 2; ++i) {
+    if (!hflags_[i]) RB_HIP(hipHostMalloc((void**)&hflags_[i], sizeof(int) * (size_t)std::max(B, 1)));
+    if (!hev_[i]) RB_HIP(hipEventCreateWithFlags(&hev_[i], hipEventDisableTiming));
+  }
+  issued_ = polled_ = 0;
   // RBI: iteration k checks the residual of the k-th iterate first; maxit + 1 checks
   limit_ = fixed_ ? opt.fixed_iters : (rbi_ ? opt.maxit + 1 : opt.maxit);
 }
@@ -718,23 +726,31 @@ void BatchSolver::issue(int iters) {
     else
       iterate_cg(k_);
   }
+  const int slot = issued_ % 2;
   if (!fixed_)
-    RB_HIP(hipMemcpyAsync(act_.data(), q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipMemcpyAsync(hflags_[slot], q.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  RB_HIP(hipEventRecord(hev_[slot], st));
+  kdone_[slot] = k_;
+  ++issued_;
 }
 
 bool BatchSolver::poll() {
-  RB_HIP(hipStreamSynchronize(s()));
+  if (polled_ == issued_) return false;
+  const int slot = polled_ % 2;
+  RB_HIP(hipEventSynchronize(hev_[slot]));
+  ++polled_;
   if (s() == ctx->stream) ctx->prof.resolve();
-  if (k_ >= limit_) return false;
+  if (kdone_[slot] >= limit_) return false;
   if (fixed_) return true;
   for (int i = 0; i < B; ++i)
-    if (act_[i]) return true;
+    if (hflags_[slot][i]) return true;
   return false;
 }
 
 void BatchSolver::finish() {
   hipStream_t st = s();
   RB_HIP(hipStreamSynchronize(st));
+  if (st == ctx->stream) ctx->prof.resolve();
   set_stencil_tiles(TuneConfig{});
   // queries still active after maxit did not converge
   if (!fixed_) {
@@ -757,8 +773,9 @@ void BatchSolver::finish() {
 
 void BatchSolver::run() {
   start();
+  if (more()) issue(chunk_);
   do {
-    issue(chunk_);
+    if (more()) issue(chunk_);  // queued before the previous chunk's flags are read
   } while (poll());
   finish();
 }

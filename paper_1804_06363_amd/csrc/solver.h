@@ -83,15 +83,25 @@ struct BatchSolver {
   // RBI
   void init_rbi();
   void iterate_rbi(int k);
-  // driver: run() = start(); while (issue(chunk), poll()); finish()
+  // driver: run() = start(); issue(chunk); while (issue(chunk) if iterations are left,
+  // poll()); finish().  One chunk runs while the host reads the previous one's flags.
   void run();
   void start();
   void issue(int iters);
-  bool poll();  // synchronises this solver's stream; true while queries are active
+  // waits for the oldest chunk in flight; true while its flags show active queries and
+  // iterations are left (false when no chunk is in flight)
+  bool poll();
+  bool more() const { return k_ < limit_; }  // iterations left to issue
   void finish();
   int k_ = 0, limit_ = 0, chunk_ = 0;
   bool fixed_ = false, rbi_ = false;
-  std::vector<int> act_;
+  // Chunks of iterations in flight (at most two): each issue() copies the active flags
+  // after its chunk into its own pinned host buffer and records an event, so the host
+  // queues the next chunk before it looks at the previous one's flags.
+  int* hflags_[2] = {nullptr, nullptr};
+  hipEvent_t hev_[2] = {nullptr, nullptr};
+  int kdone_[2] = {0, 0};  // k_ at the end of each chunk in flight
+  int issued_ = 0, polled_ = 0;
   void final_true_residual();
   void gather(double* x_user_nat, int64_t user_ld, std::vector<rb_query_stats>& stats);
   void factor();
