@@ -833,14 +833,12 @@ rb_status rb_solve_multi(rb_ctx* ctx, int nprob, const rb_problem* const* probs,
       g.solver->start();
       g.running = true;
     }
-    // every group keeps one chunk of iterations queued while the host reads the flags of
-    // the chunk before it
-    for (auto& g : gs)
-      if (g.solver->more()) g.solver->issue(g.solver->chunk_);
+    // each group issues its chunks (on large grids one more while the host reads the
+    // flags of the chunk before it), then the host reads every running group's flags
     bool any = true;
     while (any) {
       for (auto& g : gs)
-        if (g.running && g.solver->more()) g.solver->issue(g.solver->chunk_);
+        if (g.running) g.solver->fill();
       any = false;
       for (auto& g : gs)
         if (g.running) {

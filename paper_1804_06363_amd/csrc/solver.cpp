@@ -688,6 +688,10 @@ void BatchSolver::start() {
   fixed_ = opt.fixed_iters > 0;
   k_ = 0;
   chunk_ = opt.check_every > 0 ? opt.check_every : (prob->g.N >= (1 << 18) ? 4 : 16);
+  // A second chunk in flight hides the host's read of the flags behind GPU work, at the
+  // price of one chunk of near-empty launches after the last query retires: worth it on
+  // large grids (a chunk takes milliseconds), not on small ones where launches dominate.
+  depth_ = prob->g.N >= (1 << 18) ? 2 : 1;
   if (opt.use_graph && chunk_ % 2) ++chunk_;
   for (int i = 0; i < 2; ++i) {
     if (!hflags_[i]) RB_HIP(hipHostMalloc((void**)&hflags_[i], sizeof(int) * (size_t)std::max(B, 1)));
@@ -771,12 +775,14 @@ void BatchSolver::finish() {
   }
 }
 
+void BatchSolver::fill() {
+  while (more() && issued_ - polled_ < depth_) issue(chunk_);
+}
+
 void BatchSolver::run() {
   start();
-  if (more()) issue(chunk_);
-  do {
-    if (more()) issue(chunk_);  // queued before the previous chunk's flags are read
-  } while (poll());
+  do fill();
+  while (poll());
   finish();
 }
 

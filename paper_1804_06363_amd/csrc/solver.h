@@ -83,19 +83,20 @@ struct BatchSolver {
   // RBI
   void init_rbi();
   void iterate_rbi(int k);
-  // driver: run() = start(); issue(chunk); while (issue(chunk) if iterations are left,
-  // poll()); finish().  One chunk runs while the host reads the previous one's flags.
+  // driver: run() = start(); do fill(); while (poll()); finish().  On large grids one
+  // chunk runs while the host reads the previous one's flags.
   void run();
   void start();
   void issue(int iters);
+  void fill();  // issues chunks until depth_ are in flight or no iterations are left
   // waits for the oldest chunk in flight; true while its flags show active queries and
   // iterations are left (false when no chunk is in flight)
   bool poll();
   bool more() const { return k_ < limit_; }  // iterations left to issue
   void finish();
-  int k_ = 0, limit_ = 0, chunk_ = 0;
+  int k_ = 0, limit_ = 0, chunk_ = 0, depth_ = 1;
   bool fixed_ = false, rbi_ = false;
-  // Chunks of iterations in flight (at most two): each issue() copies the active flags
+  // Chunks of iterations in flight (at most depth_ <= 2): each issue() copies the active flags
   // after its chunk into its own pinned host buffer and records an event, so the host
   // queues the next chunk before it looks at the previous one's flags.
   int* hflags_[2] = {nullptr, nullptr};
