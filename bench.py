@@ -62,12 +62,14 @@ def measured_traffic(workload, prec, B, kernel):
     return int(m.group(1))
 
 
-def pass_b_kernel(cache_path, dim, N, B, n, prec):
+def pass_b_kernel(cache_path, dim, N, B, n, prec, paired=True):
     """Name of the kernel that ran pass B, from the tile choice the autotuner wrote to
     its cache file: {"arch|d<dim>|N<log2 N>|B<log2 B>|n<ceil(n/16)>|p<prec>|s<smoother>":
     [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs, kind_pro, zn_a, zn_b,
     np_gs], ...}; the marching pass B takes four nodes per thread (zn_b = 4) with at most
-    two queries per block, else two."""
+    two queries per block, else two.  The last template argument is the update of x: 0
+    every iteration; with paired updates 1 (none, even iterations) and 2 (two updates, odd
+    iterations) alternate, and the name gives both."""
     suffix = (f"|d{dim}|N{int(N).bit_length() - 1}|B{int(B).bit_length() - 1}"
               f"|n{(n + 15) // 16}|p{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[prec] }|s0")
     try:
@@ -80,8 +82,10 @@ def pass_b_kernel(cache_path, dim, N, B, n, prec):
     qpb_b, kind_b = tiles[0][1], tiles[0][5]
     if dim == 3 and kind_b == 2:
         zn = 4 if len(tiles[0]) >= 10 and tiles[0][9] == 4 and qpb_b <= 2 else 2
-        return f"k_zmarch<{qpb_b}, 1, double, {zn}>"
-    return f"k_pass_b<{dim}, {qpb_b}>"
+        stem = f"k_zmarch<{qpb_b}, 1, double, {zn}, "
+    else:
+        stem = f"k_pass_b<{dim}, {qpb_b}, "
+    return f"{stem}1> / {stem}2>" if paired else f"{stem}0>"
 
 
 def log(*a):
@@ -104,6 +108,9 @@ def main():
     ap.add_argument("--residual-copy", type=int, default=1,
                     help="keep an FP32 copy of r for the projection and the sweeps without dot "
                          "products (FP32 / BF16 preconditioner; same results, fewer bytes)")
+    ap.add_argument("--paired-x", type=int, default=1,
+                    help="pass B updates x every second iteration, for two iterations (same "
+                         "results, fewer bytes)")
     ap.add_argument("--uneven-sweeps", type=int, default=8,
                     help="Gauss-Seidel sweeps per preconditioner application in the uneven batch "
                          "(4 -> 90.7, 6 -> 111.0, 8 -> 113.2, 10 -> 113.9 mu-solves/s)")
@@ -191,12 +198,13 @@ def main():
     test = w.test_mu(B)
     x = torch.empty((B, N), dtype=torch.float64, device="cuda:0")
     opts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
-                         sweeps=args.sweeps, residual_copy=bool(args.residual_copy))
+                         sweeps=args.sweeps, residual_copy=bool(args.residual_copy),
+                         paired_x=bool(args.paired_x))
 
     # warm-up solves autotune the batched kernels' tiles (kept in the context)
     wopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=bool(args.graph),
                           autotune=True, sweeps=args.sweeps,
-                          residual_copy=bool(args.residual_copy))
+                          residual_copy=bool(args.residual_copy), paired_x=bool(args.paired_x))
     for i in range(args.warmup):
         _, st = rb.solve_batch(ctx, prob, basis, test, x=x, opts=wopts)
         log(f"warmup {i}: iters mean {st.iters.mean():.1f} max {st.iters.max()} "
@@ -206,6 +214,7 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter()
     iters_total = 0
+    odd_total = 0  # odd iterations (k = 1, 3, ...) summed over the queries
     conv = 0
     stats = []
     step_s = []
@@ -216,6 +225,7 @@ def main():
         stats.append(st)
         conv += int(((st.status == rb.RB_OK) & (st.rel_res_true <= 1e-10)).sum())
         iters_total += int(st.iters.sum())
+        odd_total += int((st.iters // 2).sum())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ctx.profile(False)
@@ -227,13 +237,18 @@ def main():
     for k, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
         log(f"  {k:14s} {ms:9.2f} ms  {n:6d} launches  {ms / max(n, 1) * 1e3:9.1f} us/launch")
 
-    # roofline of the dominant kernel: pass B reads x, p, r and writes x, r (FP64) for
-    # every active query, and the FP32 copy of r with an FP32 / BF16 preconditioner: 40
-    # (44) algorithmic bytes per DOF per active query-iteration
+    # roofline of the dominant kernel: pass B reads p, r and writes r (FP64) for every
+    # active query, and the FP32 copy of r with an FP32 / BF16 preconditioner: 24 (28)
+    # algorithmic bytes per DOF per active query-iteration; the update of x reads and
+    # writes x, 16 more in every iteration, or with paired updates 24 more (x and the
+    # previous direction read, x written) in odd iterations only: 40 (44), or 36 (40) on
+    # average
     copy = bool(args.residual_copy) and args.prec != "fp64"
+    paired = bool(args.paired_x)
     ms_b, n_b = prof.get("pass_b", (0.0, 0))
-    bytes_b = (44.0 if copy else 40.0) * N * iters_total
-    kernel_b = pass_b_kernel(tune_cache, len(w.dims), N, B, basis.n, args.prec)
+    bytes_b = (28.0 if copy else 24.0) * N * iters_total + \
+        (24.0 * N * odd_total if paired else 16.0 * N * iters_total)
+    kernel_b = pass_b_kernel(tune_cache, len(w.dims), N, B, basis.n, args.prec, paired)
     if args.graph:  # graph replays record no per-kernel events
         roofline = {"kernel": kernel_b, "bound": "hbm", "achieved": None,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
@@ -268,7 +283,8 @@ def main():
     graph_leg = None
     if args.graph_leg and not args.graph:
         gopts = rb.solve_opts(prec=args.prec, flexible=bool(args.flexible), graph=True,
-                              sweeps=args.sweeps, residual_copy=bool(args.residual_copy))
+                              sweeps=args.sweeps, residual_copy=bool(args.residual_copy),
+                              paired_x=bool(args.paired_x))
         rb.solve_batch(ctx, prob, basis, test, x=x, opts=gopts)  # capture
         torch.cuda.synchronize()
         tg = time.perf_counter()
@@ -357,7 +373,7 @@ def main():
                    "N": N, "B": B, "n": basis.n, "Q": Q, "prec": args.prec,
                    "beta": "flexible" if args.flexible else "literal",
                    "smoother": f"red-black Gauss-Seidel x{args.sweeps}",
-                   "residual_copy": copy,
+                   "residual_copy": copy, "paired_x_update": paired,
                    "graph": bool(args.graph), "parallelism": "single-gpu"},
         "step_ms": [round(v * 1e3, 2) for v in step_s],
         "median_step_ms": round(float(np.median(step_s)) * 1e3, 2),

@@ -197,6 +197,13 @@ typedef struct {
                          BF16 preconditioner: 0 = autotuned / default (MFMA tiles), 1 = MFMA
                          tiles, 2 = vector units (one node per thread, FP32 FMAs).  Changes
                          speed and summation order only. */
+  int paired_x_update; /* RBCG and CG on a stencil problem: 1 (default) = the iterate's update
+                          x += alpha_k p_k (Alg. 3) of an even iteration k is applied with the
+                          next one's, x = (x + alpha_k p_k) + alpha_k+1 p_k+1, in one read and
+                          write of x (or at the true-residual check or the end, if they come
+                          first): the same operations in the same order, so the same results
+                          bit for bit, from fewer bytes moved; 0 = every iteration.  Ignored
+                          elsewhere. */
 } rb_solve_opts;
 void rb_solve_opts_default(rb_solve_opts* opts);
 

@@ -137,6 +137,7 @@ void rb_solve_opts_default(rb_solve_opts* o) {
   o->rtol = 1e-10;
   o->maxit = 2000;
   o->residual_copy = 1;
+  o->paired_x_update = 1;
 }
 
 rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx** out) {
@@ -686,6 +687,8 @@ static void check_opts(const rb_solve_opts* o) {
              "residual_copy must be 0 or 1");
   RB_REQUIRE(o->prolong_kind >= 0 && o->prolong_kind <= 2, RB_EINVAL,
              "prolong_kind must be 0, 1 or 2");
+  RB_REQUIRE(o->paired_x_update == 0 || o->paired_x_update == 1, RB_EINVAL,
+             "paired_x_update must be 0 or 1");
   RB_REQUIRE(std::isfinite(o->floor_factor) && o->floor_factor >= 0.0, RB_EINVAL,
              "bad floor_factor");
   RB_REQUIRE(o->smooth_sweeps <= 1 || o->smoother == RB_SMOOTH_RBGS ||

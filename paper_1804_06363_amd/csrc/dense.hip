@@ -1120,12 +1120,15 @@ __global__ __launch_bounds__(256) void k_fin_alpha(const double* __restrict__ pa
 // Alg. 3, stopping test on the recursive residual; flags the query for the true-residual check
 __global__ __launch_bounds__(256) void k_fin_rr(const double* __restrict__ part, int stride,
                                                 int cnt, QState q, double rtol, int maxit,
-                                                int fixed) {
+                                                int fixed, int defer) {
   __shared__ double sh[4];
   const int b = blockIdx.x;
   if (!q.active[b]) return;
   const double rr = sum_parts(part + (size_t)b * stride, cnt, sh);
   if (threadIdx.x == 0) {
+    // an even iteration's x update waits for the next pass B (or a fold); an odd one's
+    // pass B applied it
+    if (q.apend) q.apend[b] = defer ? q.alpha[b] : 0.0;
     const int it = q.iters[b] + 1;
     q.iters[b] = it;
     const double rel = sqrt(rr / q.fnorm2[b]);
@@ -1172,6 +1175,7 @@ __global__ __launch_bounds__(256) void k_fin_true(const double* __restrict__ par
     if (q.stalls) q.stalls[b] = run;
     q.rel_true[b] = rel;
     q.flag[b] = 0;
+    if (q.apend) q.apend[b] = 0.0;  // the fold before this check applied it
     if (rel <= rtol || (part2 && run >= 2 && rel <= lvl)) {
       q.active[b] = 0;
       q.status[b] = RB_OK;
@@ -1231,9 +1235,9 @@ void launch_fin_alpha(const double* part, int stride, int cnt, const QState& q, 
   hipLaunchKernelGGL(k_fin_alpha, dim3(B), dim3(256), 0, s, part, stride, cnt, q);
 }
 void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
-                   int maxit, bool fixed, hipStream_t s) {
+                   int maxit, bool fixed, hipStream_t s, bool defer) {
   hipLaunchKernelGGL(k_fin_rr, dim3(B), dim3(256), 0, s, part, stride, cnt, q, rtol, maxit,
-                     fixed ? 1 : 0);
+                     fixed ? 1 : 0, defer ? 1 : 0);
 }
 void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
                      int maxit, hipStream_t s, const double* part2, double floor_factor) {
@@ -1254,29 +1258,45 @@ void launch_fin_sum(const double* part, int stride, int cnt, double* out, const 
 // Rows are ld (a multiple of 64) doubles; padding is zero in both vectors.  Every block
 // takes a slice of every flagged row (few rows are flagged at a time: each query reaches
 // its true-residual check once or twice), so a flagged row is folded by the whole grid.
+// A pending update (apend[b] != 0, direction p_b) joins the correction first, as pass B
+// would have added it: x_b += (xc_b + apend[b] p_b).
 __global__ __launch_bounds__(256) void k_fold(const int* __restrict__ flag, int B,
                                               double2* __restrict__ x, double2* __restrict__ xc,
-                                              int64_t ld2, int64_t slice) {
+                                              int64_t ld2, int64_t slice,
+                                              const double* __restrict__ apend,
+                                              const double2* __restrict__ p) {
   const int64_t i0 = (int64_t)blockIdx.x * slice;
   const int64_t i1 = i0 + slice < ld2 ? i0 + slice : ld2;
   for (int b = 0; b < B; ++b) {
     if (flag && !flag[b]) continue;  // uniform across the block
     double2* xb = x + (size_t)b * ld2;
     double2* cb = xc + (size_t)b * ld2;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      const double2 a = xb[i], c = cb[i];
-      xb[i] = make_double2(a.x + c.x, a.y + c.y);
-      cb[i] = make_double2(0.0, 0.0);
+    const double ap = apend ? apend[b] : 0.0;
+    if (ap != 0.0) {
+      const double2* pb = p + (size_t)b * ld2;
+      for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const double2 a = xb[i], c = cb[i], v = pb[i];
+        xb[i] = make_double2(a.x + (c.x + ap * v.x), a.y + (c.y + ap * v.y));
+        cb[i] = make_double2(0.0, 0.0);
+      }
+    } else {
+      for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const double2 a = xb[i], c = cb[i];
+        xb[i] = make_double2(a.x + c.x, a.y + c.y);
+        cb[i] = make_double2(0.0, 0.0);
+      }
     }
   }
 }
-void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s) {
+void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s,
+                 const double* apend, const double* p) {
   if (B <= 0) return;
+  RB_REQUIRE(!apend || p, RB_EINVAL, "fold: a pending update needs its direction");
   const int64_t ld2 = ld / 2;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (ld2 + 255) / 256));
   const int64_t slice = (ld2 + blocks - 1) / blocks;
   hipLaunchKernelGGL(k_fold, dim3(blocks), dim3(256), 0, s, flag, B, (double2*)x, (double2*)xc,
-                     ld2, slice);
+                     ld2, slice, apend, (const double2*)p);
 }
 
 // dst[b][pos] = value for pos < n (fill kernel; graph-safe replacement for memset)

@@ -32,6 +32,10 @@ struct QState {
   int nmax = 0;
   int* at_floor = nullptr;  // accepted at the rounding level (floor test on)
   int* stalls = nullptr;    // true-residual checks in a row that gained less than half
+  // paired x updates: alpha of an even iteration whose x update is still to be applied
+  // (with that iteration's direction), 0 once applied; null when x is updated every
+  // iteration
+  double* apend = nullptr;
 };
 
 // Segments of a partial-sum buffer written by successive colour sweeps.
@@ -76,18 +80,23 @@ void launch_apply(const StencilGeom& g, int64_t ld, int B, const double* coef, c
                   const int* flag, double* part, hipStream_t s, double* part2 = nullptr,
                   float* y32 = nullptr);
 // x_b += xc_b, xc_b = 0 for the queries with flag[b] != 0 (all of them if flag is null),
-// over the ld entries of each row
-void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s);
+// over the ld entries of each row.  apend (nullable): an x update still to be applied,
+// x_b += (xc_b + apend[b] p_b), for the queries with apend[b] != 0 (p rows of ld).
+void launch_fold(const int* flag, int B, double* x, double* xc, int64_t ld, hipStream_t s,
+                 const double* apend = nullptr, const double* p = nullptr);
 // passes A and B return the number of partial sums per query they wrote (at most
 // stencil_chunks_all(N); row stride stays stencil_chunks_all(N) in the solver's arrays)
 template <typename TY>
 int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                   const int* active, double* part, hipStream_t s);
-// r32 (nullable, stencil grids): pass B also writes an FP32 copy of r_out (rows of ld)
+// r32 (nullable, stencil grids): pass B also writes an FP32 copy of r_out (rows of ld).
+// xd (stencil grids): the update of x, 0 x += alpha p, 1 none (deferred to the next
+// iteration), 2 x = (x + a_prev p_prev) + alpha p (the deferred update first).
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
-                  const int* active, double* part, hipStream_t s, float* r32 = nullptr);
+                  const int* active, double* part, hipStream_t s, float* r32 = nullptr,
+                  int xd = 0, const double* p_prev = nullptr, const double* a_prev = nullptr);
 // returns the number of partial sums per query it wrote (row stride of part0 / part1;
 // at most stencil_chunks of the colour's node count).  RT = float (TY = float, stencil
 // grids): rhs is an FP32 copy of the right-hand side; the same y, since the update rounds
@@ -177,8 +186,10 @@ void launch_reduce_solve(bool fp64_part, const void* part, int chunks, int B, in
                          double* e64, float* e32, int e_ld, bool solve, hipStream_t s);
 void launch_fin_alpha(const double* part, int stride, int cnt, const QState& q, int B,
                       hipStream_t s);
+// defer: pass B left this iteration's x update to the next one; q.apend (if set) then
+// takes alpha of the queries active in it, else 0
 void launch_fin_rr(const double* part, int stride, int cnt, const QState& q, int B, double rtol,
-                   int maxit, bool fixed, hipStream_t s);
+                   int maxit, bool fixed, hipStream_t s, bool defer = false);
 // part2 (nullable): partial sums of (|A||x|)^2; floor_factor > 0 also accepts residuals
 // within floor_factor * eps * || |A||x| || (at_floor)
 void launch_fin_true(const double* part, int stride, int cnt, const QState& q, int B, double rtol,

@@ -106,6 +106,7 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
   x = get_ws(WS_X, vb);
   r0 = get_ws(WS_R0, vr);
   use_r32 = y32 && opt.residual_copy && opt.solver == RB_SOLVER_RBCG && !g.csr;
+  pair_x = opt.paired_x_update && opt.solver != RB_SOLVER_RBI && !g.csr;
   if (use_r32) r32 = get_ws(WS_R32, sizeof(float) * (size_t)rrows * L_);
   if (opt.beta_flexible || opt.smoother == RB_SMOOTH_JACOBI || opt.smoother == RB_SMOOTH_NONE)
     r1 = get_ws(WS_R1, vr);
@@ -138,12 +139,13 @@ BatchSolver::BatchSolver(rb_ctx* c, const rb_problem* p, const rb_basis* b,
     e32 = get_ws(WS_E32, sizeof(float) * (size_t)Bp * e_ld);
     qlist = get_ws(WS_QLIST, sizeof(int) * ((size_t)B + 1));
   }
-  qbuf = get_ws(WS_Q, (sizeof(double) * 8 + sizeof(int) * 7) * (size_t)B);
+  qbuf = get_ws(WS_Q, (sizeof(double) * 9 + sizeof(int) * 7) * (size_t)B);
   char* qb = qbuf.as<char>();
   auto takeD = [&](double*& d) { d = (double*)qb; qb += sizeof(double) * B; };
   auto takeI = [&](int*& d) { d = (int*)qb; qb += sizeof(int) * B; };
   takeD(q.fnorm2); takeD(q.rho); takeD(q.alpha); takeD(q.beta); takeD(q.rel_rec);
-  takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in);
+  takeD(q.rel_true); takeD(q.scalar); takeD(q.rr_in); takeD(q.apend);
+  if (!pair_x) q.apend = nullptr;
   takeI(q.active); takeI(q.status); takeI(q.iters); takeI(q.flag); takeI(q.restart);
   takeI(q.at_floor);
   takeI(q.stalls);
@@ -186,7 +188,7 @@ void BatchSolver::prepare() {
     launch_fill<double>(e64.as<double>(), 0, (int64_t)Bp * e_ld, 1, 0.0, st);
     launch_fill<float>(e32.as<float>(), 0, (int64_t)Bp * e_ld, 1, 0.f, st);
   }
-  launch_fill<double>(q.fnorm2, 0, 8 * (int64_t)B, 1, 0.0, st);
+  launch_fill<double>(q.fnorm2, 0, 9 * (int64_t)B, 1, 0.0, st);  // through apend
   launch_fill<int>(q.at_floor, 0, (int64_t)B, 1, 0, st);
   launch_fill<int>(q.stalls, 0, (int64_t)B, 1, 0, st);
   launch_fill<int>(q.status, 0, (int64_t)B, 1, (int)RB_OK, st);
@@ -384,11 +386,17 @@ void BatchSolver::iterate_cg(int k) {
                                  q.beta, q.active, part_m.as<double>(), st);
   }
   launch_fin_alpha(part_m.as<double>(), cN, ca, q, B, st);
-  // x += alpha p (into the correction xc), r -= alpha A p
+  // x += alpha p (into the correction xc), r -= alpha A p.  Paired updates: an even
+  // iteration leaves its x update to the next one, whose pass B reads and writes x once
+  // for both, (x + alpha_k p_k) + alpha_k+1 p_k+1, the same operations in the same order;
+  // the pending alpha sits in q.apend and its direction in p1 (the new direction of every
+  // even iteration), which a fold before the next pass B applies instead.
+  const bool defer = pair_x && !(k & 1);
   {
     ProfScope ps(ctx, "pass_b", st);
     cb = launch_pass_b(g, L_, B, coef.as<double>(), pnew, xc.as<double>(), rin, rout, q.alpha,
-                       q.active, part_m.as<double>(), st, rc);
+                       q.active, part_m.as<double>(), st, rc, !pair_x ? 0 : defer ? 1 : 2,
+                       pold, q.apend);
   }
   // stopping test: recursive, then the true residual of the flagged queries, formed from x
   // after the correction accumulated since the previous check is folded into it.  The
@@ -397,9 +405,9 @@ void BatchSolver::iterate_cg(int k) {
   // residual replacement is not undone by the rounding of the next cycle's updates
   // (group-wise updating, van der Vorst and Ye 2000).
   const bool fixed = opt.fixed_iters > 0;
-  launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st);
+  launch_fin_rr(part_m.as<double>(), cN, cb, q, B, opt.rtol, opt.maxit, fixed, st, defer);
   if (!fixed) {
-    launch_fold(q.flag, B, x.as<double>(), xc.as<double>(), L_, st);
+    launch_fold(q.flag, B, x.as<double>(), xc.as<double>(), L_, st, q.apend, p1.as<double>());
     ProfScope ps(ctx, "true_residual", st);
     double* p2 = opt.floor_factor > 0.0 ? part_m2.as<double>() : nullptr;
     launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), rout, 1, f_base, f_ld,
@@ -508,7 +516,11 @@ void BatchSolver::final_true_residual() {
   const StencilGeom& g = prob->g;
   const int64_t L_ = ld();
   hipStream_t st = s();
-  if (xc.p) launch_fold(nullptr, B, x.as<double>(), xc.as<double>(), L_, st);
+  // with paired updates, the last even iteration's of the queries still running, and of
+  // those that stopped after one (maxit, breakdown), is still pending
+  if (xc.p) launch_fold(nullptr, B, x.as<double>(), xc.as<double>(), L_, st, q.apend,
+                        p1.as<double>());
+  if (q.apend) launch_fill<double>(q.apend, 0, B, 1, 0.0, st);
   double* tmp = r0.as<double>();
   launch_apply(g, L_, B, coef.as<double>(), x.as<double>(), tmp, 1, f_base, f_ld,
                scale_d.as<double>(), ones_d.as<int>(), part_m.as<double>(), st);
@@ -577,10 +589,13 @@ void BatchSolver::autotune() {
       cur.kind_b = kind;
       cur.zn_b = zn;
       set_stencil_tiles(cur);
+      // with paired x updates, the pass B of an even iteration and that of an odd one
       const float t2 = timed([&] {
-        launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
-                      r0.as<double>(), r0.as<double>(), q.alpha, q.active, part_m.as<double>(),
-                      st, rc);
+        for (int xd : {pair_x ? 1 : 0, pair_x ? 2 : -1})
+          if (xd >= 0)
+            launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
+                          r0.as<double>(), r0.as<double>(), q.alpha, q.active,
+                          part_m.as<double>(), st, rc, xd, p0.as<double>(), q.alpha);
       });
       if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; best.zn_b = zn; }
     }

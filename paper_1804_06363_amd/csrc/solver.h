@@ -41,6 +41,7 @@ struct BatchSolver {
   // RBCG with y in FP32 on stencil grids: an FP32 copy of the current r (same rows as r0),
   // written wherever r is; read by the projection and the sweeps without dot products
   bool use_r32 = false;
+  bool pair_x = false;  // pass B updates x every second iteration, for two iterations
   Buf r32;
   // fused red-black sweep (3D grids with nx <= 255, one forward sweep): the coarse
   // correction goes to zs (black half) and one launch writes y from it

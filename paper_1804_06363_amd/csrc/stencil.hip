@@ -431,8 +431,9 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(StencilGeom g, int64_t ld, 
 }
 
 // ---- pass B: x += alpha p; r_out = r_in - alpha A p; partial ||r_out||^2 ----------------
-// r32 (nullable): an FP32 copy of r_out, rows of ld.
-template <int DIM, int QPB>
+// r32 (nullable): an FP32 copy of r_out, rows of ld.  XD: the update of x, 0 as above,
+// 1 none (deferred to the next iteration), 2 x = (x + a_prev p_prev) + alpha p.
+template <int DIM, int QPB, int XD = 0>
 __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, int B, int chunks,
                                                      const double* coef,
                                                      const double* __restrict__ p,
@@ -441,18 +442,21 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
                                                      const double* __restrict__ alpha,
                                                      const int* __restrict__ active,
                                                      double* __restrict__ part,
-                                                     float* __restrict__ r32) {
+                                                     float* __restrict__ r32,
+                                                     const double* __restrict__ p_prev,
+                                                     const double* __restrict__ a_prev) {
   extern __shared__ double dyn[];
   __shared__ double red[4 * QPB];
   const Tile tl = tile_of(chunks);
   const int q0 = tl.q0 * QPB;
   const unsigned mask = load_group<QPB>(g, coef, q0, B, active, dyn);
   if (!mask) return;
-  double acc[QPB], al[QPB];
+  double acc[QPB], al[QPB], ap[QPB];
 #pragma unroll
   for (int k = 0; k < QPB; ++k) {
     acc[k] = 0.0;
     al[k] = ((mask >> k) & 1u) ? alpha[q0 + k] : 0.0;
+    ap[k] = (XD == 2 && ((mask >> k) & 1u)) ? a_prev[q0 + k] : 0.0;
   }
 #pragma unroll
   for (int t = 0; t < 2 * kPH; ++t) {
@@ -472,7 +476,9 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(StencilGeom g, int64_t ld, 
         double d;
         const double q = apply_at<DIM, double>(
             n, cf, pp, [&](int s) { return at_byte(pb, (uint32_t)s * 8u); }, d);
-        at_byte(x + o, bp) += al[k] * pp;
+        if (XD == 0) at_byte(x + o, bp) += al[k] * pp;
+        if (XD == 2)
+          at_byte(x + o, bp) = (at_byte(x + o, bp) + ap[k] * at_byte(p_prev + o, bp)) + al[k] * pp;
         const double r = at_byte(r_in + o, bp) - al[k] * q;
         at_byte(r_out + o, bp) = r;
         if (r32) at_byte(r32 + o, (uint32_t)pos * 4u) = (float)r;
@@ -511,7 +517,7 @@ struct ZTile {
 constexpr int kZThreads = 512;
 constexpr int kZNodes = 2;  // own nodes per thread by default (zr * zc <= 1024); 4 for taller tiles
 
-template <int QPB, int MODE, typename TY, int ZN>
+template <int QPB, int MODE, typename TY, int ZN, int XD = 0>
 __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, int64_t ld, int B,
                                                       const double* coef,
                                                       const TY* __restrict__ y, int64_t y_ld,
@@ -522,10 +528,14 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
                                                       const double* __restrict__ scal,
                                                       const int* __restrict__ active,
                                                       double* __restrict__ part, int pstride,
-                                                      float* __restrict__ r32) {
+                                                      float* __restrict__ r32,
+                                                      const double* __restrict__ p_prev,
+                                                      const double* __restrict__ a_prev) {
   // MODE 0 (pass A): v = y + beta p_in, p_out = v, partial v^T A v.
   // MODE 1 (pass B): v = p_in, x += alpha v, r_out = r_in - alpha A v, partial ||r_out||^2,
-  // and the FP32 copy r32 of r_out (rows of ld) unless r32 is null.
+  // and the FP32 copy r32 of r_out (rows of ld) unless r32 is null.  XD (pass B) is the
+  // update of x: 0 as above, 1 none (deferred to the next iteration), 2 the deferred one
+  // first, x = (x + a_prev p_prev) + alpha v, the two updates in their original order.
   constexpr int NW = kZThreads / 64;
   extern __shared__ double dyn[];
   __shared__ double red[NW * QPB];
@@ -547,9 +557,12 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   const int k1 = min(g.nz, k0 + zt.kslab);
   const int P = g.nxy;
 
-  double sc[QPB];
+  double sc[QPB], ap[QPB];
 #pragma unroll
-  for (int q = 0; q < QPB; ++q) sc[q] = ((mask >> q) & 1u) ? scal[q0 + q] : 0.0;
+  for (int q = 0; q < QPB; ++q) {
+    sc[q] = ((mask >> q) & 1u) ? scal[q0 + q] : 0.0;
+    ap[q] = (XD == 2 && ((mask >> q) & 1u)) ? a_prev[q0 + q] : 0.0;
+  }
 
   // own nodes: in-plane offset m, LDS slot, x/y coefficient bases, boundary bits
   int m_[ZN], slot[ZN], cb[ZN][4], zxy[ZN];
@@ -603,10 +616,12 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   const double* rq[QPB];
   double* oq[QPB];   // p_out (pass A) or r_out (pass B)
   float* sq[QPB];    // r32 (pass B)
+  const double* vq[QPB];  // p_prev (pass B, XD = 2)
 #pragma unroll
   for (int q = 0; q < QPB; ++q) {
     const size_t b = (size_t)min(q0 + q, B - 1);
     sq[q] = (MODE == 1 && r32) ? r32 + b * ld : nullptr;
+    vq[q] = (MODE == 1 && XD == 2) ? p_prev + b * ld : nullptr;
     pq[q] = p_in + b * ld;
     yq[q] = MODE == 0 ? y + b * y_ld : nullptr;
     xq[q] = MODE == 1 ? x + b * ld : nullptr;
@@ -627,7 +642,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     TY y[QPB];
   };
   struct XR {
-    double x[ZN][QPB], r[ZN][QPB];
+    double x[ZN][QPB], r[ZN][QPB], v[ZN][QPB];  // v: p_prev (XD = 2)
   };
   auto load_raw = [&](Raw& r, int k) {
 #pragma unroll
@@ -662,8 +677,9 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       const uint32_t pos = (uint32_t)spos(k * P + m_[s]);
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
-        t.x[s][q] = at_byte(xq[q], pos * 8u);
+        if (XD != 1) t.x[s][q] = at_byte(xq[q], pos * 8u);
         t.r[s][q] = at_byte(rq[q], pos * 8u);
+        if (XD == 2) t.v[s][q] = at_byte(vq[q], pos * 8u);
       }
     }
   };
@@ -749,7 +765,8 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
           __builtin_nontemporal_store(vp, &at_byte(oq[q], o));
           acc[q] += vp * Av;
         } else {
-          at_byte(xq[q], o) = Xk.x[s][q] + sc[q] * vp;
+          if (XD == 0) at_byte(xq[q], o) = Xk.x[s][q] + sc[q] * vp;
+          if (XD == 2) at_byte(xq[q], o) = (Xk.x[s][q] + ap[q] * Xk.v[s][q]) + sc[q] * vp;
           const double r = Xk.r[s][q] - sc[q] * Av;
           at_byte(oq[q], o) = r;
           if (r32) at_byte(sq[q], (uint32_t)pos * 4u) = (float)r;
@@ -1667,7 +1684,8 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
                          const TY* y, int64_t y_ld, const double* p_in, double* p_out, double* x,
                          const double* r_in, double* r_out, const double* scal,
                          const int* active, double* part, hipStream_t s, int kind,
-                         float* r32 = nullptr, int zn = kZNodes) {
+                         float* r32 = nullptr, int zn = kZNodes, int xd = 0,
+                         const double* p_prev = nullptr, const double* a_prev = nullptr) {
   if (kind == 1) return 0;
   qpb = std::min(qpb, 4);
   if (zn != 4 || qpb > 2) zn = kZNodes;  // four nodes per thread: up to two queries per block
@@ -1680,9 +1698,16 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   const dim3 grid((unsigned)(tiles * groups));
   const size_t lds = z_lds(g, zt, qpb);
   auto go = [&](auto Q, auto Z) {
-    hipLaunchKernelGGL((k_zmarch<Q.value, MODE, TY, Z.value>), grid, dim3(kZThreads), lds, s, g,
-                       zt, ld, B, coef, y, y_ld, p_in, p_out, x, r_in, r_out, scal, active, part,
-                       pstride, r32);
+    auto run = [&](auto X) {
+      hipLaunchKernelGGL((k_zmarch<Q.value, MODE, TY, Z.value, X.value>), grid, dim3(kZThreads),
+                         lds, s, g, zt, ld, B, coef, y, y_ld, p_in, p_out, x, r_in, r_out, scal,
+                         active, part, pstride, r32, p_prev, a_prev);
+    };
+    if constexpr (MODE == 1) {
+      if (xd == 1) return run(std::integral_constant<int, 1>{});
+      if (xd == 2) return run(std::integral_constant<int, 2>{});
+    }
+    run(std::integral_constant<int, 0>{});
   };
   using Z2 = std::integral_constant<int, kZNodes>;
   using Z4 = std::integral_constant<int, 4>;
@@ -1730,19 +1755,32 @@ template int launch_pass_a<float>(const StencilGeom&, int64_t, int, const double
 
 int launch_pass_b(const StencilGeom& g, int64_t ld, int B, const double* coef, const double* p,
                   double* x, const double* r_in, double* r_out, const double* alpha,
-                  const int* active, double* part, hipStream_t s, float* r32) {
+                  const int* active, double* part, hipStream_t s, float* r32, int xd,
+                  const double* p_prev, const double* a_prev) {
   RB_REQUIRE(!r32 || !g.csr, RB_EINVAL, "FP32 residual copy: stencil grids only");
+  RB_REQUIRE(xd == 0 || !g.csr, RB_EINVAL, "paired updates of x: stencil grids only");
+  RB_REQUIRE(xd >= 0 && xd <= 2 && (xd != 2 || (p_prev && a_prev)), RB_EINVAL,
+             "bad x update of pass B");
   if (g.csr) return csr_pass_b(g, ld, B, coef, p, x, r_in, r_out, alpha, active, part, s);
   const int qpb = pick_qpb(g, B, 8, t_tiles.qpb_b ? t_tiles.qpb_b : 2);
   if (const int t = launch_zmarch<1, double>(g, qpb, ld, B, coef, nullptr, 0, p, nullptr, x, r_in,
                                              r_out, alpha, active, part, s, t_tiles.kind_b, r32,
-                                             t_tiles.zn_b ? t_tiles.zn_b : kZNodes))
+                                             t_tiles.zn_b ? t_tiles.zn_b : kZNodes, xd, p_prev,
+                                             a_prev))
     return t;
   const int chunks = stencil_chunks_all(g.N);
   dispatch(g.dim, qpb, [&](auto D, auto Q) {
-    hipLaunchKernelGGL((k_pass_b<D.value, Q.value>), grid_for(chunks, B, Q.value), dim3(kThreads),
-                       Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, p, x, r_in, r_out,
-                       alpha, active, part, r32);
+    auto run = [&](auto X) {
+      hipLaunchKernelGGL((k_pass_b<D.value, Q.value, X.value>), grid_for(chunks, B, Q.value),
+                         dim3(kThreads), Q.value * g.ct_size * 8, s, g, ld, B, chunks, coef, p, x,
+                         r_in, r_out, alpha, active, part, r32, p_prev, a_prev);
+    };
+    if (xd == 1)
+      run(std::integral_constant<int, 1>{});
+    else if (xd == 2)
+      run(std::integral_constant<int, 2>{});
+    else
+      run(std::integral_constant<int, 0>{});
   });
   return chunks;
 }

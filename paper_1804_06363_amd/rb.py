@@ -51,7 +51,7 @@ class SolveOpts(C.Structure):
                 ("check_every", C.c_int), ("autotune", C.c_int), ("stencil_kind", C.c_int),
                 ("adapt_gamma", C.c_double), ("floor_factor", C.c_double),
                 ("smooth_sweeps", C.c_int), ("residual_copy", C.c_int),
-                ("prolong_kind", C.c_int)]
+                ("prolong_kind", C.c_int), ("paired_x_update", C.c_int)]
 
 
 class QueryStats(C.Structure):
@@ -329,7 +329,7 @@ PROLONG_KIND = {"auto": 0, "mfma": 1, "vector": 2}
 def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=2000,
                flexible=False, graph=False, fixed_iters=0, check_every=0, autotune=False,
                stencil="auto", adapt_gamma=0.0, sweeps=1, floor_factor=0.0, residual_copy=True,
-               prolong="auto"):
+               prolong="auto", paired_x=True):
     o = SolveOpts()
     _lib.rb_solve_opts_default(C.byref(o))
     o.solver = SOLVER[solver]
@@ -348,6 +348,7 @@ def solve_opts(solver="rbcg", prec="fp64", smoother="rbgs", rtol=1e-10, maxit=20
     o.floor_factor = floor_factor
     o.residual_copy = int(residual_copy)
     o.prolong_kind = PROLONG_KIND[prolong]
+    o.paired_x_update = int(paired_x)
     return o
 
 

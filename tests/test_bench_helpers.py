@@ -17,14 +17,22 @@ def _cache(tmp_path, table):
 def test_pass_b_kernel_from_tuner_cache(tmp_path):
     other = "gfx950|d2|N20|B8|n3|p1|s0"
     path = _cache(tmp_path, {KEY_127: [1, 2, 4, 512, 2, 2, 1], other: [1, 4, 4, 512, 1, 1, 1]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == "k_zmarch<2, 1, double, 2>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
+        "k_zmarch<2, 1, double, 2, 0>"
+    # paired updates of x: the two variants alternate
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == \
+        "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>"
     # taller tiles (four nodes per thread) only with at most two queries per block
     path = _cache(tmp_path, {KEY_127: [1, 1, 2, 512, 2, 2, 2, 2, 2, 4, 2]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == "k_zmarch<1, 1, double, 4>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
+        "k_zmarch<1, 1, double, 4, 0>"
     path = _cache(tmp_path, {KEY_127: [1, 4, 2, 512, 2, 2, 2, 2, 2, 4, 2]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == "k_zmarch<4, 1, double, 2>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
+        "k_zmarch<4, 1, double, 2, 0>"
     path = _cache(tmp_path, {KEY_127: [1, 4, 4, 512, 2, 1]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == "k_pass_b<3, 4>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == "k_pass_b<3, 4, 0>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == \
+        "k_pass_b<3, 4, 1> / k_pass_b<3, 4, 2>"
     # another precision, a missing file, an unreadable file: no claim about the kernel
     assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "bf16") == "pass B (tiles unknown)"
     assert bench.pass_b_kernel(str(tmp_path / "none.json"), 3, 1, 1, 1, "fp32") == \
@@ -38,14 +46,14 @@ def test_measured_traffic_needs_the_profiled_kernel_and_sources(tmp_path, monkey
     h = bench.kernel_source_hash()
     prof = tmp_path / "prof.md"
     prof.write_text(f"text\n\ntraffic_bytes_per_launch: 123456 sources_sha256: {h} "
-                    "kernel: k_zmarch<2, 1, double, 2>\n")
+                    "kernel: k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", "prof.md")
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
-    assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<2, 1, double, 2>") == 123456
+    assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") == 123456
     assert bench.measured_traffic("3d127", "fp32", 256, "k_pass_b<3, 2>") is None
-    assert bench.measured_traffic("3d127", "bf16", 256, "k_zmarch<2, 1, double, 2>") is None
-    assert bench.measured_traffic("3d255", "fp32", 64, "k_zmarch<2, 1, double, 2>") is None
+    assert bench.measured_traffic("3d127", "bf16", 256, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") is None
+    assert bench.measured_traffic("3d255", "fp32", 64, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<2, 1, double, 2>") is None
+    assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") is None
 

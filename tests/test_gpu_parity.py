@@ -327,6 +327,46 @@ def test_residual_copy_is_bitwise_equal(lib, ctx, dims, blocks, stencil, prec, B
     assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
 
 
+@pytest.mark.parametrize("dims,blocks,stencil", [((63, 63), (2, 2), "auto"),
+                                                  ((31, 31, 31), (2, 2, 2), "chunked"),
+                                                  ((31, 31, 31), (2, 2, 2), "zmarch"),
+                                                  ((31, 31, 31), (2, 2, 2), "zmarch4"),
+                                                  ((129, 5, 9), (2, 2, 2), "zmarch")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("B", [5, 20])
+def test_paired_x_update_is_bitwise_equal(lib, ctx, dims, blocks, stencil, prec, B):
+    """Pass B of an even iteration leaves its update of x to the next iteration's pass B,
+    which applies both in their original order (or to the fold before a true-residual
+    check, or the end of the solve): no bit changes.  Fixed k odd and even (a pending update
+    at the end), literal and flexible beta, graph replay, plain CG, converged solves (folds
+    at checks of both parities) and queries stopped by maxit after an even iteration."""
+    op, prob, W, basis = _setup(lib, ctx, dims, blocks, 6, seed=80)
+    theta = log_uniform_mu(81, B, op.Q, 0.1, 10.0)
+
+    def both(b, **kw):
+        x0, s0 = lib.solve_batch(ctx, prob, b, theta, paired_x=False, **kw)
+        x1, s1 = lib.solve_batch(ctx, prob, b, theta, paired_x=True, **kw)
+        assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy()), kw
+        for f in ("iters", "status", "rel_res_recursive", "rel_res_true"):
+            assert np.array_equal(getattr(s0, f), getattr(s1, f)), (f, kw)
+        return s1
+
+    for k in (5, 6):
+        for flexible in (False, True):
+            both(basis, prec=prec, fixed_iters=k, sweeps=2, flexible=flexible, stencil=stencil)
+    both(basis, prec=prec, fixed_iters=7, sweeps=2, stencil=stencil, graph=True)
+    both(None, solver="cg", prec=prec, fixed_iters=5, stencil=stencil)
+    Ws = _snapshot_basis(op, 5, seed=82)
+    bs = lib.Basis.from_host(ctx, prob, Ws.T)
+    for ce in (2, 3):
+        st = both(bs, prec=prec, sweeps=2, stencil=stencil, check_every=ce)
+        assert (st.status == lib.RB_OK).all() and st.rel_res_true.max() <= 1e-10
+    st = both(bs, prec=prec, sweeps=2, stencil=stencil, rtol=1e-15, maxit=5)
+    assert (st.status == lib.RB_ENOCONV).all() and (st.iters == 5).all()
+    st = both(bs, prec=prec, sweeps=2, stencil=stencil, graph=True, flexible=True)
+    assert (st.status == lib.RB_OK).all()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_zmarch_converged(lib, ctx, prec):
     """Converged solves with the z-marching passes: queries retire at different
