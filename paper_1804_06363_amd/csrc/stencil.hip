@@ -984,7 +984,9 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   const int pu = threadIdx.x % pairs;
   // a node outside the tile or the grid is loaded from one of its colour inside them
   const int jlast = min(j0 + zt.zr, g.ny) - 1;  // last row of the tile inside the grid
-  int j[NP], lm[NP][2], slot[NP][2], cb[NP][2][4], zxy[NP][2];
+  // lm0 / lm1: in-plane offsets the two columns of a pair load from (two arrays, not one
+  // indexed by the plane's parity, which the compiler kept in scratch memory)
+  int j[NP], lm0[NP], lm1[NP], slot[NP][2], cb[NP][2][4], zxy[NP][2];
   unsigned inb[NP][2];
   bool own[NP][2];
 #pragma unroll
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
       const int i = i0 + 2 * pu + c2;
       own[a][c2] = rowok && i < g.nx;
       const int ic = own[a][c2] ? i : 0;
-      lm[a][c2] = clamp_same_parity(i, g.nx - 1) + g.nx * jl;
+      (c2 ? lm1[a] : lm0[a]) = clamp_same_parity(i, g.nx - 1) + g.nx * jl;
       slot[a][c2] = (jj + 1) * W2 + 2 * pu + c2 + 1;
       const uint32_t tx = g.tab[0][ic], ty = g.tab[1][jc];
       const int sx = tx & 0xff, sy = ty & 0xff;
@@ -1085,7 +1087,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   auto load_raw = [&](Raw& t, int k) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      const int pos = spos(k * P + (ucol(a, k) ? lm[a][0] : lm[a][1]));
+      const int pos = spos(k * P + (ucol(a, k) ? lm0[a] : lm1[a]));
 #pragma unroll
       for (int q = 0; q < QPB; ++q) t.v[a][q] = y[rowy[q] + pos];
     }
@@ -1099,7 +1101,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   auto load_rhs = [&](Rhs& t, int k) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      const int pos = spos(k * P + (ucol(a, k) ? lm[a][1] : lm[a][0]));
+      const int pos = spos(k * P + (ucol(a, k) ? lm1[a] : lm0[a]));
 #pragma unroll
       for (int q = 0; q < QPB; ++q) {
         t.r[a][q] = rhs[rowr[q] + pos];
@@ -1160,7 +1162,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     for (int a = 0; a < NP; ++a) {
       const int cu = ucol(a, k);
       if (!(cu ? own[a][1] : own[a][0])) continue;
-      const int pos = spos(k * P + (cu ? lm[a][1] : lm[a][0]));  // an own node
+      const int pos = spos(k * P + (cu ? lm1[a] : lm0[a]));  // an own node
       const unsigned inner = (cu ? inb[a][1] : inb[a][0]) | zb;
       const int su = cu ? slot[a][1] : slot[a][0];
       const int zx = cu ? zxy[a][1] : zxy[a][0];
