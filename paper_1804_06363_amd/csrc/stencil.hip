@@ -1186,8 +1186,10 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
         const double fp = fsc[q] * (double)Xk.r[a][q];
         const TY v = gs_div<TY>((TY)fp + off, d);
         y[(size_t)(q0 + q) * y_ld + pos] = v;
-        a0[q] += (double)v * fp;
-        if (FLEX) a1[q] += (double)v * Xk.r2[a][q];
+        if (part0) {  // sweeps that leave the class final only (a uniform branch)
+          a0[q] += (double)v * fp;
+          if (FLEX) a1[q] += (double)v * Xk.r2[a][q];
+        }
       }
     }
     vb = vc;
