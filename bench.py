@@ -48,18 +48,20 @@ def kernel_source_hash():
 
 def measured_traffic(workload, prec, B, kernel):
     """HBM bytes per launch of pass B's kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the calibration kernels), or None when the summary
-    is for another configuration or kernel, or the kernel's sources changed since."""
+    (FETCH_SIZE + WRITE_SIZE, scaled by the calibration kernels; one line per profiled tile
+    choice), or None when the summary is for another configuration or kernel, or the
+    kernel's sources changed since."""
     import re
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if workload != "3d127" or prec != "fp32" or B != 256 or not os.path.exists(path):
         return None
     with open(path) as f:
-        m = re.search(r"^traffic_bytes_per_launch: (\d+) sources_sha256: ([0-9a-f]+) "
-                      r"kernel: (.+)$", f.read(), re.M)
-    if not m or m.group(2) != kernel_source_hash() or m.group(3).strip() != kernel:
-        return None
-    return int(m.group(1))
+        lines = re.findall(r"^traffic_bytes_per_launch: (\d+) sources_sha256: ([0-9a-f]+) "
+                           r"kernel: (.+)$", f.read(), re.M)
+    for value, digest, name in lines:
+        if digest == kernel_source_hash() and name.strip() == kernel:
+            return int(value)
+    return None
 
 
 def pass_b_kernel(cache_path, dim, N, B, n, prec, paired=True):

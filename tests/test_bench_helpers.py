@@ -46,11 +46,15 @@ def test_measured_traffic_needs_the_profiled_kernel_and_sources(tmp_path, monkey
     h = bench.kernel_source_hash()
     prof = tmp_path / "prof.md"
     prof.write_text(f"text\n\ntraffic_bytes_per_launch: 123456 sources_sha256: {h} "
-                    "kernel: k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>\n")
+                    "kernel: k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>\n"
+                    f"traffic_bytes_per_launch: 654321 sources_sha256: {h} "
+                    "kernel: k_zmarch<1, 1, double, 4, 1> / k_zmarch<1, 1, double, 4, 2>\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", "prof.md")
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
     assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") == 123456
+    # one line per profiled tile choice
+    assert bench.measured_traffic("3d127", "fp32", 256, "k_zmarch<1, 1, double, 4, 1> / k_zmarch<1, 1, double, 4, 2>") == 654321
     assert bench.measured_traffic("3d127", "fp32", 256, "k_pass_b<3, 2>") is None
     assert bench.measured_traffic("3d127", "bf16", 256, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") is None
     assert bench.measured_traffic("3d255", "fp32", 64, "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>") is None
