@@ -68,10 +68,11 @@ def pass_b_kernel(cache_path, dim, N, B, n, prec, paired=True):
     """Name of the kernel that ran pass B, from the tile choice the autotuner wrote to
     its cache file: {"arch|d<dim>|N<log2 N>|B<log2 B>|n<ceil(n/16)>|p<prec>|s<smoother>":
     [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs, kind_pro, zn_a, zn_b,
-    np_gs], ...}; the marching pass B takes four nodes per thread (zn_b = 4) with at most
-    two queries per block, else two.  The last template argument is the update of x: 0
-    every iteration; with paired updates 1 (none, even iterations) and 2 (two updates, odd
-    iterations) alternate, and the name gives both."""
+    np_gs, nb_b], ...}; the marching pass B takes four nodes per thread (zn_b = 4) with at
+    most two queries per block, else two, and stages nb_b plane buffers.  The template
+    argument after the nodes per thread is the update of x: 0 every iteration; with paired
+    updates 1 (none, even iterations) and 2 (two updates, odd iterations) alternate, and the
+    name gives both."""
     suffix = (f"|d{dim}|N{int(N).bit_length() - 1}|B{int(B).bit_length() - 1}"
               f"|n{(n + 15) // 16}|p{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[prec] }|s0")
     try:
@@ -81,13 +82,16 @@ def pass_b_kernel(cache_path, dim, N, B, n, prec, paired=True):
         tiles = []
     if len(tiles) != 1 or len(tiles[0]) < 6:
         return "pass B (tiles unknown)"
-    qpb_b, kind_b = tiles[0][1], tiles[0][5]
+    t = tiles[0]
+    qpb_b, kind_b = t[1], t[5]
     if dim == 3 and kind_b == 2:
-        zn = 4 if len(tiles[0]) >= 10 and tiles[0][9] == 4 and qpb_b <= 2 else 2
-        stem = f"k_zmarch<{qpb_b}, 1, double, {zn}, "
+        zn = 4 if len(t) >= 10 and t[9] == 4 and qpb_b <= 2 else 2
+        if len(t) < 12 or t[11] not in (1, 2):
+            return "pass B (tiles unknown)"
+        stem, tail = f"k_zmarch<{qpb_b}, 1, double, {zn}, ", f", {t[11]}>"
     else:
-        stem = f"k_pass_b<{dim}, {qpb_b}, "
-    return f"{stem}1> / {stem}2>" if paired else f"{stem}0>"
+        stem, tail = f"k_pass_b<{dim}, {qpb_b}, ", ">"
+    return f"{stem}1{tail} / {stem}2{tail}" if paired else f"{stem}0{tail}"
 
 
 def log(*a):

@@ -174,6 +174,8 @@ struct TuneConfig {
                                          // 2 vector units
   int zn_a = 0, zn_b = 0;                // marching passes A / B: nodes per thread (0 = 2)
   int np_gs = 0;                         // marching sweeps: column pairs per thread (0 = 2)
+  int nb_b = 0;                          // marching pass B: LDS plane buffers, 1 or 2 (0 =
+                                         // 2 where they fit in 64 KB)
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

@@ -584,20 +584,31 @@ void BatchSolver::autotune() {
                                 part_m.as<double>(), st);
       });
       if (t1 < ta) { ta = t1; best.qpb_a = c; best.kind_a = kind; best.zn_a = zn; }
-      cur = best;
-      cur.qpb_b = c;
-      cur.kind_b = kind;
-      cur.zn_b = zn;
-      set_stencil_tiles(cur);
-      // with paired x updates, the pass B of an even iteration and that of an odd one
-      const float t2 = timed([&] {
-        for (int xd : {pair_x ? 1 : 0, pair_x ? 2 : -1})
-          if (xd >= 0)
-            launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
-                          r0.as<double>(), r0.as<double>(), q.alpha, q.active,
-                          part_m.as<double>(), st, rc, xd, p0.as<double>(), q.alpha);
-      });
-      if (t2 < tb) { tb = t2; best.qpb_b = c; best.kind_b = kind; best.zn_b = zn; }
+      // marching pass B with one and (where they fit) two LDS plane buffers
+      const int nbs = kind == 2 && pass_b_two_buffers(g, B, c, zn ? zn : 2) ? 2 : 1;
+      for (int nb = 1; nb <= nbs; ++nb) {
+        cur = best;
+        cur.qpb_b = c;
+        cur.kind_b = kind;
+        cur.zn_b = zn;
+        cur.nb_b = nb;
+        set_stencil_tiles(cur);
+        // with paired x updates, the pass B of an even iteration and that of an odd one
+        const float t2 = timed([&] {
+          for (int xd : {pair_x ? 1 : 0, pair_x ? 2 : -1})
+            if (xd >= 0)
+              launch_pass_b(g, L_, B, coef.as<double>(), p1.as<double>(), x.as<double>(),
+                            r0.as<double>(), r0.as<double>(), q.alpha, q.active,
+                            part_m.as<double>(), st, rc, xd, p0.as<double>(), q.alpha);
+        });
+        if (t2 < tb) {
+          tb = t2;
+          best.qpb_b = c;
+          best.kind_b = kind;
+          best.zn_b = zn;
+          best.nb_b = nb;
+        }
+      }
     }
   }
   for (int kp : {1, 2, 4}) {  // chunked, marching with 2 or 4 column pairs per thread (3D)

@@ -517,7 +517,7 @@ struct ZTile {
 constexpr int kZThreads = 512;
 constexpr int kZNodes = 2;  // own nodes per thread by default (zr * zc <= 1024); 4 for taller tiles
 
-template <int QPB, int MODE, typename TY, int ZN, int XD = 0>
+template <int QPB, int MODE, typename TY, int ZN, int XD = 0, int NB = 1>
 __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, int64_t ld, int B,
                                                       const double* coef,
                                                       const TY* __restrict__ y, int64_t y_ld,
@@ -549,7 +549,9 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
   double* cfs = dyn;
   const int W2 = zt.zc + 2;  // LDS row pitch (halo column on each side)
   const int plane = (zt.zr + 2) * W2;
-  double* pl = dyn + QPB * g.ct_size;  // [QPB][zr + 2][zc + 2]
+  // [NB][QPB][zr + 2][zc + 2]: with two buffers, plane k is staged in buffer k % 2,
+  // which the block last read two planes before, so one barrier per plane suffices
+  double* pl = dyn + QPB * g.ct_size;
   const unsigned mask = load_group<QPB>(g, coef, q0, B, active, cfs);
   if (!mask) return;
   const int j0 = rtile * zt.zr, i0 = ctile * zt.zc;
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
 
   // z data of the slab's planes: tangential state and the coefficient-table offsets of
   // the lower and upper z faces
-  int* zinfo = reinterpret_cast<int*>(pl + QPB * plane);  // [kslab][3]
+  int* zinfo = reinterpret_cast<int*>(pl + NB * QPB * plane);  // [kslab][3]
   for (int kk = threadIdx.x; kk < k1 - k0; kk += kZThreads) {
     const uint32_t tz = g.tab[2][k0 + kk];
     zinfo[3 * kk] = tz & 0xff;
@@ -723,17 +725,18 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
     load_raw(Rk3, min(k + 3, klast));
     load_halo(Hn, min(k + 1, klast));
     load_xr(Xn, min(k + 1, klast));
-    __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
+    double* const pk = NB == 2 ? pl + (k & 1) * QPB * plane : pl;
+    if (NB == 1) __syncthreads();  // the previous plane's LDS reads are done
 #pragma unroll
     for (int s = 0; s < ZN; ++s)
       if (own[s])
 #pragma unroll
-        for (int q = 0; q < QPB; ++q) pl[q * plane + slot[s]] = vc[s][q];
+        for (int q = 0; q < QPB; ++q) pk[q * plane + slot[s]] = vc[s][q];
     if (hv)
 #pragma unroll
       for (int q = 0; q < QPB; ++q)
-        pl[q * plane + hslot] = MODE == 0 ? (double)Hk.y[q] + sc[q] * Hk.p[q] : Hk.p[q];
-    __syncthreads();
+        pk[q * plane + hslot] = MODE == 0 ? (double)Hk.y[q] + sc[q] * Hk.p[q] : Hk.p[q];
+    __syncthreads();  // the plane is staged (and zinfo is written)
     const int sz = zinfo[3 * (k - k0)];
     const int zlo = zinfo[3 * (k - k0) + 1];
     const int zhi = zinfo[3 * (k - k0) + 2];
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(kZThreads) void k_zmarch(StencilGeom g, ZTile zt, i
       for (int q = 0; q < QPB; ++q) {
         if (!live(q)) continue;
         const double* cf = cfs + q * g.ct_size;
-        const double* lp = pl + q * plane + slot[s];
+        const double* lp = pk + q * plane + slot[s];
         const double vals[6] = {lp[-1], lp[1], lp[-W2], lp[W2], vb[s][q], vn[s][q]};
         double d = 0.0, off = 0.0;
 #pragma unroll
@@ -950,7 +953,8 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
                                                          int64_t rhs2_ld,
                                                          const int* __restrict__ active,
                                                          double* __restrict__ part0,
-                                                         double* __restrict__ part1) {
+                                                         double* __restrict__ part1,
+                                                         int nbuf) {
   constexpr int NW = kZThreads / 64;
   extern __shared__ double dyn[];
   __shared__ double red[NW * QPB];
@@ -964,7 +968,9 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
   TY* cfs = reinterpret_cast<TY*>(dyn);
   const int W2 = zt.zc + 2;  // LDS row pitch (halo column on each side)
   const int plane = (zt.zr + 2) * W2;
-  TY* pl = cfs + QPB * g.ct_size;  // [QPB][zr + 2][zc + 2]
+  // [nbuf][QPB][zr + 2][zc + 2]: with two buffers, plane k is staged in buffer k % 2,
+  // which the block last read two planes before, so one barrier per plane suffices
+  TY* pl = cfs + QPB * g.ct_size;
   const unsigned mask = load_group<QPB, TY>(g, coef, q0, B, active, cfs);
   if (!mask) return;
   const int j0 = rtile * zt.zr, i0 = ctile * zt.zc;  // i0 is even
@@ -1110,7 +1116,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     }
   };
 
-  int* zinfo = reinterpret_cast<int*>(pl + QPB * plane);  // [kslab][3]
+  int* zinfo = reinterpret_cast<int*>(pl + nbuf * QPB * plane);  // [kslab][3]
   for (int kk = threadIdx.x; kk < k1 - k0; kk += kZThreads) {
     const uint32_t tz = g.tab[2][k0 + kk];
     zinfo[3 * kk] = tz & 0xff;
@@ -1137,23 +1143,24 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
     load_raw(Rk3, min(k + 3, klast));
     load_halo(Hn, min(k + 1, klast));
     load_rhs(Xn, min(k + 1, klast));
-    __syncthreads();  // the previous plane's LDS reads are done (and zinfo is written)
+    TY* const pk = pl + (nbuf == 2 ? (k & 1) * QPB * plane : 0);
+    if (nbuf == 1) __syncthreads();  // the previous plane's LDS reads are done
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
       const int cu = ucol(a, k);
       if (cu ? own[a][0] : own[a][1]) {
         const int ss = cu ? slot[a][0] : slot[a][1];
 #pragma unroll
-        for (int q = 0; q < QPB; ++q) pl[q * plane + ss] = vc.v[a][q];
+        for (int q = 0; q < QPB; ++q) pk[q * plane + ss] = vc.v[a][q];
       }
     }
     {
       const int hs = hsel(k);
       if (hs ? hvc[1] : hvc[0])
 #pragma unroll
-        for (int q = 0; q < QPB; ++q) pl[q * plane + (hs ? hsl[1] : hsl[0])] = Hk.v[q];
+        for (int q = 0; q < QPB; ++q) pk[q * plane + (hs ? hsl[1] : hsl[0])] = Hk.v[q];
     }
-    __syncthreads();
+    __syncthreads();  // the plane is staged (and zinfo is written)
     const int sz = zinfo[3 * (k - k0)];
     const int zlo = zinfo[3 * (k - k0) + 1];
     const int zhi = zinfo[3 * (k - k0) + 2];
@@ -1174,7 +1181,7 @@ __global__ __launch_bounds__(kZThreads) void k_gs_zmarch(StencilGeom g, ZTile zt
       for (int q = 0; q < QPB; ++q) {
         if (!live(q)) continue;
         const TY* cf = cfs + q * g.ct_size;
-        const TY* lp = pl + q * plane + su;
+        const TY* lp = pk + q * plane + su;
         const TY nv[6] = {lp[-1], lp[1], lp[-W2], lp[W2], vb.v[a][q], vn.v[a][q]};
         TY d = TY(0), off = TY(0);
 #pragma unroll
@@ -1672,8 +1679,8 @@ static bool z_plan(const StencilGeom& g, int groups, ZTile& zt, int zn = kZNodes
   return true;
 }
 
-static size_t z_lds(const StencilGeom& g, const ZTile& zt, int qpb) {
-  return (size_t)qpb * (g.ct_size + (zt.zr + 2) * (zt.zc + 2)) * sizeof(double) +
+static size_t z_lds(const StencilGeom& g, const ZTile& zt, int qpb, int nbuf = 1) {
+  return (size_t)qpb * (g.ct_size + nbuf * (zt.zr + 2) * (zt.zc + 2)) * sizeof(double) +
          (size_t)3 * zt.kslab * sizeof(int);
 }
 
@@ -1700,18 +1707,26 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const int pstride = stencil_chunks_all(g.N);  // row stride of the partial sums
   const dim3 grid((unsigned)(tiles * groups));
-  const size_t lds = z_lds(g, zt, qpb);
+  // pass B stages two plane buffers (one barrier per plane) when they fit in 64 KB, unless
+  // the tiles ask for one; pass A keeps one, whose variants need fewer registers (more
+  // blocks per CU)
+  const int nbuf = MODE == 1 && t_tiles.nb_b != 1 && z_lds(g, zt, qpb, 2) <= 65536 ? 2 : 1;
+  const size_t lds = z_lds(g, zt, qpb, nbuf);
   auto go = [&](auto Q, auto Z) {
-    auto run = [&](auto X) {
-      hipLaunchKernelGGL((k_zmarch<Q.value, MODE, TY, Z.value, X.value>), grid, dim3(kZThreads),
-                         lds, s, g, zt, ld, B, coef, y, y_ld, p_in, p_out, x, r_in, r_out, scal,
-                         active, part, pstride, r32, p_prev, a_prev);
+    auto run = [&](auto X, auto NBc) {
+      hipLaunchKernelGGL((k_zmarch<Q.value, MODE, TY, Z.value, X.value, NBc.value>), grid,
+                         dim3(kZThreads), lds, s, g, zt, ld, B, coef, y, y_ld, p_in, p_out, x,
+                         r_in, r_out, scal, active, part, pstride, r32, p_prev, a_prev);
     };
+    using N1 = std::integral_constant<int, 1>;
+    using N2 = std::integral_constant<int, 2>;
     if constexpr (MODE == 1) {
-      if (xd == 1) return run(std::integral_constant<int, 1>{});
-      if (xd == 2) return run(std::integral_constant<int, 2>{});
+      auto by_nb = [&](auto X) { return nbuf == 2 ? run(X, N2{}) : run(X, N1{}); };
+      if (xd == 1) return by_nb(std::integral_constant<int, 1>{});
+      if (xd == 2) return by_nb(std::integral_constant<int, 2>{});
+      return by_nb(std::integral_constant<int, 0>{});
     }
-    run(std::integral_constant<int, 0>{});
+    run(std::integral_constant<int, 0>{}, N1{});
   };
   using Z2 = std::integral_constant<int, kZNodes>;
   using Z4 = std::integral_constant<int, 4>;
@@ -1727,6 +1742,13 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
       break;
   }
   return tiles;
+}
+
+bool pass_b_two_buffers(const StencilGeom& g, int B, int qpb, int zn) {
+  qpb = std::min(qpb, 4);
+  if (zn != 4 || qpb > 2) zn = kZNodes;
+  ZTile zt;
+  return z_plan(g, (B + qpb - 1) / qpb, zt, zn) && z_lds(g, zt, qpb, 2) <= 65536;
 }
 
 template <typename TY>
@@ -1828,15 +1850,20 @@ static int launch_gs_zmarch(const StencilGeom& g, int color, int qpb, int B, con
   ZTile zt;
   const int groups = (B + qpb - 1) / qpb;
   if (!zg_plan(g, groups, stencil_chunks(color ? g.N - g.NR : g.NR), zt, np)) return 0;
-  const size_t lds = (size_t)qpb * (g.ct_size + (zt.zr + 2) * (zt.zc + 2)) * sizeof(TY) +
-                     (size_t)3 * zt.kslab * sizeof(int);
+  // two plane buffers (one barrier per plane) when they fit in 64 KB, else one
+  auto lds_of = [&](int nb) {
+    return (size_t)qpb * (g.ct_size + nb * (zt.zr + 2) * (zt.zc + 2)) * sizeof(TY) +
+           (size_t)3 * zt.kslab * sizeof(int);
+  };
+  const int nbuf = lds_of(2) <= 65536 ? 2 : 1;
+  const size_t lds = lds_of(nbuf);
   if (lds > 65536) return 0;
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const dim3 grid((unsigned)(tiles * groups));
   auto go = [&](auto Q, auto F, auto NPc) {
     hipLaunchKernelGGL((k_gs_zmarch<Q.value, TY, F.value, RT, NPc.value>), grid, dim3(kZThreads),
                        lds, s, g, zt, color, B, coef, y, y_ld, rhs, rhs_ld, rhs_scale, rhs2,
-                       rhs2_ld, active, part0, part1);
+                       rhs2_ld, active, part0, part1, nbuf);
   };
   using P2 = std::integral_constant<int, kGsPairs>;
   using P4 = std::integral_constant<int, 4>;

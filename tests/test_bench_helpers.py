@@ -16,19 +16,23 @@ def _cache(tmp_path, table):
 
 def test_pass_b_kernel_from_tuner_cache(tmp_path):
     other = "gfx950|d2|N20|B8|n3|p1|s0"
-    path = _cache(tmp_path, {KEY_127: [1, 2, 4, 512, 2, 2, 1], other: [1, 4, 4, 512, 1, 1, 1]})
+    path = _cache(tmp_path, {KEY_127: [1, 2, 4, 512, 2, 2, 1, 2, 2, 2, 2, 2],
+                             other: [1, 4, 4, 512, 1, 1, 1]})
     assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
-        "k_zmarch<2, 1, double, 2, 0>"
+        "k_zmarch<2, 1, double, 2, 0, 2>"
     # paired updates of x: the two variants alternate
     assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == \
-        "k_zmarch<2, 1, double, 2, 1> / k_zmarch<2, 1, double, 2, 2>"
+        "k_zmarch<2, 1, double, 2, 1, 2> / k_zmarch<2, 1, double, 2, 2, 2>"
     # taller tiles (four nodes per thread) only with at most two queries per block
+    path = _cache(tmp_path, {KEY_127: [1, 1, 2, 512, 2, 2, 2, 2, 2, 4, 2, 1]})
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
+        "k_zmarch<1, 1, double, 4, 0, 1>"
+    path = _cache(tmp_path, {KEY_127: [1, 4, 2, 512, 2, 2, 2, 2, 2, 4, 2, 1]})
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
+        "k_zmarch<4, 1, double, 2, 0, 1>"
+    # a marching pass B without its number of plane buffers: no claim about the kernel
     path = _cache(tmp_path, {KEY_127: [1, 1, 2, 512, 2, 2, 2, 2, 2, 4, 2]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
-        "k_zmarch<1, 1, double, 4, 0>"
-    path = _cache(tmp_path, {KEY_127: [1, 4, 2, 512, 2, 2, 2, 2, 2, 4, 2]})
-    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == \
-        "k_zmarch<4, 1, double, 2, 0>"
+    assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == "pass B (tiles unknown)"
     path = _cache(tmp_path, {KEY_127: [1, 4, 4, 512, 2, 1]})
     assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32", False) == "k_pass_b<3, 4, 0>"
     assert bench.pass_b_kernel(path, 3, 2048383, 256, 40, "fp32") == \
