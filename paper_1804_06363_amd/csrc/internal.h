@@ -176,6 +176,7 @@ struct TuneConfig {
   int np_gs = 0;                         // marching sweeps: column pairs per thread (0 = 2)
   int nb_b = 0;                          // marching pass B: LDS plane buffers, 1 or 2 (0 =
                                          // 2 where they fit in 64 KB)
+  int nb_a = 0;                          // marching pass A: the same (0 = 1)
 };
 // Autotuner cache: key -> choice; persisted as JSON when RB_AUTOTUNE_CACHE names a file.
 struct Tuner {

@@ -90,9 +90,9 @@ template <typename TY>
 int launch_pass_a(const StencilGeom& g, int64_t ld, int B, const double* coef, const TY* y,
                   int64_t y_ld, const double* p_old, double* p_new, const double* beta,
                   const int* active, double* part, hipStream_t s);
-// whether the marching pass B with qpb queries per block and zn nodes per thread can
+// whether the marching passes with qpb queries per block and zn nodes per thread can
 // stage two plane buffers (within 64 KB of LDS)
-bool pass_b_two_buffers(const StencilGeom& g, int B, int qpb, int zn);
+bool zmarch_two_buffers(const StencilGeom& g, int B, int qpb, int zn);
 // r32 (nullable, stencil grids): pass B also writes an FP32 copy of r_out (rows of ld).
 // xd (stencil grids): the update of x, 0 x += alpha p, 1 none (deferred to the next
 // iteration), 2 x = (x + a_prev p_prev) + alpha p (the deferred update first).

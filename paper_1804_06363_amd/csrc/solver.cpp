@@ -569,23 +569,33 @@ void BatchSolver::autotune() {
     if (kind == 2 && g.dim != 3) break;
     for (int c : caps) {
       if (c > B || (kind == 2 && c > 4) || (zn == 4 && c > 2)) break;
-      cur = best;
-      cur.qpb_a = c;
-      cur.kind_a = kind;
-      cur.zn_a = zn;
-      set_stencil_tiles(cur);
-      const float t1 = timed([&] {
-        if (y32)
-          launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_, p0.as<double>(),
-                               p1.as<double>(), q.beta, q.active, part_m.as<double>(), st);
-        else
-          launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_,
-                                p0.as<double>(), p1.as<double>(), q.beta, q.active,
-                                part_m.as<double>(), st);
-      });
-      if (t1 < ta) { ta = t1; best.qpb_a = c; best.kind_a = kind; best.zn_a = zn; }
-      // marching pass B with one and (where they fit) two LDS plane buffers
-      const int nbs = kind == 2 && pass_b_two_buffers(g, B, c, zn ? zn : 2) ? 2 : 1;
+      // the marching passes with one and (where they fit) two LDS plane buffers
+      const int nbs = kind == 2 && zmarch_two_buffers(g, B, c, zn ? zn : 2) ? 2 : 1;
+      for (int nb = 1; nb <= nbs; ++nb) {
+        cur = best;
+        cur.qpb_a = c;
+        cur.kind_a = kind;
+        cur.zn_a = zn;
+        cur.nb_a = nb;
+        set_stencil_tiles(cur);
+        const float t1 = timed([&] {
+          if (y32)
+            launch_pass_a<float>(g, L_, B, coef.as<double>(), y.as<float>(), L_,
+                                 p0.as<double>(), p1.as<double>(), q.beta, q.active,
+                                 part_m.as<double>(), st);
+          else
+            launch_pass_a<double>(g, L_, B, coef.as<double>(), y.as<double>(), L_,
+                                  p0.as<double>(), p1.as<double>(), q.beta, q.active,
+                                  part_m.as<double>(), st);
+        });
+        if (t1 < ta) {
+          ta = t1;
+          best.qpb_a = c;
+          best.kind_a = kind;
+          best.zn_a = zn;
+          best.nb_a = nb;
+        }
+      }
       for (int nb = 1; nb <= nbs; ++nb) {
         cur = best;
         cur.qpb_b = c;

@@ -1707,10 +1707,11 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   const int tiles = zt.rt * zt.ct * zt.slabs;
   const int pstride = stencil_chunks_all(g.N);  // row stride of the partial sums
   const dim3 grid((unsigned)(tiles * groups));
-  // pass B stages two plane buffers (one barrier per plane) when they fit in 64 KB, unless
-  // the tiles ask for one; pass A keeps one, whose variants need fewer registers (more
-  // blocks per CU)
-  const int nbuf = MODE == 1 && t_tiles.nb_b != 1 && z_lds(g, zt, qpb, 2) <= 65536 ? 2 : 1;
+  // two plane buffers (one barrier per plane) where they fit in 64 KB: pass B unless the
+  // tiles ask for one, pass A when they ask for two (its variants with one buffer need
+  // fewer registers)
+  const bool two = MODE == 1 ? t_tiles.nb_b != 1 : t_tiles.nb_a == 2;
+  const int nbuf = two && z_lds(g, zt, qpb, 2) <= 65536 ? 2 : 1;
   const size_t lds = z_lds(g, zt, qpb, nbuf);
   auto go = [&](auto Q, auto Z) {
     auto run = [&](auto X, auto NBc) {
@@ -1720,13 +1721,12 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
     };
     using N1 = std::integral_constant<int, 1>;
     using N2 = std::integral_constant<int, 2>;
+    auto by_nb = [&](auto X) { return nbuf == 2 ? run(X, N2{}) : run(X, N1{}); };
     if constexpr (MODE == 1) {
-      auto by_nb = [&](auto X) { return nbuf == 2 ? run(X, N2{}) : run(X, N1{}); };
       if (xd == 1) return by_nb(std::integral_constant<int, 1>{});
       if (xd == 2) return by_nb(std::integral_constant<int, 2>{});
-      return by_nb(std::integral_constant<int, 0>{});
     }
-    run(std::integral_constant<int, 0>{}, N1{});
+    by_nb(std::integral_constant<int, 0>{});
   };
   using Z2 = std::integral_constant<int, kZNodes>;
   using Z4 = std::integral_constant<int, 4>;
@@ -1744,7 +1744,7 @@ static int launch_zmarch(const StencilGeom& g, int qpb, int64_t ld, int B, const
   return tiles;
 }
 
-bool pass_b_two_buffers(const StencilGeom& g, int B, int qpb, int zn) {
+bool zmarch_two_buffers(const StencilGeom& g, int B, int qpb, int zn) {
   qpb = std::min(qpb, 4);
   if (zn != 4 || qpb > 2) zn = kZNodes;
   ZTile zt;

@@ -26,7 +26,7 @@ void Tuner::put(const std::string& key, const TuneConfig& c) {
 
 // File format: one JSON object,
 // {"key": [qpb_a, qpb_b, qpb_gs, proj_target, kind_a, kind_b, kind_gs, kind_pro, zn_a,
-// zn_b, np_gs, nb_b], ...} (the last eight optional)
+// zn_b, np_gs, nb_b, nb_a], ...} (the last nine optional)
 void Tuner::load() {
   if (loaded) return;
   loaded = true;
@@ -49,10 +49,11 @@ void Tuner::load() {
     TuneConfig c;
     const int got =
         std::sscanf(t.c_str() + l + 1,
-                    "%d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d", &c.qpb_a,
-                    &c.qpb_b, &c.qpb_gs, &c.proj_target, &c.kind_a, &c.kind_b, &c.kind_gs,
-                    &c.kind_pro, &c.zn_a, &c.zn_b, &c.np_gs, &c.nb_b);
-    if (got == 4 || got == 6 || got == 7 || got == 8 || got == 10 || got == 11 || got == 12)
+                    "%d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d , %d",
+                    &c.qpb_a, &c.qpb_b, &c.qpb_gs, &c.proj_target, &c.kind_a, &c.kind_b,
+                    &c.kind_gs, &c.kind_pro, &c.zn_a, &c.zn_b, &c.np_gs, &c.nb_b, &c.nb_a);
+    if (got == 4 || got == 6 || got == 7 || got == 8 || got == 10 || got == 11 || got == 12 ||
+        got == 13)
       put(t.substr(a + 1, b - a - 1), c);
     i = r + 1;
   }
@@ -68,7 +69,7 @@ void Tuner::save() const {
     f << "  \"" << table[i].first << "\": [" << c.qpb_a << ", " << c.qpb_b << ", " << c.qpb_gs
       << ", " << c.proj_target << ", " << c.kind_a << ", " << c.kind_b << ", " << c.kind_gs
       << ", " << c.kind_pro << ", " << c.zn_a << ", " << c.zn_b << ", " << c.np_gs << ", "
-      << c.nb_b << "]"
+      << c.nb_b << ", " << c.nb_a << "]"
       << (i + 1 < table.size() ? "," : "") << "\n";
   }
   f << "}\n";
